@@ -1,0 +1,264 @@
+"""Plain FP64 CPU oracle for the CCAKE 2.0 SPH stage (arXiv 2511.22852).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` are the only permitted callers.  The
+product path (``paper_2511_22852_amd``) never imports this package and shares
+no code with it.
+
+The arithmetic lives in ``ccake_oracle.c`` (compiled with gcc, no FMA
+contraction, OpenMP over particles); this module only marshals numpy arrays.
+Units: hbar = c = 1, fm.  Table axes and zeta/s parameters are accepted in GeV
+and converted with hbar*c = 0.1973269804 GeV fm.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ccake_oracle.c")
+LIB = os.path.join(HERE, "libccake_oracle.so")
+HBARC = 0.1973269804
+
+NVAR = 17
+NAUX = 19
+(V_X1, V_X2, V_X3, V_U1, V_U2, V_U3, V_S, V_NB, V_NS, V_NQ, V_B,
+ V_P11, V_P12, V_P13, V_P22, V_P23, V_P33) = range(NVAR)
+(A_SIGSTAR, A_S, A_NB, A_NS, A_NQ, A_T, A_MUB, A_MUS, A_MUQ, A_P, A_E,
+ A_CS2, A_INTABLE, A_GAMMA, A_THETA, A_NNB, A_F1, A_F2, A_F3) = range(NAUX)
+
+EOS_CONFORMAL, EOS_TABLE, EOS_GAS, EOS_MODCONF = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (C11, -O2, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC",
+            "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("hyperbolic", ctypes.c_int32),
+        ("viscous", ctypes.c_int32), ("ncharge", ctypes.c_int32),
+        ("use_cells", ctypes.c_int32), ("nthreads", ctypes.c_int32),
+        ("density_mode", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("h", ctypes.c_double), ("eta_over_s", ctypes.c_double),
+        ("zeta_peak", ctypes.c_double), ("zeta_Tpeak", ctypes.c_double),
+        ("zeta_width", ctypes.c_double), ("taupi_coeff", ctypes.c_double),
+        ("tauPi_ratio", ctypes.c_double), ("c_PiPi", ctypes.c_double),
+        ("c_Pipi", ctypes.c_double), ("c_pipi", ctypes.c_double),
+        ("c_piPi", ctypes.c_double),
+    ]
+
+
+class EosC(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("nT", ctypes.c_int32), ("nB", ctypes.c_int32),
+        ("nS", ctypes.c_int32), ("nQ", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+        ("fstar", ctypes.c_double), ("tol", ctypes.c_double),
+        ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
+        ("cols", ctypes.POINTER(ctypes.c_double)),
+        ("A0", ctypes.c_double), ("muq0", ctypes.c_double * 3), ("cq", ctypes.c_double * 3),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.orc_kernel_w.restype = ctypes.c_double
+        L.orc_kernel_w.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_kernel_dw_over_r.restype = ctypes.c_double
+        L.orc_kernel_dw_over_r.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_pairs.restype = ctypes.c_int64
+        L.orc_pairs.argtypes = [ctypes.POINTER(Params), ctypes.c_int64, dp, ctypes.c_int64, ip, ip]
+        L.orc_eos_invert.restype = ctypes.c_int
+        L.orc_eos_invert.argtypes = [ctypes.POINTER(EosC), ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp, ip]
+        L.orc_eos_eval.restype = None
+        L.orc_eos_eval.argtypes = [ctypes.POINTER(EosC), ctypes.c_int, ctypes.c_int64, dp, dp]
+        L.orc_rhs.restype = ctypes.c_int
+        L.orc_rhs.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
+                              ctypes.c_int64, dp, dp, dp]
+        L.orc_heun_step.restype = ctypes.c_int
+        L.orc_heun_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int64, dp, dp]
+        L.orc_init.restype = ctypes.c_int
+        L.orc_init.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
+                               ctypes.c_int64, dp, dp, ctypes.c_int, dp, dp]
+        L.orc_totals.restype = None
+        L.orc_totals.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
+                                 ctypes.c_int64, dp, dp]
+        assert L.orc_nvar() == NVAR and L.orc_naux() == NAUX
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def params(dim=2, hyperbolic=True, viscous=False, ncharge=0, h=0.3, eta_over_s=0.0,
+           zeta_peak=0.0, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, taupi_coeff=5.0,
+           tauPi_ratio=1.0, c_PiPi=1.0, c_Pipi=0.0, c_pipi=4.0 / 3.0, c_piPi=0.0,
+           use_cells=None, nthreads=0, density_mode=0) -> Params:
+    p = Params()
+    p.dim, p.hyperbolic, p.viscous, p.ncharge = dim, int(hyperbolic), int(viscous), ncharge
+    p.use_cells = 0 if use_cells is None else int(use_cells)
+    p.nthreads = nthreads
+    p.density_mode = density_mode
+    p.h, p.eta_over_s = h, eta_over_s
+    p.zeta_peak = zeta_peak
+    p.zeta_Tpeak = zeta_Tpeak_GeV / HBARC
+    p.zeta_width = zeta_width_GeV / HBARC
+    p.taupi_coeff, p.tauPi_ratio = taupi_coeff, tauPi_ratio
+    p.c_PiPi, p.c_Pipi, p.c_pipi, p.c_piPi = c_PiPi, c_Pipi, c_pipi, c_piPi
+    return p
+
+
+@dataclass
+class Eos:
+    c: EosC
+    keep: object = None  # keeps the table buffer alive
+
+
+def eos_conformal(fstar: float = 11.0) -> Eos:
+    e = EosC()
+    e.kind, e.fstar, e.tol, e.max_iter = EOS_CONFORMAL, fstar, 1e-13, 60
+    return Eos(e)
+
+
+def eos_gas() -> Eos:
+    e = EosC()
+    e.kind, e.tol, e.max_iter = EOS_GAS, 1e-13, 60
+    return Eos(e)
+
+
+def eos_modconf(A0, muq0, cq) -> Eos:
+    e = EosC()
+    e.kind, e.tol, e.max_iter = EOS_MODCONF, 1e-13, 60
+    e.A0 = A0
+    for q in range(3):
+        e.muq0[q] = muq0[q]
+        e.cq[q] = cq[q]
+    return Eos(e)
+
+
+def eos_table(cols: np.ndarray, lo_fm, hi_fm, tol=1e-13, max_iter=60) -> Eos:
+    """cols: (7, nT, nB, nS, nQ) dimensionless columns; axes in fm^-1."""
+    cols = _f64(cols)
+    assert cols.ndim == 5 and cols.shape[0] == 7
+    e = EosC()
+    e.kind = EOS_TABLE
+    e.nT, e.nB, e.nS, e.nQ = cols.shape[1:]
+    e.tol, e.max_iter = tol, max_iter
+    for k in range(4):
+        e.lo[k] = lo_fm[k]
+        e.hi[k] = hi_fm[k]
+    e.cols = _dp(cols)
+    return Eos(e, cols)
+
+
+def kernel_w(dim, h, r):
+    return lib().orc_kernel_w(dim, h, r)
+
+
+def kernel_dw_over_r(dim, h, r):
+    return lib().orc_kernel_dw_over_r(dim, h, r)
+
+
+def pairs(prm: Params, y: np.ndarray):
+    y = _f64(y)
+    n = y.shape[1]
+    tot = lib().orc_pairs(ctypes.byref(prm), n, _dp(y), 0, None, None)
+    a = np.empty(max(tot, 1), np.int32)
+    b = np.empty(max(tot, 1), np.int32)
+    lib().orc_pairs(ctypes.byref(prm), n, _dp(y), tot, _ip(a), _ip(b))
+    return a[:tot], b[:tot]
+
+
+def eos_invert(eos: Eos, mode: int, ncharge: int, x4: np.ndarray):
+    x4 = _f64(x4)
+    n = x4.shape[1]
+    out = np.empty((4, n))
+    it = np.empty(n, np.int32)
+    bad = lib().orc_eos_invert(ctypes.byref(eos.c), mode, ncharge, n, _dp(x4), _dp(out), _ip(it))
+    return out, it, bad
+
+
+def eos_eval(eos: Eos, use_table: bool, x4: np.ndarray):
+    """Columns p, e, s, nB, nS, nQ, cs2, kappa at points (T, muB, muS, muQ)."""
+    x4 = _f64(x4)
+    n = x4.shape[1]
+    out = np.empty((8, n))
+    lib().orc_eos_eval(ctypes.byref(eos.c), int(use_table), n, _dp(x4), _dp(out))
+    return out
+
+
+def init(prm: Params, eos: Eos, t0: float, xi, u, dens_kind: int, dens):
+    xi, u, dens = _f64(xi), _f64(u), _f64(dens)
+    n = xi.shape[1]
+    y = np.zeros((NVAR, n))
+    bad = lib().orc_init(ctypes.byref(prm), ctypes.byref(eos.c), t0, n, _dp(xi), _dp(u),
+                         dens_kind, _dp(dens), _dp(y))
+    if bad:
+        raise RuntimeError(f"oracle init: {bad} EoS inversions did not converge")
+    return y
+
+
+def rhs(prm: Params, eos: Eos, t: float, y):
+    y = _f64(y)
+    n = y.shape[1]
+    dy = np.zeros((NVAR, n))
+    aux = np.zeros((NAUX, n))
+    bad = lib().orc_rhs(ctypes.byref(prm), ctypes.byref(eos.c), t, n, _dp(y), _dp(dy), _dp(aux))
+    return dy, aux, bad
+
+
+def heun_step(prm: Params, eos: Eos, t: float, dt: float, y):
+    y = _f64(y).copy()
+    n = y.shape[1]
+    aux = np.zeros((NAUX, n))
+    bad = lib().orc_heun_step(ctypes.byref(prm), ctypes.byref(eos.c), t, dt, n, _dp(y), _dp(aux))
+    return y, aux, bad
+
+
+def totals(prm: Params, eos: Eos, t: float, y):
+    y = _f64(y)
+    out = np.zeros(8)
+    lib().orc_totals(ctypes.byref(prm), ctypes.byref(eos.c), t, y.shape[1], _dp(y), _dp(out))
+    return out
+
+
+def evolve(prm: Params, eos: Eos, t0: float, dt: float, nsteps: int, y):
+    """nsteps Heun steps from (t0, y); returns (t, y, aux of the last stage)."""
+    t = t0
+    aux = None
+    for _ in range(nsteps):
+        y, aux, bad = heun_step(prm, eos, t, dt, y)
+        if bad:
+            raise RuntimeError(f"oracle: {bad} EoS inversions did not converge at t={t}")
+        t += dt
+    return t, y, aux
