@@ -1,0 +1,263 @@
+/*
+ * ccake.h -- C ABI of the MI355X (gfx950) implementation of one Runge-Kutta
+ * stage of the relativistic viscous SPH of CCAKE 2.0 (arXiv 2511.22852).
+ *
+ * The calls follow the paper's problem statement: an equation of state
+ * ("Equation of state", "EoS inverter"), a particle system carrying the
+ * dynamical variables {r, u, s/sigma, Pi/sigma, pi/sigma, n_q/sigma}
+ * ("Equations of motion", SPH subsection), the conservation laws with
+ * minimal Israel-Stewart relaxation (eq. conservation_source, eq. min_bul_rel,
+ * eq. min_she_rel) and a time step.
+ *
+ * Conventions
+ *   - Every call returns a ccake_status; 0 is success.  On failure the handle
+ *     keeps a message readable with ccake_last_error(handle).
+ *   - Units: hbar = c = 1; lengths and times in fm; T, mu in fm^-1; densities
+ *     in fm^-3; energy density and pressure in fm^-4.
+ *   - Arrays are FP64 structure-of-arrays, row-major [row][n], in the caller's
+ *     particle order (index 0..n-1) unless stated otherwise.
+ *   - mem = CCAKE_HOST: host pointers (copied synchronously);
+ *     mem = CCAKE_DEVICE: device pointers valid on the library's device; the
+ *     copy is enqueued on the handle's stream and the pointer must stay valid
+ *     until the stream reaches it.
+ *   - The state layout (17 rows, CCAKE_ROW_*) is the exchange format of
+ *     ccake_set_state / ccake_get_state (checkpoint / restore).
+ *   - Handles are not thread-safe; one simulation per stream.
+ */
+#ifndef CCAKE_H
+#define CCAKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ccake_status;
+enum {
+  CCAKE_OK = 0,
+  CCAKE_E_ARG = 1,         /* invalid argument (sizes, non-finite or negative input) */
+  CCAKE_E_HIP = 2,         /* HIP runtime error (message in ccake_last_error) */
+  CCAKE_E_NONFINITE = 3,   /* a particle update produced a non-finite value (sticky) */
+  CCAKE_E_EOS_NOCONV = 4,  /* an EoS inversion did not converge, backup included (sticky) */
+  CCAKE_E_CAPACITY = 5,    /* workspace, cell grid or server capacity exceeded */
+  CCAKE_E_STATE = 6,       /* call out of sequence (e.g. step before init) */
+  CCAKE_E_NOMEM = 7        /* device allocation failed */
+};
+
+enum { CCAKE_HOST = 0, CCAKE_DEVICE = 1 };
+enum { CCAKE_CARTESIAN = 0, CCAKE_HYPERBOLIC = 1 };
+enum { CCAKE_FP64 = 0, CCAKE_MIXED = 1 };
+/* density_mode: how the rest-frame s and n_q of a particle are formed
+ *   SMOOTHED: s_a = sum_b S_b W_ab / (gamma_a sqrt(-g))  (SPH interpolation of
+ *             the lab-frame density, "SPH interpretation of a fluid element")
+ *   SPECIFIC: s_a = S_a sigma_a with sigma_a = sigma*_a / (gamma_a sqrt(-g))
+ *             (the particle's own s/sigma, "Equations of motion") */
+enum { CCAKE_DENS_SMOOTHED = 0, CCAKE_DENS_SPECIFIC = 1 };
+/* dens_kind of ccake_init_particles */
+enum { CCAKE_INIT_S = 0, CCAKE_INIT_E = 1 };
+
+/* rows of the state exchange format */
+enum {
+  CCAKE_ROW_X1 = 0, CCAKE_ROW_X2, CCAKE_ROW_X3, CCAKE_ROW_U1, CCAKE_ROW_U2, CCAKE_ROW_U3,
+  CCAKE_ROW_S, CCAKE_ROW_NB, CCAKE_ROW_NS, CCAKE_ROW_NQ, CCAKE_ROW_B,
+  CCAKE_ROW_P11, CCAKE_ROW_P12, CCAKE_ROW_P13, CCAKE_ROW_P22, CCAKE_ROW_P23, CCAKE_ROW_P33,
+  CCAKE_NROW
+};
+
+/* per-particle diagnostics of one right-hand-side evaluation (ccake_rhs, ccake_read) */
+enum {
+  CCAKE_AUX_SIGSTAR = 0, CCAKE_AUX_S, CCAKE_AUX_NB, CCAKE_AUX_NS, CCAKE_AUX_NQ, CCAKE_AUX_T,
+  CCAKE_AUX_MUB, CCAKE_AUX_MUS, CCAKE_AUX_MUQ, CCAKE_AUX_P, CCAKE_AUX_E, CCAKE_AUX_CS2,
+  CCAKE_AUX_INTABLE, CCAKE_AUX_GAMMA, CCAKE_AUX_THETA, CCAKE_AUX_NNB, CCAKE_AUX_F1,
+  CCAKE_AUX_F2, CCAKE_AUX_F3, CCAKE_NAUX
+};
+
+typedef struct ccake_eos ccake_eos;
+typedef struct ccake_sim ccake_sim;
+typedef struct ccake_server ccake_server;
+
+/* Run parameters ("Equations of motion", "Transport coefficients", kernel h).
+ *   dim            spatial dimensions carried by particles: 2 or 3
+ *   coords         CCAKE_CARTESIAN (t,x,y[,z]) or CCAKE_HYPERBOLIC (tau,x,y[,eta])
+ *   viscous        0 ideal; 1 minimal Israel-Stewart shear + bulk
+ *   precision      CCAKE_FP64, or CCAKE_MIXED (pair sums in FP32 with Kahan
+ *                  compensation; state, Newton, update and totals in FP64)
+ *   ncharge        0 or 3 (B, S, Q)
+ *   density_mode   CCAKE_DENS_SMOOTHED or CCAKE_DENS_SPECIFIC
+ *   h              smoothing length (fm)
+ *   eta_over_s     constant eta/s (eta = eta_over_s * s)
+ *   zeta_*         zeta/s = zeta_peak exp(-(T - zeta_Tpeak)^2 / (2 zeta_width^2)), T in fm^-1
+ *   taupi_coeff    tau_pi = taupi_coeff * eta / (e + p)
+ *   tauPi_ratio    tau_Pi = tauPi_ratio * tau_pi
+ *   c_PiPi,c_Pipi  first-order DNMR-type bulk couplings / tau_Pi (minimal IS: 1, 0)
+ *   c_pipi,c_piPi  first-order DNMR-type shear couplings / tau_pi (minimal IS: 4/3, 0)
+ *   skin           cell edge = 2h + skin; must exceed 2 dt max(1, 1/x0)          */
+typedef struct ccake_config {
+  int32_t dim, coords, viscous, precision, ncharge, density_mode;
+  double h;
+  double eta_over_s;
+  double zeta_peak, zeta_Tpeak, zeta_width;
+  double taupi_coeff, tauPi_ratio;
+  double c_PiPi, c_Pipi, c_pipi, c_piPi;
+  double skin;
+} ccake_config;
+
+/* Per-event counters of the last evaluation (ccake_totals). */
+typedef struct ccake_counters {
+  uint32_t nonfinite;      /* sticky: non-finite particle updates */
+  uint32_t noconv;         /* sticky: EoS inversions that failed */
+  uint32_t backup;         /* last stage: inversions served by the backup EoS */
+  uint32_t newton_iters;   /* last stage: total Newton iterations */
+  int32_t first_bad;       /* lowest particle index with a non-finite update, or -1 */
+  uint32_t capacity_err;   /* sticky: cell-grid capacity problems */
+} ccake_counters;
+
+/* ---------------------------------------------------------------- EoS ---- */
+
+/* Conformal EoS e = fstar T^4, p = e/3 (charges ignored); inversion in closed
+ * form.  Paper: conformal EoS of the Gubser checks ("Code validation").      */
+ccake_status ccake_eos_create_conformal(ccake_eos** out, double fstar);
+
+/* Analytic massless gas of u, d, s quarks and gluons,
+ * p = (19 pi^2/36) T^4 + sum_f [mu_f^2 T^2/2 + mu_f^4/(4 pi^2)];
+ * inverted by damped Newton with the analytic Jacobian.                      */
+ccake_status ccake_eos_create_gas(ccake_eos** out, int32_t max_iter, double tol);
+
+/* Tabulated 4D EoS on a regular (T, muB, muS, muQ) grid ("Equation of state",
+ * online inverter of "EoS inverter") with the analytic gas as backup EoS.
+ *   n[4]        nodes per axis (>= 2 each)
+ *   lo[4],hi[4] axis ranges in fm^-1
+ *   cols        host array [7][n0][n1][n2][n3]: p/T^4, s/T^3, nB/T^3,
+ *               nS/T^3, nQ/T^3, c_s^2, (dp/de)_n (dimensionless); copied to a
+ *               device table owned by the EoS (node-major, 64 B per node)
+ *   max_iter    Newton iterations per solve; tol: max scaled residual
+ * Inversion: the backup gas root is found first; when it lies inside the axes
+ * the table interpolant is solved from it and used if it converges inside.  */
+ccake_status ccake_eos_create_table(ccake_eos** out, const int32_t n[4], const double lo[4], const double hi[4],
+                                    const double* cols, int32_t max_iter, double tol);
+
+ccake_status ccake_eos_destroy(ccake_eos* eos);
+
+/* Batch inversion (s or e, nB, nS, nQ) -> (T, muB, muS, muQ) on the device.
+ *   mode     0: entropy density given; 1: energy density given
+ *   in, out  device arrays [4][n]; in_table (optional, device int32[n]) gets 1
+ *            when the table answered, 0 when the backup did
+ *   stream   hipStream_t (NULL = default stream); asynchronous
+ * Returns CCAKE_E_EOS_NOCONV after synchronising when some solve failed.     */
+ccake_status ccake_eos_invert(ccake_eos* eos, int32_t mode, int32_t ncharge, int64_t n, const double* in,
+                              double* out, int32_t* in_table, void* stream);
+
+/* --------------------------------------------------------- simulation ---- */
+
+/* Device bytes a simulation of n particles needs; the caller allocates them
+ * (e.g. a torch uint8 tensor) and passes the pointer to ccake_create.        */
+ccake_status ccake_workspace_bytes(const ccake_config* cfg, int64_t n, size_t* bytes);
+
+/* Creates a simulation of n particles in a caller-owned device workspace of at
+ * least ccake_workspace_bytes bytes (256-byte aligned).  The workspace and the
+ * EoS must outlive the simulation.  stream: hipStream_t (NULL = default).    */
+ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, const ccake_eos* eos, int64_t n,
+                          void* workspace, size_t bytes, void* stream);
+
+/* Initial condition at x0 = t0 ("SPH interpretation of a fluid element",
+ * m_b = 1): positions xi [dim][n], flow u^i [dim][n] (contravariant), and
+ * dens [4][n] = (s or e, nB, nS, nQ) in the rest frame (dens_kind
+ * CCAKE_INIT_S or CCAKE_INIT_E).  Computes sigma*_a = sum_b W_ab and sets
+ * S_a = s_a gamma_a sqrt(-g)/sigma*_a, N_a likewise, Pi = pi = 0.
+ * CCAKE_E_ARG on non-finite input or negative s / e.  Synchronises.          */
+ccake_status ccake_init_particles(ccake_sim* sim, double t0, const double* xi, const double* u, int32_t dens_kind,
+                                  const double* dens, int32_t mem);
+
+/* Raw state upload / download in the 17-row exchange format (checkpoint and
+ * restore).  get_state synchronises.                                         */
+ccake_status ccake_set_state(ccake_sim* sim, double t, const double* y, int32_t mem);
+ccake_status ccake_get_state(ccake_sim* sim, double* y, int32_t mem);
+ccake_status ccake_time(const ccake_sim* sim, double* t);
+
+/* nsteps Heun (second-order Runge-Kutta) steps of size dt; each stage bins the
+ * particles, forms the density sums, inverts the EoS, forms the gradient sums
+ * and solves the local equations of motion.  Asynchronous on the stream;
+ * returns a sticky error (CCAKE_E_NONFINITE / CCAKE_E_EOS_NOCONV /
+ * CCAKE_E_CAPACITY) already observed from an earlier call.                   */
+ccake_status ccake_step(ccake_sim* sim, double dt, int32_t nsteps);
+
+/* Synchronises and reports the sticky per-particle error state.             */
+ccake_status ccake_check(ccake_sim* sim);
+
+/* One evaluation of the right-hand side at the current state, without
+ * stepping: rates f [17][n] and diagnostics aux [CCAKE_NAUX][n] (either may be
+ * NULL), caller order.  Synchronises.                                        */
+ccake_status ccake_rhs(ccake_sim* sim, double* f, double* aux, int32_t mem);
+
+/* One diagnostic field (CCAKE_AUX_*) at the current state, caller order.     */
+ccake_status ccake_read(ccake_sim* sim, int32_t field, double* out, int32_t mem);
+
+/* Totals at the current state: out[8] = (S, N_B, N_S, N_Q, E, M_1, M_2, M_3)
+ * with E = sum sqrt(-g) T^00/sigma* and M_i = sum sqrt(-g) G_ii T^0i/sigma*
+ * (conserved energy and momentum in Cartesian coordinates; "Exact
+ * conservation").  cnt (optional) receives the counters.  Synchronises.     */
+ccake_status ccake_totals(ccake_sim* sim, double* out, ccake_counters* cnt);
+
+/* Test support: the neighbour relation {(a, b) : |x_a - x_b|^2 < (2h)^2}
+ * (self included) at the current positions, as caller indices, in no
+ * particular order.  a, b: device int32 arrays of capacity cap; npairs gets
+ * the total (pairs beyond cap are counted but not written).  Synchronises.  */
+ccake_status ccake_debug_pairs(ccake_sim* sim, int64_t cap, int32_t* a, int32_t* b, int64_t* npairs);
+
+ccake_status ccake_destroy(ccake_sim* sim);
+
+/* ------------------------------------------------------------ serving ---- */
+
+/* A persistent serving loop: events of uneven particle count are submitted
+ * as they arrive, admitted when their device footprint fits the budget and a
+ * slot is free, advanced together by batched launches (one Heun step over all
+ * resident events per iteration), and returned when they reach t_end.  A
+ * host thread owns the loop; the device work runs on the server's stream.
+ *   budget_bytes     device bytes the resident events may occupy
+ *   max_particles    resident particle capacity; max_events: slot capacity
+ *   dt               step of every event                                     */
+typedef struct ccake_event_desc {
+  int64_t n;              /* particles */
+  double t0, t_end;       /* start and end of the evolution */
+  const double* xi;       /* host [dim][n] */
+  const double* u;        /* host [dim][n] */
+  int32_t dens_kind;      /* CCAKE_INIT_S or CCAKE_INIT_E */
+  const double* dens;     /* host [4][n]; copied at submission */
+  int64_t user_tag;
+} ccake_event_desc;
+
+typedef struct ccake_event_result {
+  int64_t ticket, user_tag, n;
+  int32_t status;         /* ccake_status of the event */
+  int32_t steps;
+  double t_submit, t_admit, t_finish;  /* seconds on the server's clock */
+  double* state;          /* host [17][n], owned by the server until ccake_server_release */
+  double totals[8];
+} ccake_event_result;
+
+ccake_status ccake_server_create(ccake_server** out, const ccake_config* cfg, const ccake_eos* eos,
+                                 size_t budget_bytes, int64_t max_particles, int32_t max_events, double dt,
+                                 void* stream);
+/* Copies the event's arrays and queues it; returns its ticket.  Rejects with
+ * CCAKE_E_CAPACITY an event that can never fit the budget or capacity.      */
+ccake_status ccake_server_submit(ccake_server* srv, const ccake_event_desc* ev, int64_t* ticket);
+/* Moves up to cap finished events into res; *count gets how many.           */
+ccake_status ccake_server_poll(ccake_server* srv, ccake_event_result* res, int32_t cap, int32_t* count);
+/* Blocks until every submitted event has finished.                           */
+ccake_status ccake_server_drain(ccake_server* srv);
+ccake_status ccake_server_release(ccake_server* srv, ccake_event_result* res);
+/* Server clock (seconds since creation) and counters. */
+ccake_status ccake_server_stats(ccake_server* srv, double* now, int64_t* steps, int64_t* particle_steps,
+                                int32_t* resident);
+ccake_status ccake_server_destroy(ccake_server* srv);
+
+/* Message of the last failure on a handle (eos, sim or server); never NULL. */
+const char* ccake_last_error(const void* handle);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCAKE_H */

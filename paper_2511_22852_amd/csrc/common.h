@@ -1,0 +1,109 @@
+// Shared device/host definitions of the CCAKE SPH library (gfx950).
+//
+// Layout conventions
+//   * particle state: 17 rows of FP64, row-major [row][capacity], particles of
+//     one event contiguous and, after binning, sorted by (cell, id);
+//   * rows: x^1..x^3, u^1..u^3, S = s/sigma, N_B, N_S, N_Q (= n_q/sigma),
+//     B = Pi/sigma, P^{ij} = pi^{ij}/sigma for ij = 11,12,13,22,23,33
+//     (the dynamical variables of the paper's SPH equations of motion);
+//   * the index 3 is eta (hyperbolic) or z (Cartesian); in 2+1D it is a
+//     symmetry direction (u^3 = 0, no particle coordinate).
+#pragma once
+#include <stdint.h>
+
+namespace ccake {
+
+enum Row {
+  R_X1, R_X2, R_X3, R_U1, R_U2, R_U3, R_S, R_NB, R_NS, R_NQ, R_B,
+  R_P11, R_P12, R_P13, R_P22, R_P23, R_P33, NROW
+};
+
+// auxiliary per-particle outputs of a right-hand-side evaluation (debug/parity)
+enum Aux {
+  X_SIGSTAR, X_S, X_NB, X_NS, X_NQ, X_T, X_MUB, X_MUS, X_MUQ, X_P, X_E,
+  X_CS2, X_INTABLE, X_GAMMA, X_THETA, X_NNB, X_F1, X_F2, X_F3, NAUXROW
+};
+
+// per-particle thermodynamic record written by pass 1, read (own particle) by pass 2
+enum Th {
+  T_SIGSTAR, T_T, T_MUB, T_MUS, T_MUQ, T_P, T_E, T_CS2, T_KAP, T_PI,
+  T_ETA, T_ZETA, T_TAUPI, T_TAUPIB, T_S, T_NB, T_NS, T_NQ, T_NNB, NTH
+};
+
+// neighbour record written by pass 1, read for every neighbour by pass 2:
+// (p+Pi)/sigma*^2, A^{ji}/sigma*^2 (j,i spatial, row-major j*3+i), u^k, v^k
+enum Rec { Q_PP, Q_A11, Q_A12, Q_A13, Q_A21, Q_A22, Q_A23, Q_A31, Q_A32, Q_A33,
+           Q_U1, Q_U2, Q_U3, Q_V1, Q_V2, Q_V3, NREC };
+
+// warm-start record of the EoS inversion (carried with the particle)
+enum Warm { W_T, W_MUB, W_MUS, W_MUQ, NWARM };
+
+enum EosKind { EOS_CONFORMAL = 0, EOS_TABLE = 1, EOS_GAS = 2 };
+
+// table node: 8 doubles, the four Newton columns first (32-byte aligned)
+enum TabCol { TC_S, TC_NB, TC_NS, TC_NQ, TC_P, TC_CS2, TC_KAP, TC_PAD, TC_STRIDE };
+
+struct EosDev {
+  int32_t kind;
+  int32_t n[4];
+  int32_t max_iter;
+  double lo[4], hi[4], d[4];
+  double fstar;
+  double tol;
+  const double* tab;  // node-major [nT][nB][nS][nQ][8]
+};
+
+struct Params {
+  int32_t dim, hyperbolic, viscous, ncharge, density_mode, mixed;
+  double h;
+  double eta_over_s, zeta_peak, zeta_Tpeak, zeta_width;
+  double taupi_coeff, tauPi_ratio;
+  double c_PiPi, c_Pipi, c_pipi, c_piPi;
+  double cell_edge;   // >= 2h + skin
+};
+
+// one event of a batch (device-resident table)
+struct EventDev {
+  int64_t p_base;     // first particle slot
+  int64_t c_base;     // first cell slot
+  int32_t n;          // particles
+  int32_t c_cap;      // cell capacity
+  int32_t nc[3];      // grid cells per axis (this step)
+  int32_t active;
+  double lo[3];       // grid origin (this step)
+  double edge;        // cell edge (this step, >= cell_edge)
+  double t;           // current x^0
+  double dt;          // step size
+  uint32_t nonfinite; // count of non-finite state updates (sticky)
+  uint32_t noconv;    // count of EoS inversions that failed (sticky)
+  uint32_t backup;    // EoS inversions served by the analytic backup (last stage)
+  int32_t first_bad;  // lowest original id with a non-finite update, or -1
+  uint32_t capacity_err;
+  uint32_t newton_iters; // total Newton iterations (last stage)
+};
+
+// device arrays of a batch (pointers into one workspace)
+struct BatchDev {
+  double* Y0;        // home state [NROW][cap]
+  double* Ys;        // sorted step-start state [NROW][cap]
+  double* Y1;        // stage state [NROW][cap]
+  double* th;        // [NTH][cap]
+  double* rec;       // [NREC][cap] fp64 neighbour records
+  float* recf;       // [NREC][cap] fp32 neighbour records (mixed precision)
+  double* warm;      // home warm start [NWARM][cap]
+  double* warms;     // sorted warm start [NWARM][cap]
+  int32_t* id;       // home original ids
+  int32_t* ids;      // sorted original ids
+  int32_t* ev;       // event of each slot (-1 = empty)
+  int32_t* key;      // local cell key (home order)
+  int32_t* keys;     // local cell key (sorted order)
+  int32_t* perm;     // sorted slot -> home slot
+  int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
+  int32_t* cell_fill;   // [ccap] counts / cursors
+  EventDev* evt;     // [max_events]
+  int64_t cap;       // particle slots
+  int64_t ccap;      // cell slots
+  int32_t max_events;
+};
+
+}  // namespace ccake

@@ -1,0 +1,55 @@
+// Internal host-side definitions shared by runtime.cpp and server.cpp.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "ccake.h"
+#include "common.h"
+
+namespace ccake {
+
+enum : uint32_t { HANDLE_EOS = 0xCCA0E05u, HANDLE_SIM = 0xCCA051Au, HANDLE_SERVER = 0xCCA05E7u };
+
+struct Handle {
+  uint32_t magic = 0;
+  std::string err;
+};
+
+// byte offsets of the arrays of one batch inside its workspace
+struct Layout {
+  size_t Y0, Ys, Y1, th, rec, recf, warm, warms, aux, id, ids, ev, key, keys, perm, cs, cf, evt, scratch, total;
+};
+
+ccake_status fail(Handle* h, ccake_status code, const char* fmt, ...);
+bool validate_config(const ccake_config* c, std::string* why);
+Params to_params(const ccake_config& c);
+uint32_t live_rows(const Params& p);
+int64_t cell_capacity(const ccake_config& c, int64_t n);
+Layout make_layout(int64_t cap, int64_t ccap, int nev);
+BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int nev);
+
+}  // namespace ccake
+
+struct ccake_eos : ccake::Handle {
+  ccake::EosDev dev;
+  double* d_tab = nullptr;
+  uint32_t* d_bad = nullptr;
+};
+
+struct ccake_sim : ccake::Handle {
+  ccake_config cfg;
+  ccake::Params prm;
+  ccake::EosDev eos;
+  ccake::BatchDev b;
+  ccake::Layout L;
+  char* base = nullptr;
+  int64_t n = 0, ccap = 0;
+  hipStream_t stream = nullptr;
+  double t = 0.0, dt_host = 0.0;
+  bool initialised = false;
+  bool use_graph = false, graph_ready = false, pending = false;
+  hipGraphExec_t graph = nullptr;
+  hipEvent_t evt_done = nullptr;
+  ccake::EventDev* h_evt = nullptr;  // pinned copy of the event record
+};

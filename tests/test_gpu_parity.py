@@ -1,0 +1,329 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Bars: neighbour pair sets bit-exact; FP64 rates and one Heun step within a
+normwise relative 1e-12 per state row; FP64 trajectories within 1e-9; mixed
+precision (FP32-Kahan pair sums) within relative L2 1e-4 on e and n_B and
+conservation drift within 1e-6 of the FP64 drift.
+"""
+import numpy as np
+import pytest
+
+from paper_2511_22852_amd import inputs as I
+
+from cases import make, perturb, rel_inf, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2511_22852_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    return oracle_mod
+
+
+def sim_from_state(B, cfg, geos, y, t):
+    s = B.Sim(cfg, geos, y.shape[1])
+    s.set_state(t, y)
+    return s
+
+
+def orc_state(O, xi, dim):
+    y = np.zeros((O.NVAR, xi.shape[1]))
+    y[:dim] = xi
+    y[O.V_S] = 1.0
+    return y
+
+
+# ---------------------------------------------------------------- pairs ----
+PAIR_CASES = [
+    ("cloud2d", lambda: (I.random_cloud(3000, 2, 6.0, seed=1), 2, 0.15)),
+    ("cloud3d", lambda: (I.random_cloud(4000, 3, 3.0, seed=2), 3, 0.2)),
+    ("ties2d", lambda: (I.tie_lattice(60, 0.1, 2, 0.0, 0), 2, 0.15)),
+    ("ties3d", lambda: (I.tie_lattice(16, 0.1, 3, 0.0, 0), 3, 0.15)),
+    ("ties2d_jitter", lambda: (I.tie_lattice(50, 0.08, 2, 0.01, 5), 2, 0.24)),
+    ("single", lambda: (np.zeros((2, 1)), 2, 0.3)),
+]
+
+
+@pytest.mark.parametrize("name,build", PAIR_CASES, ids=[c[0] for c in PAIR_CASES])
+def test_pairs_bit_exact(B, O, name, build):
+    xi, dim, h = build()
+    prm, oe, cfg, ge = make(O, B, dim=dim, hyperbolic=False, h=h, eos="conformal")
+    y = orc_state(O, xi, dim)
+    sim = sim_from_state(B, cfg, ge, y, 1.0)
+    ga, gb = sim.pairs()
+    oa, ob = O.pairs(prm, y)
+    assert np.array_equal(ga, oa) and np.array_equal(gb, ob)
+
+
+# ------------------------------------------------------------- rates -------
+def lumpy_small(side=48, rhoB=0.05, rhoQ=0.02, seed=1):
+    return I.lumpy_2d_workload(n_side=side, seed=seed, n_hot=10, radius=1.0, rhoB=rhoB, rhoQ=rhoQ)
+
+
+def lumpy3d_small():
+    return I.lumpy_3d_workload(nxy=20, dxy=0.1, neta=12, deta=0.125, h=0.3, seed=3, n_hot=6, radius=0.6)
+
+
+RATE_CASES = {
+    "gubser2d_ideal": dict(wl=lambda: I.gubser_workload(), kw=dict(dim=2, eos="conformal", h=0.3), visc=False),
+    "gubser2d_cartesian": dict(wl=lambda: I.gubser_workload(hyperbolic=False),
+                               kw=dict(dim=2, hyperbolic=False, eos="conformal", h=0.3), visc=False),
+    "lumpy2d_visc_table_backup": dict(wl=lambda: lumpy_small(),
+                                      kw=dict(dim=2, viscous=True, ncharge=3, eos="table", h=0.24), visc=True),
+    "lumpy2d_visc_table_inside": dict(wl=lambda: lumpy_small(rhoB=0.005, rhoQ=0.002),
+                                      kw=dict(dim=2, viscous=True, ncharge=3, eos="table", h=0.24), visc=True),
+    "lumpy2d_visc_specific": dict(wl=lambda: lumpy_small(rhoB=0.005, rhoQ=0.002),
+                                  kw=dict(dim=2, viscous=True, ncharge=3, eos="table", h=0.24, density_mode=1),
+                                  visc=True),
+    "lumpy2d_visc_dnmr": dict(wl=lambda: lumpy_small(),
+                              kw=dict(dim=2, viscous=True, ncharge=3, eos="gas", h=0.24,
+                                      coeffs=dict(c_PiPi=0.7, c_Pipi=0.3, c_pipi=1.1, c_piPi=0.2)), visc=True),
+    "lumpy3d_visc_table": dict(wl=lumpy3d_small, kw=dict(dim=3, viscous=True, ncharge=3, eos="table", h=0.3),
+                               visc=True),
+    "lumpy3d_ideal_cartesian": dict(wl=lumpy3d_small, kw=dict(dim=3, hyperbolic=False, ncharge=3, eos="gas", h=0.3),
+                                    visc=False),
+}
+
+
+def prepared(B, O, name, precision=0):
+    c = RATE_CASES[name]
+    w = c["wl"]()
+    kw = dict(c["kw"])
+    prm, oe, cfg, ge = make(O, B, precision=precision, **kw)
+    t0 = w.t0 if kw.get("hyperbolic", True) else 1.0
+    y = O.init(prm, oe, t0, w.xi, w.u, w.dens_kind, w.dens)
+    y = perturb(O, y, kw["dim"], c["visc"], seed=7)
+    return prm, oe, cfg, ge, y, t0
+
+
+@pytest.mark.parametrize("name", list(RATE_CASES))
+def test_init_parity(B, O, name):
+    c = RATE_CASES[name]
+    w = c["wl"]()
+    prm, oe, cfg, ge = make(O, B, **c["kw"])
+    t0 = w.t0 if c["kw"].get("hyperbolic", True) else 1.0
+    y = O.init(prm, oe, t0, w.xi, w.u, w.dens_kind, w.dens)
+    sim = B.Sim(cfg, ge, w.n)
+    sim.init_particles(t0, w.xi, w.u, w.dens_kind, w.dens)
+    g = sim.get_state()
+    for r in (O.V_S, O.V_NB, O.V_NS, O.V_NQ):
+        assert rel_inf(g[r], y[r]) <= 1e-12, r
+    assert np.array_equal(g[: c["kw"]["dim"]], y[: c["kw"]["dim"]])
+
+
+@pytest.mark.parametrize("name", list(RATE_CASES))
+def test_rate_parity_fp64(B, O, name):
+    prm, oe, cfg, ge, y, t0 = prepared(B, O, name)
+    f_o, aux_o, bad = O.rhs(prm, oe, t0, y)
+    assert bad == 0
+    sim = sim_from_state(B, cfg, ge, y, t0)
+    f_g, aux_g = sim.rhs()
+    for r in range(O.NVAR):
+        if np.abs(f_o[r]).max() == 0.0:
+            assert np.abs(f_g[r]).max() == 0.0, r
+        else:
+            assert rel_inf(f_g[r], f_o[r]) <= 1e-12, (r, rel_inf(f_g[r], f_o[r]))
+    for a in (O.A_SIGSTAR, O.A_S, O.A_T, O.A_P, O.A_E, O.A_GAMMA, O.A_MUB, O.A_MUQ, O.A_THETA,
+              O.A_F1, O.A_F2):
+        assert rel_inf(aux_g[a], aux_o[a]) <= 1e-12, (a, rel_inf(aux_g[a], aux_o[a]))
+    assert np.array_equal(aux_g[O.A_INTABLE], aux_o[O.A_INTABLE])
+    assert np.array_equal(aux_g[O.A_NNB], aux_o[O.A_NNB])
+
+
+@pytest.mark.parametrize("name", ["gubser2d_ideal", "lumpy2d_visc_table_inside", "lumpy3d_visc_table"])
+def test_heun_step_parity_fp64(B, O, name):
+    prm, oe, cfg, ge, y, t0 = prepared(B, O, name)
+    dt = 0.005
+    yo, _, bad = O.heun_step(prm, oe, t0, dt, y)
+    assert bad == 0
+    sim = sim_from_state(B, cfg, ge, y, t0)
+    sim.step(dt, 1)
+    sim.check()
+    yg = sim.get_state()
+    for r in range(O.NVAR):
+        if np.abs(yo[r]).max() > 0:
+            assert rel_inf(yg[r], yo[r]) <= 1e-12, (r, rel_inf(yg[r], yo[r]))
+
+
+def test_gubser_trajectory_fp64(B, O):
+    """Gubser flow on the 51 x 51 lattice, tau 1 -> 2 fm in 200 Heun steps."""
+    w = I.gubser_workload()
+    prm, oe, cfg, ge = make(O, B, dim=2, eos="conformal", h=w.h)
+    y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    _, yo, aux_o = O.evolve(prm, oe, w.t0, w.dt, w.nsteps, y)
+    sim = B.Sim(cfg, ge, w.n)
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    sim.step(w.dt, w.nsteps)
+    sim.check()
+    yg = sim.get_state()
+    assert abs(sim.t - 2.0) < 1e-12
+    for r in (O.V_X1, O.V_X2, O.V_U1, O.V_U2, O.V_S):
+        assert rel_inf(yg[r], yo[r]) <= 1e-9, r
+    e_g = sim.read(B.AUX_E)
+    _, aux_final, _ = O.rhs(prm, oe, w.t0 + w.nsteps * w.dt, yo)
+    assert rel_inf(e_g, aux_final[O.A_E]) <= 1e-9
+
+
+def test_lumpy_viscous_trajectory_fp64(B, O):
+    w = lumpy_small(side=40)
+    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", h=w.h)
+    y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    n = 60
+    _, yo, _ = O.evolve(prm, oe, w.t0, w.dt, n, y)
+    sim = B.Sim(cfg, ge, w.n)
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    sim.step(w.dt, n)
+    sim.check()
+    yg = sim.get_state()
+    for r in (O.V_X1, O.V_U1, O.V_U2, O.V_S, O.V_B, O.V_P11, O.V_P12, O.V_P33):
+        assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))
+
+
+def test_full_size_lumpy_step(B, O):
+    """The 40,000-particle viscous BSQ event (200 x 200 at 0.08 fm, h = 0.24)
+    in the launch configuration of the benchmark: one FP64 Heun step from the
+    initial condition, every particle compared."""
+    w = I.lumpy_2d_workload()
+    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", table_size="full", h=w.h)
+    y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    yo, aux_o, bad = O.heun_step(prm, oe, w.t0, w.dt, y)
+    assert bad == 0
+    sim = B.Sim(cfg, ge, w.n)
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    sim.step(w.dt, 1)
+    sim.check()
+    yg = sim.get_state()
+    for r in range(O.NVAR):
+        if np.abs(yo[r]).max() > 0:
+            assert rel_inf(yg[r], yo[r]) <= 1e-12, (r, rel_inf(yg[r], yo[r]))
+
+
+# -------------------------------------------------------- mixed precision ---
+def test_mixed_precision_lumpy(B, O):
+    w = lumpy_small(side=60, rhoB=0.005, rhoQ=0.002)
+    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", h=w.h, precision=B.MIXED)
+    y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    n = 100
+    t, yo, _ = O.evolve(prm, oe, w.t0, w.dt, n, y)
+    _, aux_o, _ = O.rhs(prm, oe, t, yo)
+    sim = B.Sim(cfg, ge, w.n)
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    sim.step(w.dt, n)
+    sim.check()
+    f, aux_g = sim.rhs()
+    assert rel_l2(aux_g[O.A_E], aux_o[O.A_E]) <= 1e-4
+    assert rel_l2(aux_g[O.A_NB], aux_o[O.A_NB]) <= 1e-4
+
+
+def test_mixed_precision_conservation(B, O):
+    """Cartesian ideal run: N_q and S exactly constant in both precisions, and
+    the mixed-precision energy / momentum drift within 1e-6 of the FP64 one."""
+    w = lumpy_small(side=50, rhoB=0.02, rhoQ=0.01)
+    rng = np.random.default_rng(3)
+    u = 0.1 * rng.standard_normal(w.xi.shape)
+    tots = {}
+    for prec in (B.FP64, B.MIXED):
+        prm, oe, cfg, ge = make(O, B, dim=2, hyperbolic=False, ncharge=3, eos="gas", h=w.h, density_mode=1,
+                                precision=prec)
+        sim = B.Sim(cfg, ge, w.n)
+        sim.init_particles(1.0, w.xi, u, 0, w.dens / 20.0)
+        t0, _ = sim.totals()
+        y0 = sim.get_state()
+        sim.step(0.005, 100)
+        sim.check()
+        t1, cnt = sim.totals()
+        y1 = sim.get_state()
+        for r in (O.V_S, O.V_NB, O.V_NS, O.V_NQ):
+            assert np.array_equal(y1[r], y0[r])
+        tots[prec] = (t0, t1)
+    (a0, a1), (b0, b1) = tots[B.FP64], tots[B.MIXED]
+    assert abs((b1[4] - b0[4]) - (a1[4] - a0[4])) / a0[4] <= 1e-6
+    for k in (5, 6):
+        assert abs((b1[k] - b0[k]) - (a1[k] - a0[k])) / a0[4] <= 1e-6
+
+
+# ------------------------------------------------------------- misc ---------
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("kind", ["gas", "table"])
+def test_eos_invert_parity(B, O, mode, kind):
+    from cases import table
+    if kind == "gas":
+        oe, ge = O.eos_gas(), B.Eos.gas()
+    else:
+        cols, lo, hi = table("full")
+        oe, ge = O.eos_table(cols, lo, hi), B.Eos.table(cols, lo, hi)
+    rng = np.random.default_rng(4)
+    n = 5000
+    T = rng.uniform(0.06, 0.7, n) / I.HBARC
+    mu = rng.uniform(-0.5, 0.5, (3, n)) / I.HBARC
+    th = O.eos_eval(O.eos_gas(), False, np.vstack([T, mu]))
+    x = np.stack([th[2] if mode == 0 else th[1], th[3], th[4], th[5]])
+    out_o, it_o, bad = O.eos_invert(oe, mode, 3, x)
+    out_g, it_g = ge.invert(mode, 3, x)
+    assert bad == 0
+    assert np.array_equal(it_o, it_g)
+    assert rel_inf(out_g[0], out_o[0]) <= 1e-12
+    assert np.abs(out_g[1:] - out_o[1:]).max() <= 1e-12 * out_o[0].max()
+
+
+def test_totals_parity(B, O):
+    prm, oe, cfg, ge, y, t0 = prepared(B, O, "lumpy2d_visc_table_inside")
+    tot_o = O.totals(prm, oe, t0, y)
+    sim = sim_from_state(B, cfg, ge, y, t0)
+    tot_g, cnt = sim.totals()
+    assert np.allclose(tot_g[:4], tot_o[:4], rtol=1e-13, atol=0)
+    assert np.allclose(tot_g[4], tot_o[4], rtol=1e-12)
+    assert np.abs(tot_g[5:] - tot_o[5:]).max() <= 1e-12 * abs(tot_o[4])
+    assert cnt.nonfinite == 0 and cnt.noconv == 0
+
+
+def test_determinism_and_checkpoint(B, O):
+    prm, oe, cfg, ge, y, t0 = prepared(B, O, "lumpy2d_visc_table_backup")
+    runs = []
+    for split in (False, True):
+        sim = sim_from_state(B, cfg, ge, y, t0)
+        if split:
+            sim.step(0.005, 10)
+            ck = sim.get_state()
+            t = sim.t
+            sim.close()
+            sim = sim_from_state(B, cfg, ge, ck, t)
+            sim.step(0.005, 10)
+        else:
+            sim.step(0.005, 20)
+        sim.check()
+        runs.append(sim.get_state())
+    sim = sim_from_state(B, cfg, ge, y, t0)
+    sim.step(0.005, 20)
+    again = sim.get_state()
+    assert np.array_equal(runs[0], again)  # bitwise reproducible
+    assert rel_inf(runs[1], runs[0]) <= 1e-12  # restore from a checkpoint
+
+
+def test_rejects_bad_input(B, O):
+    prm, oe, cfg, ge = make(O, B, dim=2, eos="conformal")
+    xi = I.lattice((4, 4), 0.2, 0.0)
+    sim = B.Sim(cfg, ge, xi.shape[1])
+    dens = np.ones((4, xi.shape[1]))
+    dens[0, 3] = np.nan
+    with pytest.raises(B.CcakeError) as e:
+        sim.init_particles(1.0, xi, np.zeros_like(xi), 0, dens)
+    assert e.value.status == B.E_ARG
+    dens[0, 3] = -1.0
+    with pytest.raises(B.CcakeError):
+        sim.init_particles(1.0, xi, np.zeros_like(xi), 0, dens)
+    dens[0, 3] = 1.0
+    sim.init_particles(1.0, xi, np.zeros_like(xi), 0, dens)
+    with pytest.raises(B.CcakeError) as e:
+        sim.step(1.0, 1)  # dt larger than the binning skin allows
+    assert e.value.status == B.E_ARG
