@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPH Runge-Kutta stage on one MI355X.
+
+Workload: the 2+1D boost-invariant viscous BSQ event of 40,000 particles
+(200 x 200 lattice at 0.08 fm, h = 0.24 fm, 150 seeded Gaussian hot spots,
+rhoB = 0.05 s, rhoQ = 0.02 s, eta/s = 0.08, zeta/s Gaussian peak 0.02 at
+0.17 GeV, 64 x 32^3 synthetic massless-gas EoS table, Heun steps of
+dt = 0.005 fm/c from tau = 0.6 fm/c).  One step is one pass of the whole hot
+path: binning, both Heun stages (density sums, EoS inversion, gradient sums,
+local equations of motion, update).  Inputs are resident on the GPU before
+the timed region; the event is re-initialised (outside the timed region)
+after the warm-up.
+
+Reported: particle-steps/s for FP32-Kahan pair sums (value) and FP64; the
+roofline of the dominant kernel from HIP-event timings on the simulation's
+stream; the FP64 CPU oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # vector FP64: 256 CU x 128 flop/clk x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3     # vector FP32, published (packed) figure
+
+METRIC = "SPH particle-steps/s (FP64 vs FP32-Kahan) + p50/p99 event latency, 1 GPU"
+
+
+def algorithmic_model(dim, viscous, ncharge, mixed):
+    """Compulsory HBM bytes per particle and flops per accepted pair of the two
+    pass kernels (one launch = one Heun stage).  Neighbour reads are staged
+    on chip and are not counted; see the design doc for the derivation."""
+    nP = (6 if dim == 3 else 4) if viscous else 0
+    state = 2 * dim + 1 + ncharge + (1 + nP if viscous else 0)
+    rec = 1 + (dim * dim if viscous else 0) + 2 * dim
+    th = 18
+    recb = 4 if mixed else 8
+    pass1_bytes = 8 * state + 8 * 8 + 4 + 8 * th + recb * rec
+    # pass 2 reads the stage state and the step-start state, its own thermo
+    # record (11 values) and neighbour record, writes the new state
+    pass2_bytes = 8 * state * 2 + 8 * 11 + recb * rec + 8 * state + 4
+    pair1 = 5 + 2 + 7 + 2 * (2 + ncharge)
+    pair2 = (5 + 2 + 5 + dim + 1 + 2 * dim + 2 * dim * dim) + ((3 * dim * dim + 2 * dim) if viscous else 0)
+    return dict(pass1_bytes=pass1_bytes, pass2_bytes=pass2_bytes, pass1_pair_flops=pair1, pass2_pair_flops=pair2)
+
+
+def run_gpu(B, I, w, eos, precision, steps, warmup):
+    import torch
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, precision=precision, ncharge=3, h=w.h,
+                   eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02)
+    sim = B.Sim(cfg, eos, w.n)
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    if warmup:
+        sim.step(w.dt, warmup)
+        sim.check()
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    nnb = float(sim.read(B.AUX_NNB).mean())
+    torch.cuda.synchronize()
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w.dt, steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sim.check()
+    tot, cnt = sim.totals()
+    # kernel durations: the same steps again, kernels bracketed by HIP events
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    sim.set_profiling(True)
+    sim.step(w.dt, steps)
+    ms, launches = sim.kernel_times()
+    sim.set_profiling(False)
+    sim.check()
+    sim.close()
+    return dict(elapsed=elapsed, nnb=nnb, ms=ms, launches=launches, totals=tot.tolist(),
+                backup=cnt.backup, newton_iters=cnt.newton_iters)
+
+
+def cpu_baseline_run(I, w, min_seconds):
+    """The FP64 oracle on the same event, Heun steps from the initial state
+    until at least min_seconds of wall time; OpenMP over particles."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    cols, lo, hi = I.massless_gas_table()
+    prm = O.params(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=w.h, eta_over_s=0.08,
+                   zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, use_cells=1, nthreads=threads)
+    eos = O.eos_table(cols, lo, hi)
+    y = O.init(prm, eos, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    t = w.t0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        y, _, _ = O.heun_step(prm, eos, t, w.dt, y)
+        t += w.dt
+        steps += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=w.n * steps / el, unit="particle-steps/s", cores=threads, kind="oracle",
+                sample=f"{w.n}-particle lumpy viscous BSQ event, {steps} FP64 Heun steps from the initial "
+                       f"state in {el:.1f} s (uniform-grid neighbour search, OpenMP over particles)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1480, help="timed Heun steps (1480 = tau 0.6 -> 8 fm/c)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
+              "note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2511_22852_amd import binding as B
+    from paper_2511_22852_amd import inputs as I
+
+    w = I.lumpy_2d_workload()
+    cols, lo, hi = I.massless_gas_table()
+    eos = B.Eos.table(cols, lo, hi)
+    res = {}
+    for name, prec in (("fp64", B.FP64), ("mixed", B.MIXED)):
+        res[name] = run_gpu(B, I, w, eos, prec, args.steps, args.warmup)
+        print(f"[bench] {name}: {args.steps} steps in {res[name]['elapsed']:.3f} s", file=sys.stderr, flush=True)
+
+    head = res["mixed"]
+    value = w.n * args.steps / head["elapsed"]
+    value64 = w.n * args.steps / res["fp64"]["elapsed"]
+    model = algorithmic_model(2, True, 3, True)
+
+    # roofline of the dominant kernel of the headline (mixed) run
+    names = ["binning", "pass1_density_eos", "pass2_gradients_eom_update"]
+    k = max((1, 2), key=lambda i: head["ms"][i])
+    avg_s = head["ms"][k] / head["launches"][k] / 1e3
+    nbytes = w.n * (model["pass1_bytes"] if k == 1 else model["pass2_bytes"])
+    flops = w.n * head["nnb"] * (model["pass1_pair_flops"] if k == 1 else model["pass2_pair_flops"])
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (FP32_PEAK_TFLOPS * 1e12)
+    if t_hbm >= t_alu:
+        roof = dict(bound="hbm", achieved=nbytes / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = names[k]
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["algorithmic_bytes_per_launch"] = nbytes
+    roof["algorithmic_flops_per_launch"] = flops
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["elapsed"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (Kahan) pair sums, f64 state/EoS/update",
+        "data": "synthetic",
+        "config": {"workload": "lumpy_2d_viscous_bsq_40k", "particles": w.n, "h_fm": w.h, "dt_fm": w.dt,
+                   "tau0_fm": w.t0, "eos": "massless-gas table 64x32x32x32 + analytic backup",
+                   "precision": "mixed", "mean_neighbours": head["nnb"]},
+        "fp64": {"value": value64, "ms_per_step": res["fp64"]["elapsed"] / args.steps * 1e3},
+        "mixed_over_fp64": value / value64,
+        "kernel_ms_per_step": {"mixed": [m / args.steps for m in head["ms"]],
+                               "fp64": [m / args.steps for m in res["fp64"]["ms"]],
+                               "groups": names},
+        "eos_backup_fraction_last_stage": head["backup"] / w.n,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_run(I, w, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -33,7 +33,7 @@ EXPORTS = [
     "ccake_eos_create_conformal", "ccake_eos_create_gas", "ccake_eos_create_table",
     "ccake_eos_destroy", "ccake_eos_invert", "ccake_workspace_bytes", "ccake_create",
     "ccake_init_particles", "ccake_set_state", "ccake_get_state", "ccake_time", "ccake_step",
-    "ccake_check", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
+    "ccake_check", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
     "ccake_destroy", "ccake_server_create", "ccake_server_submit", "ccake_server_poll",
     "ccake_server_drain", "ccake_server_release", "ccake_server_stats", "ccake_server_destroy",
     "ccake_last_error",
@@ -85,6 +85,9 @@ def lib():
     """Load libccake_hip.so; raises when it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime (same soname); loading torch first makes
+        # the library bind to that one instead of bringing a second runtime in
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_22852_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
@@ -104,6 +107,8 @@ def lib():
             "ccake_time": [vp, dp],
             "ccake_step": [vp, dbl, i32],
             "ccake_check": [vp],
+            "ccake_set_profiling": [vp, i32],
+            "ccake_kernel_times": [vp, dp, ctypes.POINTER(i64)],
             "ccake_rhs": [vp, vp, vp, i32],
             "ccake_read": [vp, i32, vp, i32],
             "ccake_totals": [vp, dp, ctypes.POINTER(Counters)],
@@ -259,6 +264,16 @@ class Sim:
     def synchronize(self):
         self.stream.synchronize()
 
+    def set_profiling(self, enable=True):
+        _check(lib().ccake_set_profiling(self.h, int(enable)), self.h)
+
+    def kernel_times(self):
+        """(ms, launches) per kernel group: 0 binning, 1 pass 1, 2 pass 2."""
+        ms = (ctypes.c_double * 3)()
+        nl = (ctypes.c_int64 * 3)()
+        _check(lib().ccake_kernel_times(self.h, ms, nl), self.h)
+        return list(ms), list(nl)
+
     # -- evaluation --------------------------------------------------------------
     def rhs(self):
         f = np.empty((NROW, self.n))
@@ -295,6 +310,69 @@ class Sim:
     def close(self):
         if getattr(self, "h", None):
             lib().ccake_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching serving loop (ccake_server_*): events are submitted
+    as they arrive, admitted by device footprint, stepped together, returned
+    when they reach their end time."""
+
+    def __init__(self, cfg: Config, eos: Eos, budget_bytes: int, max_particles: int, max_events: int, dt: float,
+                 device="cuda:0"):
+        import torch
+        self.cfg, self.eos, self.device = cfg, eos, torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        _check(lib().ccake_server_create(ctypes.byref(h), ctypes.byref(cfg), eos.h, int(budget_bytes),
+                                         int(max_particles), int(max_events), dt,
+                                         ctypes.c_void_p(self.stream.cuda_stream)), what="ccake_server_create")
+        self.h = h
+
+    def submit(self, t0, t_end, xi, u, dens_kind, dens, tag=0):
+        xi, u, dens = _f64(xi), _f64(u), _f64(dens)
+        d = EventDesc()
+        d.n = xi.shape[1]
+        d.t0, d.t_end = t0, t_end
+        dp = ctypes.POINTER(ctypes.c_double)
+        d.xi, d.u, d.dens = xi.ctypes.data_as(dp), u.ctypes.data_as(dp), dens.ctypes.data_as(dp)
+        d.dens_kind, d.user_tag = dens_kind, tag
+        t = ctypes.c_int64()
+        _check(lib().ccake_server_submit(self.h, ctypes.byref(d), ctypes.byref(t)), self.h)
+        return t.value
+
+    def poll(self, cap=64):
+        res = (EventResult * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().ccake_server_poll(self.h, res, cap, ctypes.byref(cnt)), self.h)
+        out = []
+        for k in range(cnt.value):
+            r = res[k]
+            state = np.ctypeslib.as_array(r.state, shape=(NROW * r.n,)).reshape(NROW, r.n).copy()
+            out.append(dict(ticket=r.ticket, tag=r.user_tag, n=r.n, status=r.status, steps=r.steps,
+                            t_submit=r.t_submit, t_admit=r.t_admit, t_finish=r.t_finish, state=state,
+                            totals=list(r.totals)))
+            lib().ccake_server_release(self.h, ctypes.byref(r))
+        return out
+
+    def drain(self):
+        _check(lib().ccake_server_drain(self.h), self.h)
+
+    def stats(self):
+        now, steps, ps, res = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().ccake_server_stats(self.h, ctypes.byref(now), ctypes.byref(steps), ctypes.byref(ps),
+                                        ctypes.byref(res)), self.h)
+        return dict(now=now.value, steps=steps.value, particle_steps=ps.value, resident=res.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ccake_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -6,15 +6,18 @@
 
 namespace ccake {
 
+// marks (optional): 2 events recorded before and after the binning kernels
 hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, uint32_t rowmask,
-                      hipStream_t s);
+                      hipStream_t s, const hipEvent_t* marks = nullptr);
 // which = 0: full Heun step (two stages); which = 1: pass 1 (+ pass 2 in rate mode when fout != null)
+// marks (optional, which = 0): 5 events around pass 1 / pass 2 of both stages
 hipError_t launch_passes(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, int which,
-                         double* fout, double* aux, hipStream_t s);
+                         double* fout, double* aux, hipStream_t s, const hipEvent_t* marks = nullptr);
 hipError_t launch_advance(const BatchDev& b, hipStream_t s);
 hipError_t launch_reset_stage_counters(const BatchDev& b, hipStream_t s);
+// only_event >= 0 restricts the initialisation to that event
 hipError_t launch_init(const BatchDev& b, const Params& prm, const EosDev& eos, int dens_kind, const double* dens,
-                       int64_t nslots, hipStream_t s);
+                       int64_t nslots, hipStream_t s, int only_event = -1);
 hipError_t launch_commit(const BatchDev& b, int64_t nslots, uint32_t rowmask, hipStream_t s);
 hipError_t launch_pairs(const BatchDev& b, const Params& prm, int e, int64_t n, int64_t* counter, int64_t cap,
                         int32_t* pa, int32_t* pb, hipStream_t s);

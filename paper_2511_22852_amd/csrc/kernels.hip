@@ -759,11 +759,11 @@ __global__ void k_reset_stage_counters(BatchDev b) {
 // initialisation: S = s gamma sqrt(-g) / sigma*, N likewise (sorted order)
 template <int D>
 __global__ void __launch_bounds__(256) k_init(BatchDev b, Params prm, EosDev eos, int dens_kind,
-                                              const double* __restrict__ dens, int64_t nslots) {
+                                              const double* __restrict__ dens, int64_t nslots, int only_event) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nslots) return;
   const int e = b.ev[j];
-  if (e < 0) return;
+  if (e < 0 || (only_event >= 0 && e != only_event)) return;
   const EventDev& E = b.evt[e];
   const double t = E.t;
   const int64_t cap = b.cap;
@@ -929,30 +929,37 @@ __global__ void __launch_bounds__(256) k_eos_invert(EosDev eos, int mode, int nq
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, uint32_t rowmask,
-                      hipStream_t s) {
+                      hipStream_t s, const hipEvent_t* marks) {
   if (nslots <= 0 || nevents <= 0) return hipSuccess;
+  if (marks) (void)hipEventRecord(marks[0], s);
   hipLaunchKernelGGL(k_bbox, dim3(nevents), dim3(256), 0, s, b, prm, prm.dim);
   hipLaunchKernelGGL(k_count, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, b, prm.dim, nslots);
   hipLaunchKernelGGL(k_scan, dim3(nevents), dim3(1024), 0, s, b, prm.dim);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, b, nslots);
   hipLaunchKernelGGL(k_cellsort, dim3(8, nevents), dim3(256), 0, s, b, prm.dim);
   hipLaunchKernelGGL(k_permute, dim3(blocks_for(nslots, 256)), dim3(256), 0, s, b, nslots, rowmask);
+  if (marks) (void)hipEventRecord(marks[1], s);
   return hipGetLastError();
 }
 
 template <int D, bool VISC, bool MIXED>
 static void launch_passes_t(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, int which,
-                            double* fout, double* aux, hipStream_t s) {
+                            double* fout, double* aux, hipStream_t s, const hipEvent_t* marks) {
   const unsigned g = blocks_for(nslots, 256);
   if (which == 0) {  // full Heun step
+    if (marks) (void)hipEventRecord(marks[0], s);
     hipLaunchKernelGGL((k_pass1<D, VISC, MIXED>), dim3(g), dim3(256), 0, s, b, prm, eos, b.Ys, 0, nslots,
                        (double*)nullptr);
+    if (marks) (void)hipEventRecord(marks[1], s);
     hipLaunchKernelGGL((k_pass2<D, VISC, MIXED>), dim3(g), dim3(256), 0, s, b, prm, b.Ys, 0, 0, nslots,
                        (double*)nullptr, (double*)nullptr);
+    if (marks) (void)hipEventRecord(marks[2], s);
     hipLaunchKernelGGL((k_pass1<D, VISC, MIXED>), dim3(g), dim3(256), 0, s, b, prm, eos, b.Y1, 1, nslots,
                        (double*)nullptr);
+    if (marks) (void)hipEventRecord(marks[3], s);
     hipLaunchKernelGGL((k_pass2<D, VISC, MIXED>), dim3(g), dim3(256), 0, s, b, prm, b.Y1, 1, 1, nslots,
                        (double*)nullptr, (double*)nullptr);
+    if (marks) (void)hipEventRecord(marks[4], s);
   } else if (which == 1) {  // right-hand side only, at the sorted state
     hipLaunchKernelGGL((k_pass1<D, VISC, MIXED>), dim3(g), dim3(256), 0, s, b, prm, eos, b.Ys, 0, nslots, aux);
     if (fout)
@@ -962,18 +969,18 @@ static void launch_passes_t(const BatchDev& b, const Params& prm, const EosDev& 
 }
 
 hipError_t launch_passes(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, int which,
-                         double* fout, double* aux, hipStream_t s) {
+                         double* fout, double* aux, hipStream_t s, const hipEvent_t* marks) {
   if (nslots <= 0) return hipSuccess;
   const int key = (prm.dim == 3 ? 4 : 0) + (prm.viscous ? 2 : 0) + (prm.mixed ? 1 : 0);
   switch (key) {
-    case 0: launch_passes_t<2, false, false>(b, prm, eos, nslots, which, fout, aux, s); break;
-    case 1: launch_passes_t<2, false, true>(b, prm, eos, nslots, which, fout, aux, s); break;
-    case 2: launch_passes_t<2, true, false>(b, prm, eos, nslots, which, fout, aux, s); break;
-    case 3: launch_passes_t<2, true, true>(b, prm, eos, nslots, which, fout, aux, s); break;
-    case 4: launch_passes_t<3, false, false>(b, prm, eos, nslots, which, fout, aux, s); break;
-    case 5: launch_passes_t<3, false, true>(b, prm, eos, nslots, which, fout, aux, s); break;
-    case 6: launch_passes_t<3, true, false>(b, prm, eos, nslots, which, fout, aux, s); break;
-    case 7: launch_passes_t<3, true, true>(b, prm, eos, nslots, which, fout, aux, s); break;
+    case 0: launch_passes_t<2, false, false>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
+    case 1: launch_passes_t<2, false, true>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
+    case 2: launch_passes_t<2, true, false>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
+    case 3: launch_passes_t<2, true, true>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
+    case 4: launch_passes_t<3, false, false>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
+    case 5: launch_passes_t<3, false, true>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
+    case 6: launch_passes_t<3, true, false>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
+    case 7: launch_passes_t<3, true, true>(b, prm, eos, nslots, which, fout, aux, s, marks); break;
   }
   return hipGetLastError();
 }
@@ -989,12 +996,13 @@ hipError_t launch_reset_stage_counters(const BatchDev& b, hipStream_t s) {
 }
 
 hipError_t launch_init(const BatchDev& b, const Params& prm, const EosDev& eos, int dens_kind, const double* dens,
-                       int64_t nslots, hipStream_t s) {
+                       int64_t nslots, hipStream_t s, int only_event) {
   const unsigned g = blocks_for(nslots, 256);
+  if (g == 0) return hipSuccess;
   if (prm.dim == 3)
-    hipLaunchKernelGGL(k_init<3>, dim3(g), dim3(256), 0, s, b, prm, eos, dens_kind, dens, nslots);
+    hipLaunchKernelGGL(k_init<3>, dim3(g), dim3(256), 0, s, b, prm, eos, dens_kind, dens, nslots, only_event);
   else
-    hipLaunchKernelGGL(k_init<2>, dim3(g), dim3(256), 0, s, b, prm, eos, dens_kind, dens, nslots);
+    hipLaunchKernelGGL(k_init<2>, dim3(g), dim3(256), 0, s, b, prm, eos, dens_kind, dens, nslots, only_event);
   return hipGetLastError();
 }
 

@@ -427,11 +427,53 @@ extern "C" ccake_status ccake_time(const ccake_sim* s, double* t) {
   return CCAKE_OK;
 }
 
-static ccake_status enqueue_step(ccake_sim* s) {
+static const int PROF_MARKS = 7;  // 2 around the binning, 5 around the passes
+
+static ccake_status enqueue_step(ccake_sim* s, const hipEvent_t* marks) {
   HIPCHK(s, launch_reset_stage_counters(s->b, s->stream));
-  HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream));
-  HIPCHK(s, launch_passes(s->b, s->prm, s->eos, s->n, 0, nullptr, nullptr, s->stream));
+  HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream, marks));
+  HIPCHK(s, launch_passes(s->b, s->prm, s->eos, s->n, 0, nullptr, nullptr, s->stream, marks ? marks + 2 : nullptr));
   HIPCHK(s, launch_advance(s->b, s->stream));
+  return CCAKE_OK;
+}
+
+// accumulate the kernel durations of nsteps profiled steps (synchronises)
+static ccake_status collect_profile(ccake_sim* s, int nsteps) {
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (int k = 0; k < nsteps; ++k) {
+    const hipEvent_t* m = &s->prof_ev[(size_t)k * PROF_MARKS];
+    float a = 0.f, b1 = 0.f, b2 = 0.f, c1 = 0.f, c2 = 0.f;
+    HIPCHK(s, hipEventElapsedTime(&a, m[0], m[1]));
+    HIPCHK(s, hipEventElapsedTime(&b1, m[2], m[3]));
+    HIPCHK(s, hipEventElapsedTime(&c1, m[3], m[4]));
+    HIPCHK(s, hipEventElapsedTime(&b2, m[4], m[5]));
+    HIPCHK(s, hipEventElapsedTime(&c2, m[5], m[6]));
+    s->prof_ms[0] += a;
+    s->prof_ms[1] += (double)b1 + b2;
+    s->prof_ms[2] += (double)c1 + c2;
+    s->prof_n[0] += 1;
+    s->prof_n[1] += 2;
+    s->prof_n[2] += 2;
+  }
+  return CCAKE_OK;
+}
+
+extern "C" ccake_status ccake_set_profiling(ccake_sim* s, int32_t enable) {
+  if (!s) return CCAKE_E_ARG;
+  s->prof = enable != 0;
+  for (int k = 0; k < 3; ++k) {
+    s->prof_ms[k] = 0.0;
+    s->prof_n[k] = 0;
+  }
+  return CCAKE_OK;
+}
+
+extern "C" ccake_status ccake_kernel_times(ccake_sim* s, double* ms, int64_t* launches) {
+  if (!s || !ms || !launches) return CCAKE_E_ARG;
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = s->prof_ms[k];
+    launches[k] = s->prof_n[k];
+  }
   return CCAKE_OK;
 }
 
@@ -457,10 +499,30 @@ extern "C" ccake_status ccake_step(ccake_sim* s, double dt, int32_t nsteps) {
   }
   s->dt_host = dt;
   HIPCHK(s, hipMemcpyAsync(&s->b.evt[0].dt, &s->dt_host, sizeof(double), hipMemcpyHostToDevice, s->stream));
+  if (s->prof) {
+    // direct launches bracketed by timing events
+    const size_t need = (size_t)nsteps * PROF_MARKS;
+    while (s->prof_ev.size() < need) {
+      hipEvent_t e;
+      HIPCHK(s, hipEventCreate(&e));
+      s->prof_ev.push_back(e);
+    }
+    for (int k = 0; k < nsteps; ++k) {
+      ccake_status st = enqueue_step(s, &s->prof_ev[(size_t)k * PROF_MARKS]);
+      if (st) return st;
+    }
+    ccake_status st = collect_profile(s, nsteps);
+    if (st) return st;
+    s->t += dt * nsteps;
+    HIPCHK(s, hipMemcpyAsync(s->h_evt, s->b.evt, sizeof(EventDev), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipEventRecord(s->evt_done, s->stream));
+    s->pending = true;
+    return CCAKE_OK;
+  }
   if (s->use_graph && !s->graph_ready) {
     hipError_t e1 = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
     if (e1 == hipSuccess) {
-      ccake_status st = enqueue_step(s);
+      ccake_status st = enqueue_step(s, nullptr);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(s->stream, &g);
       if (st == CCAKE_OK && e2 == hipSuccess && g &&
@@ -479,7 +541,7 @@ extern "C" ccake_status ccake_step(ccake_sim* s, double dt, int32_t nsteps) {
     if (s->graph_ready) {
       HIPCHK(s, hipGraphLaunch(s->graph, s->stream));
     } else {
-      ccake_status st = enqueue_step(s);
+      ccake_status st = enqueue_step(s, nullptr);
       if (st) return st;
     }
   }
@@ -573,6 +635,7 @@ extern "C" ccake_status ccake_destroy(ccake_sim* s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->graph_ready) (void)hipGraphExecDestroy(s->graph);
   if (s->evt_done) (void)hipEventDestroy(s->evt_done);
+  for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->h_evt) (void)hipHostFree(s->h_evt);
   delete s;
   return CCAKE_OK;

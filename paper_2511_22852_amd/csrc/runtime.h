@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "ccake.h"
 #include "common.h"
@@ -52,4 +53,9 @@ struct ccake_sim : ccake::Handle {
   hipGraphExec_t graph = nullptr;
   hipEvent_t evt_done = nullptr;
   ccake::EventDev* h_evt = nullptr;  // pinned copy of the event record
+  // kernel timing with HIP events on the simulation's stream (profiling mode)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;
+  double prof_ms[3] = {0.0, 0.0, 0.0};
+  int64_t prof_n[3] = {0, 0, 0};
 };
