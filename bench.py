@@ -33,22 +33,30 @@ FP32_PEAK_TFLOPS = 157.3     # vector FP32, published (packed) figure
 METRIC = "SPH particle-steps/s (FP64 vs FP32-Kahan) + p50/p99 event latency, 1 GPU"
 
 
-def algorithmic_model(dim, viscous, ncharge, mixed):
-    """Compulsory HBM bytes per particle and flops per accepted pair of the two
-    pass kernels (one launch = one Heun stage).  Neighbour reads are staged
-    on chip and are not counted; see the design doc for the derivation."""
+GROUPS = ["binning", "density_sums", "eos_inversion", "gradient_sums", "eom_update"]
+
+
+def algorithmic_model(dim, viscous, ncharge, mixed, smoothed=True):
+    """Per kernel of one Heun stage: compulsory HBM bytes per particle (each
+    array the kernel must touch, read or written once; neighbour data reused
+    on chip is not counted) and flops per accepted neighbour pair.  The
+    derivation is in DESIGN.md."""
     nP = (6 if dim == 3 else 4) if viscous else 0
     state = 2 * dim + 1 + ncharge + (1 + nP if viscous else 0)
     rec = 1 + (dim * dim if viscous else 0) + 2 * dim
-    th = 18
     recb = 4 if mixed else 8
-    pass1_bytes = 8 * state + 8 * 8 + 4 + 8 * th + recb * rec
-    # pass 2 reads the stage state and the step-start state, its own thermo
-    # record (11 values) and neighbour record, writes the new state
-    pass2_bytes = 8 * state * 2 + 8 * 11 + recb * rec + 8 * state + 4
-    pair1 = 5 + 2 + 7 + 2 * (2 + ncharge)
-    pair2 = (5 + 2 + 5 + dim + 1 + 2 * dim + 2 * dim * dim) + ((3 * dim * dim + 2 * dim) if viscous else 0)
-    return dict(pass1_bytes=pass1_bytes, pass2_bytes=pass2_bytes, pass1_pair_flops=pair1, pass2_pair_flops=pair2)
+    nth = 6 + (5 if viscous else 0)
+    ngs = dim + dim * dim + 1
+    dens_in = dim + ((1 + ncharge) if smoothed else 0)
+    return {
+        "density_sums": dict(bytes=8 * dens_in + 4 + 8 * 6,
+                             pair_flops=5 + 1 + 1 + 7 + 1 + (2 * (1 + ncharge) if smoothed else 0)),
+        "eos_inversion": dict(bytes=8 * 5 + 8 * (state - dim) + 8 * 4 * 2 + 8 * nth + recb * rec, pair_flops=0),
+        "gradient_sums": dict(bytes=8 * dim + 4 + recb * rec + 8 + 8 * ngs,
+                              pair_flops=5 + 1 + 1 + 5 + 1 + dim + 1 + 2 * dim + 4 * dim * dim + 3 * dim
+                              + ((4 * dim * dim + dim) if viscous else 0)),
+        "eom_update": dict(bytes=8 * ngs + 8 * nth + 8 * state * 3, pair_flops=0),
+    }
 
 
 def run_gpu(B, I, w, eos, precision, steps, warmup):
@@ -138,11 +146,11 @@ def main():
     model = algorithmic_model(2, True, 3, True)
 
     # roofline of the dominant kernel of the headline (mixed) run
-    names = ["binning", "pass1_density_eos", "pass2_gradients_eom_update"]
-    k = max((1, 2), key=lambda i: head["ms"][i])
+    names = GROUPS
+    k = max(range(1, len(GROUPS)), key=lambda i: head["ms"][i])
     avg_s = head["ms"][k] / head["launches"][k] / 1e3
-    nbytes = w.n * (model["pass1_bytes"] if k == 1 else model["pass2_bytes"])
-    flops = w.n * head["nnb"] * (model["pass1_pair_flops"] if k == 1 else model["pass2_pair_flops"])
+    nbytes = w.n * model[names[k]]["bytes"]
+    flops = w.n * head["nnb"] * model[names[k]]["pair_flops"]
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (FP32_PEAK_TFLOPS * 1e12)
     if t_hbm >= t_alu:

@@ -188,12 +188,14 @@ ccake_status ccake_check(ccake_sim* sim);
 
 /* Measurement support.  With profiling enabled, ccake_step launches its
  * kernels directly (no HIP graph) with HIP timing events recorded on the
- * simulation's stream around the binning kernels, pass 1 and pass 2 of both
- * Heun stages, and synchronises at the end of the call.  Enabling resets the
- * accumulators.  ccake_kernel_times returns, per group (0 binning, 1 pass 1,
- * 2 pass 2), the summed milliseconds and the number of launches.            */
+ * simulation's stream around the binning kernels and around each kernel of
+ * both Heun stages, and synchronises at the end of the call.  Enabling resets
+ * the accumulators.  ccake_kernel_times returns, per group (0 binning, 1
+ * density sums, 2 EoS inversion, 3 gradient sums, 4 equations of motion and
+ * update), the summed milliseconds and the number of launches.              */
+enum { CCAKE_NPROF = 5 };
 ccake_status ccake_set_profiling(ccake_sim* sim, int32_t enable);
-ccake_status ccake_kernel_times(ccake_sim* sim, double ms[3], int64_t launches[3]);
+ccake_status ccake_kernel_times(ccake_sim* sim, double ms[CCAKE_NPROF], int64_t launches[CCAKE_NPROF]);
 
 /* One evaluation of the right-hand side at the current state, without
  * stepping: rates f [17][n] and diagnostics aux [CCAKE_NAUX][n] (either may be

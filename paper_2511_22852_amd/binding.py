@@ -268,9 +268,9 @@ class Sim:
         _check(lib().ccake_set_profiling(self.h, int(enable)), self.h)
 
     def kernel_times(self):
-        """(ms, launches) per kernel group: 0 binning, 1 pass 1, 2 pass 2."""
-        ms = (ctypes.c_double * 3)()
-        nl = (ctypes.c_int64 * 3)()
+        """(ms, launches) per kernel group: 0 binning, 1 density, 2 EoS, 3 gradients, 4 EoM + update."""
+        ms = (ctypes.c_double * 5)()
+        nl = (ctypes.c_int64 * 5)()
         _check(lib().ccake_kernel_times(self.h, ms, nl), self.h)
         return list(ms), list(nl)
 

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libccake_hip.so")
-SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp"]
+SOURCES = ["binning.hip", "stage.hip", "kernels.hip", "runtime.cpp", "server.cpp"]
 ARCH = os.environ.get("CCAKE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,265 @@
+// Cell binning of a batch of events: per-event bounding box and grid (cell
+// edge >= 2h + skin, the kernel support of "Kernel function" plus the skin
+// that keeps stage-2 pairs inside the block), stable counting sort of the
+// particles by (cell, original id).  This is the uniform-grid neighbour
+// binning the paper takes from Cabana's VerletList, rebuilt as
+//   k_bbox   grid-stride min/max per event: wave reduction, one atomic per wave
+//            on order-preserving integer images of the coordinates
+//   k_grid   one thread per event: grid origin, cells per axis, reset of the box
+//   k_count  particle -> cell key, atomic count per cell
+//   k_scan   one block per event: exclusive scan of the counts
+//   k_scatter particle -> slot of its cell (arbitrary order within the cell)
+//   k_cellsort one wave per cell: rank by original id, so the order inside a
+//            cell is deterministic; clears the counts for the next binning
+//   k_permute gather of the state, warm starts, ids and keys into cell order
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "kernels.h"
+#include "sph_device.h"
+
+namespace ccake {
+
+__global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslots) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int e = i < nslots ? b.ev[i] : -1;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  if (e >= 0) {
+    for (int k = 0; k < dim; ++k) {
+      const double x = row(b.Y0, b.cap, R_X1 + k, i);
+      if (isfinite(x)) {
+        lo[k] = x;
+        hi[k] = x;
+      }
+    }
+  }
+  // is the whole wave on one event?
+  const int e0 = __shfl(e, 0, 64);
+  const bool uniform = __all(e == e0);
+  if (uniform) {
+    if (e0 < 0) return;
+    for (int k = 0; k < dim; ++k) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        lo[k] = fmin(lo[k], __shfl_xor(lo[k], off, 64));
+        hi[k] = fmax(hi[k], __shfl_xor(hi[k], off, 64));
+      }
+    }
+    if (lane == 0) {
+      EventDev* E = b.evt + e0;
+      for (int k = 0; k < dim; ++k) {
+        if (isfinite(lo[k])) atomicMin(&E->bb_min[k], ordered_bits(lo[k]));
+        if (isfinite(hi[k])) atomicMax(&E->bb_max[k], ordered_bits(hi[k]));
+      }
+    }
+  } else if (e >= 0) {
+    EventDev* E = b.evt + e;
+    for (int k = 0; k < dim; ++k) {
+      if (isfinite(lo[k])) atomicMin(&E->bb_min[k], ordered_bits(lo[k]));
+      if (isfinite(hi[k])) atomicMax(&E->bb_max[k], ordered_bits(hi[k]));
+    }
+  }
+}
+
+__global__ void k_grid(BatchDev b, Params prm, int dim) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b.max_events) return;
+  EventDev* E = b.evt + e;
+  if (!E->active) return;
+  double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+  bool empty = false;
+  for (int k = 0; k < dim; ++k) {
+    if (E->bb_min[k] == BB_EMPTY_MIN || E->bb_max[k] == BB_EMPTY_MAX) {
+      empty = true;
+    } else {
+      lo[k] = from_ordered_bits(E->bb_min[k]);
+      hi[k] = from_ordered_bits(E->bb_max[k]);
+    }
+    E->bb_min[k] = BB_EMPTY_MIN;
+    E->bb_max[k] = BB_EMPTY_MAX;
+  }
+  if (empty) {
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = 0.0;
+    if (E->n > 0) E->capacity_err += 1;  // every coordinate non-finite
+  }
+  double edge = prm.cell_edge;
+  int64_t nc[3] = {1, 1, 1}, tot = 1;
+  // coarsen the grid (never below the cutoff) until it fits the capacity
+  for (int it = 0; it < 64; ++it) {
+    tot = 1;
+    for (int k = 0; k < dim; ++k) {
+      nc[k] = (int64_t)floor((hi[k] - lo[k]) / edge) + 1;
+      tot *= nc[k];
+    }
+    if (tot + 1 <= E->c_cap) break;
+    edge *= 1.25;
+  }
+  if (tot + 1 > E->c_cap) {
+    E->capacity_err += 1;
+    for (int k = 0; k < 3; ++k) nc[k] = 1;
+  }
+  for (int k = 0; k < 3; ++k) {
+    E->lo[k] = lo[k];
+    E->nc[k] = (int32_t)nc[k];
+  }
+  E->edge = edge;
+}
+
+__global__ void __launch_bounds__(256) k_count(BatchDev b, int dim, int64_t nslots) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nslots) return;
+  const int e = b.ev[i];
+  if (e < 0) return;
+  const EventDev& E = b.evt[e];
+  int32_t key = 0, stride = 1;
+  for (int k = 0; k < dim; ++k) {
+    const double u = (row(b.Y0, b.cap, R_X1 + k, i) - E.lo[k]) / E.edge;
+    int c = (int)floor(u);
+    c = c < 0 ? 0 : (c >= E.nc[k] ? E.nc[k] - 1 : c);
+    key += c * stride;
+    stride *= E.nc[k];
+  }
+  b.key[i] = key;
+  atomicAdd(&b.cell_fill[E.c_base + key], 1);
+}
+
+// exclusive scan of the cell counts of one event (one 1024-thread block per event)
+__global__ void __launch_bounds__(1024) k_scan(BatchDev b, int dim) {
+  const int e = blockIdx.x;
+  const EventDev& E = b.evt[e];
+  if (!E.active) return;
+  int64_t ncell = 1;
+  for (int k = 0; k < dim; ++k) ncell *= E.nc[k];
+  __shared__ int32_t part[1024];
+  const int T = blockDim.x;
+  const int64_t chunk = (ncell + T - 1) / T;
+  const int64_t c0 = threadIdx.x * chunk, c1 = min(ncell, c0 + chunk);
+  int32_t* cf = b.cell_fill + E.c_base;
+  int32_t* cs = b.cell_start + E.c_base;
+  int32_t sum = 0;
+  for (int64_t c = c0; c < c1; ++c) sum += cf[c];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    const int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int32_t run = (int32_t)E.p_base + (threadIdx.x > 0 ? part[threadIdx.x - 1] : 0);
+  for (int64_t c = c0; c < c1; ++c) {
+    const int32_t cnt = cf[c];
+    cs[c] = run;
+    cf[c] = run;  // becomes the scatter cursor
+    run += cnt;
+  }
+  if (threadIdx.x == T - 1) cs[ncell] = (int32_t)(E.p_base + E.n);
+}
+
+__global__ void __launch_bounds__(256) k_scatter(BatchDev b, int64_t nslots) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nslots) return;
+  const int e = b.ev[i];
+  if (e < 0) return;
+  const int32_t slot = atomicAdd(&b.cell_fill[b.evt[e].c_base + b.key[i]], 1);
+  b.perm[slot] = (int32_t)i;
+}
+
+// one wave per cell: the rank of each member is the number of members with a
+// smaller original id (ids are unique within an event)
+constexpr int SORT_CAP = 1024;  // members per cell held in LDS by one wave
+__global__ void __launch_bounds__(256) k_cellsort(BatchDev b, int dim) {
+  __shared__ int32_t s_id[4][SORT_CAP];
+  __shared__ int32_t s_p[4][SORT_CAP];
+  const int e = blockIdx.y;
+  const EventDev& E = b.evt[e];
+  if (!E.active) return;
+  int64_t ncell = 1;
+  for (int k = 0; k < dim; ++k) ncell *= E.nc[k];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t* cs = b.cell_start + E.c_base;
+  int32_t* cf = b.cell_fill + E.c_base;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + w; c < ncell; c += nwaves) {
+    const int32_t s = cs[c], m = cs[c + 1] - s;
+    if (lane == 0) cf[c] = 0;
+    if (m <= 1) continue;
+    if (m <= SORT_CAP) {
+      for (int k = lane; k < m; k += 64) {
+        const int32_t p = b.perm[s + k];
+        s_p[w][k] = p;
+        s_id[w][k] = b.id[p];
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      for (int k = lane; k < m; k += 64) {
+        const int32_t mine = s_id[w][k];
+        int rank = 0;
+        for (int q = 0; q < m; ++q) rank += s_id[w][q] < mine ? 1 : 0;
+        b.perm[s + rank] = s_p[w][k];
+      }
+      __builtin_amdgcn_wave_barrier();
+    } else if (lane == 0) {
+      // oversized cell (degenerate grid): insertion sort by one lane
+      for (int32_t i = s + 1; i < s + m; ++i) {
+        const int32_t p = b.perm[i];
+        const int32_t pid = b.id[p];
+        int32_t j = i - 1;
+        while (j >= s && b.id[b.perm[j]] > pid) {
+          b.perm[j + 1] = b.perm[j];
+          --j;
+        }
+        b.perm[j + 1] = p;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_permute(BatchDev b, int64_t nslots, uint32_t rowmask) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nslots || b.ev[j] < 0) return;
+  const int64_t src = b.perm[j];
+  for (int r = 0; r < NROW; ++r)
+    if (rowmask & (1u << r)) b.Ys[(int64_t)r * b.cap + j] = b.Y0[(int64_t)r * b.cap + src];
+  for (int w = 0; w < NWARM; ++w) b.warms[(int64_t)w * b.cap + j] = b.warm[(int64_t)w * b.cap + src];
+  b.ids[j] = b.id[src];
+  b.keys[j] = b.key[src];
+}
+
+// sorted -> home (after an initialisation)
+__global__ void __launch_bounds__(256) k_commit(BatchDev b, int64_t nslots, uint32_t rowmask) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nslots || b.ev[j] < 0) return;
+  for (int r = 0; r < NROW; ++r)
+    if (rowmask & (1u << r)) b.Y0[(int64_t)r * b.cap + j] = b.Ys[(int64_t)r * b.cap + j];
+  for (int w = 0; w < NWARM; ++w) b.warm[(int64_t)w * b.cap + j] = b.warms[(int64_t)w * b.cap + j];
+  b.id[j] = b.ids[j];
+}
+
+static inline unsigned blocks_of(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, uint32_t rowmask,
+                      hipStream_t s, const hipEvent_t* marks) {
+  if (nslots <= 0 || nevents <= 0) return hipSuccess;
+  if (marks) (void)hipEventRecord(marks[0], s);
+  hipLaunchKernelGGL(k_bbox, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, prm.dim, nslots);
+  hipLaunchKernelGGL(k_grid, dim3(blocks_of(nevents, 64)), dim3(64), 0, s, b, prm, prm.dim);
+  hipLaunchKernelGGL(k_count, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, prm.dim, nslots);
+  hipLaunchKernelGGL(k_scan, dim3(nevents), dim3(1024), 0, s, b, prm.dim);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, nslots);
+  // enough waves for one cell each on a 40k-particle event, grid-stride beyond
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(512, nslots / (nevents * 64) + 1));
+  hipLaunchKernelGGL(k_cellsort, dim3(gx, nevents), dim3(256), 0, s, b, prm.dim);
+  hipLaunchKernelGGL(k_permute, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, nslots, rowmask);
+  if (marks) (void)hipEventRecord(marks[1], s);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit(const BatchDev& b, int64_t nslots, uint32_t rowmask, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_commit, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, nslots, rowmask);
+  return hipGetLastError();
+}
+
+}  // namespace ccake

@@ -9,6 +9,7 @@
 //   * the index 3 is eta (hyperbolic) or z (Cartesian); in 2+1D it is a
 //     symmetry direction (u^3 = 0, no particle coordinate).
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace ccake {
@@ -37,6 +38,13 @@ enum Rec { Q_PP, Q_A11, Q_A12, Q_A13, Q_A21, Q_A22, Q_A23, Q_A31, Q_A32, Q_A33,
 
 // warm-start record of the EoS inversion (carried with the particle)
 enum Warm { W_T, W_MUB, W_MUS, W_MUQ, NWARM };
+
+// density sums of a particle (lab frame, kernel normalisation applied) and its neighbour count
+enum DSum { DS_SIG, DS_S, DS_NB, DS_NS, DS_NQ, DS_NNB, NDSUM };
+
+// gradient sums of a particle: force F_i, d_k u^j (row-major k*3+j, divided by sigma*), div v
+enum GSum { GS_F1, GS_F2, GS_F3, GS_DU11, GS_DU12, GS_DU13, GS_DU21, GS_DU22, GS_DU23, GS_DU31, GS_DU32,
+            GS_DU33, GS_DIVV, NGSUM };
 
 enum EosKind { EOS_CONFORMAL = 0, EOS_TABLE = 1, EOS_GAS = 2 };
 
@@ -80,7 +88,30 @@ struct EventDev {
   int32_t first_bad;  // lowest original id with a non-finite update, or -1
   uint32_t capacity_err;
   uint32_t newton_iters; // total Newton iterations (last stage)
+  // bounding-box accumulators of the next binning: order-preserving integer
+  // images of the coordinates (reset to the empty box after every use)
+  unsigned long long bb_min[3], bb_max[3];
 };
+
+// order-preserving map double -> unsigned 64-bit (for atomic min / max)
+__host__ __device__ inline unsigned long long ordered_bits(double d) {
+  union {
+    double d;
+    unsigned long long u;
+  } v;
+  v.d = d;
+  return (v.u & 0x8000000000000000ull) ? ~v.u : (v.u | 0x8000000000000000ull);
+}
+__host__ __device__ inline double from_ordered_bits(unsigned long long u) {
+  union {
+    double d;
+    unsigned long long u;
+  } v;
+  v.u = (u & 0x8000000000000000ull) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+  return v.d;
+}
+constexpr unsigned long long BB_EMPTY_MIN = 0xFFFFFFFFFFFFFFFFull;
+constexpr unsigned long long BB_EMPTY_MAX = 0ull;
 
 // device arrays of a batch (pointers into one workspace)
 struct BatchDev {
@@ -92,6 +123,8 @@ struct BatchDev {
   float* recf;       // [NREC][cap] fp32 neighbour records (mixed precision)
   double* warm;      // home warm start [NWARM][cap]
   double* warms;     // sorted warm start [NWARM][cap]
+  double* dsum;      // [NDSUM][cap] density sums (sorted order)
+  double* gsum;      // [NGSUM][cap] gradient sums (sorted order)
   int32_t* id;       // home original ids
   int32_t* ids;      // sorted original ids
   int32_t* ev;       // event of each slot (-1 = empty)

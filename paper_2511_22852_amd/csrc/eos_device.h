@@ -194,74 +194,93 @@ __device__ inline void inv_resid(const EosDev& e, bool use_table, int mode, cons
   }
 }
 
-// nu x nu (nu <= 4) solve by Gaussian elimination with partial pivoting.
-__device__ inline bool lsolve(int nu, double A[4][4], const double b[4], double x[4]) {
-  double M[4][5];
+// NU x NU (NU = 1 or 4) solve by Gaussian elimination with partial pivoting;
+// all indices are compile-time constants (row exchanges are selects), so the
+// system stays in registers.
+template <int NU>
+__device__ inline bool lsolve(double A[4][4], double b[4], double x[4]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) M[i][j] = A[i][j];
-    M[i][4] = b[i];
-  }
-  for (int col = 0; col < nu; ++col) {
+  for (int col = 0; col < NU; ++col) {
     int piv = col;
-    for (int r = col + 1; r < nu; ++r)
-      if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
-    if (!(M[piv][col] != 0.0) || !isfinite(M[piv][col])) return false;
-    if (piv != col) {
-      for (int j = 0; j < 5; ++j) {
-        double t = M[col][j];
-        M[col][j] = M[piv][j];
-        M[piv][j] = t;
+    double best = fabs(A[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < NU; ++r) {
+      const double v = fabs(A[r][col]);
+      if (v > best) {
+        best = v;
+        piv = r;
       }
     }
-    for (int r = col + 1; r < nu; ++r) {
-      double fct = M[r][col] / M[col][col];
-      for (int j = col; j < 5; ++j) M[r][j] -= fct * M[col][j];
+    if (!(best > 0.0) || !isfinite(best)) return false;
+#pragma unroll
+    for (int r = col + 1; r < NU; ++r) {
+      const bool sw = piv == r;
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        const double a = A[col][j], c = A[r][j];
+        A[col][j] = sw ? c : a;
+        A[r][j] = sw ? a : c;
+      }
+      const double a = b[col], c = b[r];
+      b[col] = sw ? c : a;
+      b[r] = sw ? a : c;
+    }
+#pragma unroll
+    for (int r = col + 1; r < NU; ++r) {
+      const double fct = A[r][col] / A[col][col];
+#pragma unroll
+      for (int j = col; j < NU; ++j) A[r][j] -= fct * A[col][j];
+      b[r] -= fct * b[col];
     }
   }
-  for (int i = nu - 1; i >= 0; --i) {
-    double acc = M[i][4];
-    for (int j = i + 1; j < nu; ++j) acc -= M[i][j] * x[j];
-    x[i] = acc / M[i][i];
+#pragma unroll
+  for (int i = NU - 1; i >= 0; --i) {
+    double acc = b[i];
+#pragma unroll
+    for (int j = i + 1; j < NU; ++j) acc -= A[i][j] * x[j];
+    x[i] = acc / A[i][i];
   }
   return true;
 }
 
-__device__ __forceinline__ double maxnorm(int nu, const double r[4]) {
+template <int NU>
+__device__ __forceinline__ double maxnorm(const double r[4]) {
   double m = 0.0;
-  for (int k = 0; k < nu; ++k) {
-    double a = fabs(r[k]);
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const double a = fabs(r[k]);
     m = (a <= m) ? m : a;  // propagates NaN
   }
   return m;
 }
 
 // Damped Newton: full step halved until the max-norm of the scaled residual
-// decreases; the table solve keeps iterates inside the table axes.
-__device__ inline bool newton(const EosDev& e, bool use_table, int mode, const double tgt[4], int nq,
-                              double x[4], int max_iter, int* iters) {
-  const int nu = nq > 0 ? 4 : 1;
+// decreases; the table solve keeps iterates inside the table axes.  Unknowns
+// (T, muB, muS, muQ), or T alone without charges.
+template <int NQ>
+__device__ inline bool newton(const EosDev& e, bool use_table, int mode, const double tgt[4], double x[4],
+                              int max_iter, int* iters) {
+  constexpr int NU = NQ > 0 ? 4 : 1;
   double r[4], J[4][4];
   inv_resid(e, use_table, mode, tgt, x, r, J);
-  double nr = maxnorm(nu, r);
+  double nr = maxnorm<NU>(r);
   int it = 0;
   for (; it < max_iter; ++it) {
     if (nr <= e.tol) break;
     double rhs[4] = {-r[0], -r[1], -r[2], -r[3]}, dx[4] = {0.0, 0.0, 0.0, 0.0};
-    if (!lsolve(nu, J, rhs, dx)) break;
+    if (!lsolve<NU>(J, rhs, dx)) break;
     double lam = 1.0, xt[4], rt[4], Jt[4][4], nrt = 0.0;
     bool acc = false;
     for (int hv = 0; hv < 40; ++hv) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) xt[k] = x[k] + (k < nu ? lam * dx[k] : 0.0);
+      for (int k = 0; k < 4; ++k) xt[k] = x[k] + (k < NU ? lam * dx[k] : 0.0);
       if (xt[0] <= 0.0) xt[0] = 0.5 * x[0];
       if (use_table) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) xt[k] = fmin(fmax(xt[k], e.lo[k]), e.hi[k]);
       }
       inv_resid(e, use_table, mode, tgt, xt, rt, Jt);
-      nrt = maxnorm(nu, rt);
+      nrt = maxnorm<NU>(rt);
       if (nrt < nr) {
         acc = true;
         break;
@@ -281,6 +300,7 @@ __device__ inline bool newton(const EosDev& e, bool use_table, int mode, const d
   *iters += it;
   return nr <= e.tol;
 }
+
 
 __device__ __forceinline__ bool in_axes(const EosDev& e, const double x[4]) {
   bool ok = true;
@@ -332,8 +352,8 @@ __device__ inline void thermo_fill(const EosDev& e, bool table, double T, const 
 // (from the warm start when given); if its root lies inside the table axes the
 // table interpolant is solved from that root and accepted when it converges
 // inside; otherwise the gas is the backup.  Conformal: closed form.
-__device__ inline void eos_invert(const EosDev& e, int mode, int nq, const double in[4], const double* warm,
-                                  Thermo& th) {
+template <int NQ>
+__device__ inline void eos_invert(const EosDev& e, int mode, const double in[4], const double* warm, Thermo& th) {
   th.iters = 0;
   th.in_table = 0;
   th.ok = 1;
@@ -344,21 +364,21 @@ __device__ inline void eos_invert(const EosDev& e, int mode, int nq, const doubl
     return;
   }
   const double ag = 19.0 * CCAKE_PI * CCAKE_PI / 36.0;
-  double tgt[4] = {in[0], nq > 0 ? in[1] : 0.0, nq > 0 ? in[2] : 0.0, nq > 0 ? in[3] : 0.0};
+  double tgt[4] = {in[0], NQ > 0 ? in[1] : 0.0, NQ > 0 ? in[2] : 0.0, NQ > 0 ? in[3] : 0.0};
   double x[4];
   if (warm && warm[0] > 0.0 && isfinite(warm[0]) && isfinite(warm[1]) && isfinite(warm[2]) && isfinite(warm[3])) {
     x[0] = warm[0];
-    x[1] = nq > 0 ? warm[1] : 0.0;
-    x[2] = nq > 0 ? warm[2] : 0.0;
-    x[3] = nq > 0 ? warm[3] : 0.0;
+    x[1] = NQ > 0 ? warm[1] : 0.0;
+    x[2] = NQ > 0 ? warm[2] : 0.0;
+    x[3] = NQ > 0 ? warm[3] : 0.0;
   } else {
     x[0] = mode == 0 ? cbrt(in[0] / (4.0 * ag)) : pow(in[0] / (3.0 * ag), 0.25);
     x[1] = x[2] = x[3] = 0.0;
   }
-  bool ok = newton(e, false, mode, tgt, nq, x, e.max_iter * 4, &th.iters);
+  bool ok = newton<NQ>(e, false, mode, tgt, x, e.max_iter * 4, &th.iters);
   if (e.kind == EOS_TABLE && ok && in_axes(e, x)) {
     double xt[4] = {x[0], x[1], x[2], x[3]};
-    bool okt = newton(e, true, mode, tgt, nq, xt, e.max_iter, &th.iters);
+    bool okt = newton<NQ>(e, true, mode, tgt, xt, e.max_iter, &th.iters);
     if (okt && in_axes(e, xt)) {
       thermo_fill(e, true, xt[0], xt + 1, th);
       th.in_table = 1;
@@ -368,5 +388,6 @@ __device__ inline void eos_invert(const EosDev& e, int mode, int nq, const doubl
   th.ok = ok ? 1 : 0;
   thermo_fill(e, false, x[0], x + 1, th);
 }
+
 
 }  // namespace ccake

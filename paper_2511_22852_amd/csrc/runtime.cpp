@@ -107,6 +107,8 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.recf = take(&o, sizeof(float) * NREC * cap);
   L.warm = take(&o, D8 * NWARM * cap);
   L.warms = take(&o, D8 * NWARM * cap);
+  L.dsum = take(&o, D8 * NDSUM * cap);
+  L.gsum = take(&o, D8 * NGSUM * cap);
   L.aux = take(&o, D8 * NAUXROW * cap);
   L.id = take(&o, I4 * cap);
   L.ids = take(&o, I4 * cap);
@@ -132,6 +134,8 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.recf = (float*)(base + L.recf);
   b.warm = (double*)(base + L.warm);
   b.warms = (double*)(base + L.warms);
+  b.dsum = (double*)(base + L.dsum);
+  b.gsum = (double*)(base + L.gsum);
   b.id = (int32_t*)(base + L.id);
   b.ids = (int32_t*)(base + L.ids);
   b.ev = (int32_t*)(base + L.ev);
@@ -300,9 +304,12 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
     delete s;
     return CCAKE_E_NOMEM;
   }
-  // slot -> event map: every slot belongs to event 0
+  // slot -> event map: every slot belongs to event 0; cell counts start at zero
+  // (the binning leaves them zero after every use)
   std::vector<int32_t> ev((size_t)n, 0);
   hipError_t he = hipMemcpy(s->b.ev, ev.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (ccap + 1));
+  if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) {
     ccake_destroy(s);
     return CCAKE_E_HIP;
@@ -323,6 +330,10 @@ static ccake_status write_event(ccake_sim* s, double t, double dt) {
   E.dt = dt;
   E.first_bad = INT32_MAX;
   E.edge = s->prm.cell_edge;
+  for (int k = 0; k < 3; ++k) {
+    E.bb_min[k] = BB_EMPTY_MIN;
+    E.bb_max[k] = BB_EMPTY_MAX;
+  }
   *s->h_evt = E;
   HIPCHK(s, hipMemcpyAsync(s->b.evt, s->h_evt, sizeof(EventDev), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -427,7 +438,7 @@ extern "C" ccake_status ccake_time(const ccake_sim* s, double* t) {
   return CCAKE_OK;
 }
 
-static const int PROF_MARKS = 7;  // 2 around the binning, 5 around the passes
+static const int PROF_MARKS = 12;  // 2 around the binning, 5 around each stage's kernels
 
 static ccake_status enqueue_step(ccake_sim* s, const hipEvent_t* marks) {
   HIPCHK(s, launch_reset_stage_counters(s->b, s->stream));
@@ -442,18 +453,19 @@ static ccake_status collect_profile(ccake_sim* s, int nsteps) {
   HIPCHK(s, hipStreamSynchronize(s->stream));
   for (int k = 0; k < nsteps; ++k) {
     const hipEvent_t* m = &s->prof_ev[(size_t)k * PROF_MARKS];
-    float a = 0.f, b1 = 0.f, b2 = 0.f, c1 = 0.f, c2 = 0.f;
+    float a = 0.f;
     HIPCHK(s, hipEventElapsedTime(&a, m[0], m[1]));
-    HIPCHK(s, hipEventElapsedTime(&b1, m[2], m[3]));
-    HIPCHK(s, hipEventElapsedTime(&c1, m[3], m[4]));
-    HIPCHK(s, hipEventElapsedTime(&b2, m[4], m[5]));
-    HIPCHK(s, hipEventElapsedTime(&c2, m[5], m[6]));
     s->prof_ms[0] += a;
-    s->prof_ms[1] += (double)b1 + b2;
-    s->prof_ms[2] += (double)c1 + c2;
     s->prof_n[0] += 1;
-    s->prof_n[1] += 2;
-    s->prof_n[2] += 2;
+    for (int st = 0; st < 2; ++st) {
+      const hipEvent_t* q = m + 2 + 5 * st;
+      for (int g = 0; g < 4; ++g) {
+        float x = 0.f;
+        HIPCHK(s, hipEventElapsedTime(&x, q[g], q[g + 1]));
+        s->prof_ms[1 + g] += x;
+        s->prof_n[1 + g] += 1;
+      }
+    }
   }
   return CCAKE_OK;
 }
@@ -461,7 +473,7 @@ static ccake_status collect_profile(ccake_sim* s, int nsteps) {
 extern "C" ccake_status ccake_set_profiling(ccake_sim* s, int32_t enable) {
   if (!s) return CCAKE_E_ARG;
   s->prof = enable != 0;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < CCAKE_NPROF; ++k) {
     s->prof_ms[k] = 0.0;
     s->prof_n[k] = 0;
   }
@@ -470,7 +482,7 @@ extern "C" ccake_status ccake_set_profiling(ccake_sim* s, int32_t enable) {
 
 extern "C" ccake_status ccake_kernel_times(ccake_sim* s, double* ms, int64_t* launches) {
   if (!s || !ms || !launches) return CCAKE_E_ARG;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < CCAKE_NPROF; ++k) {
     ms[k] = s->prof_ms[k];
     launches[k] = s->prof_n[k];
   }

@@ -19,7 +19,7 @@ struct Handle {
 
 // byte offsets of the arrays of one batch inside its workspace
 struct Layout {
-  size_t Y0, Ys, Y1, th, rec, recf, warm, warms, aux, id, ids, ev, key, keys, perm, cs, cf, evt, scratch, total;
+  size_t Y0, Ys, Y1, th, rec, recf, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, cs, cf, evt, scratch, total;
 };
 
 ccake_status fail(Handle* h, ccake_status code, const char* fmt, ...);
@@ -56,6 +56,6 @@ struct ccake_sim : ccake::Handle {
   // kernel timing with HIP events on the simulation's stream (profiling mode)
   bool prof = false;
   std::vector<hipEvent_t> prof_ev;
-  double prof_ms[3] = {0.0, 0.0, 0.0};
-  int64_t prof_n[3] = {0, 0, 0};
+  double prof_ms[CCAKE_NPROF] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t prof_n[CCAKE_NPROF] = {0, 0, 0, 0, 0};
 };

@@ -166,6 +166,10 @@ static ccake_status admit_and_init(ccake_server* s, std::vector<std::pair<int, P
     E.dt = s->dt;
     E.first_bad = INT32_MAX;
     E.edge = s->prm.cell_edge;
+    for (int k = 0; k < 3; ++k) {
+      E.bb_min[k] = BB_EMPTY_MIN;
+      E.bb_max[k] = BB_EMPTY_MAX;
+    }
     if ((st = srv_hip(s, hipMemcpyAsync(s->b.evt + e, &E, sizeof E, hipMemcpyHostToDevice, s->stream), "event")))
       return st;
     std::vector<int32_t> ev((size_t)n, e);
@@ -352,6 +356,7 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
   s->b = bind_batch(s->arena, s->L, max_particles, s->ccap, max_events);
   (void)hipMemset(s->b.ev, 0xFF, sizeof(int32_t) * max_particles);
   (void)hipMemset(s->b.evt, 0, sizeof(EventDev) * max_events);
+  (void)hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (s->ccap + 1));
   (void)hipDeviceSynchronize();
   s->palloc.init(max_particles);
   s->calloc_.init(s->ccap + max_events);

@@ -1,0 +1,157 @@
+// Device helpers shared by the binning and stage kernels: the cubic-spline
+// kernel of the paper ("Kernel function"), the exact pair test, compensated
+// FP32 accumulation, and the neighbour block of a particle's cell.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace ccake {
+
+#ifndef CCAKE_PI
+#define CCAKE_PI 3.14159265358979323846
+#endif
+
+// W = sigma_d w(q), q = r/h: sigma_2 = 10/(7 pi h^2), sigma_3 = 1/(pi h^3)
+template <int D>
+__device__ __forceinline__ double sigma_d(double h) {
+  return D == 2 ? 10.0 / (7.0 * CCAKE_PI * h * h) : 1.0 / (CCAKE_PI * h * h * h);
+}
+
+// w(q) = 1 - 3/2 q^2 + 3/4 q^3 (q <= 1), (2 - q)^3 / 4 (1 < q <= 2), 0 beyond
+__device__ __forceinline__ double spline_w(double q) {
+  if (q <= 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+  if (q <= 2.0) {
+    double t = 2.0 - q;
+    return 0.25 * t * t * t;
+  }
+  return 0.0;
+}
+
+// w'(q) = -3 q + 9/4 q^2 (q <= 1), -3/4 (2 - q)^2 (1 < q <= 2), 0 beyond
+__device__ __forceinline__ double spline_dw(double q) {
+  if (q <= 1.0) return -3.0 * q + 2.25 * q * q;
+  if (q <= 2.0) {
+    double t = 2.0 - q;
+    return -0.75 * t * t;
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ float spline_wf(float q) {
+  if (q <= 1.0f) return 1.0f - 1.5f * q * q + 0.75f * q * q * q;
+  if (q <= 2.0f) {
+    float t = 2.0f - q;
+    return 0.25f * t * t * t;
+  }
+  return 0.0f;
+}
+
+__device__ __forceinline__ float spline_dwf(float q) {
+  if (q <= 1.0f) return -3.0f * q + 2.25f * q * q;
+  if (q <= 2.0f) {
+    float t = 2.0f - q;
+    return -0.75f * t * t;
+  }
+  return 0.0f;
+}
+
+// Compensated (Kahan) FP32 accumulator; value = s - c.
+struct Kahan {
+  float s, c;
+  __device__ __forceinline__ void add(float x) {
+    float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  // merge another compensated sum (TwoSum of the heads, compensations added)
+  __device__ __forceinline__ void merge(float s2, float c2) {
+    float t = s + s2;
+    float bp = t - s;
+    float err = (s - (t - bp)) + (s2 - bp);
+    c = c + c2 - err;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+// squared distance, accumulated axis by axis with separately rounded
+// products and sums (FMA contraction off) so that the pair relation is
+// reproducible bit for bit
+template <int D>
+__device__ __forceinline__ double dist2(const double xa[3], const double xb[3]) {
+#pragma clang fp contract(off)
+  double dx = xa[0] - xb[0];
+  double d2 = dx * dx;
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    double dk = xa[k] - xb[k];
+    d2 = d2 + dk * dk;
+  }
+  return d2;
+}
+
+__device__ __forceinline__ double row(const double* Y, int64_t cap, int r, int64_t i) {
+  return Y[(int64_t)r * cap + i];
+}
+
+__device__ __forceinline__ double metric_G3(const Params& prm, double t) { return prm.hyperbolic ? t * t : 1.0; }
+__device__ __forceinline__ double sqrt_g(const Params& prm, double t) { return prm.hyperbolic ? t : 1.0; }
+
+// Adds per-lane EoS counters to the event records with one atomic per wave
+// when all particles of the wave belong to one event (the common case).
+// Every lane of the wave must call it; lanes without a particle pass e = -1.
+__device__ inline void wave_count_eos(EventDev* evt, int e, uint32_t backup, uint32_t iters, uint32_t noconv) {
+  const unsigned long long m = __ballot(e >= 0);
+  if (m == 0) return;
+  const int src = __ffsll((unsigned long long)m) - 1;
+  const int e0 = __shfl(e, src, 64);
+  if (__all(e < 0 || e == e0)) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      backup += __shfl_xor(backup, off, 64);
+      iters += __shfl_xor(iters, off, 64);
+      noconv += __shfl_xor(noconv, off, 64);
+    }
+    if ((int)(threadIdx.x & 63) == src) {
+      if (backup) atomicAdd(&evt[e0].backup, backup);
+      if (iters) atomicAdd(&evt[e0].newton_iters, iters);
+      if (noconv) atomicAdd(&evt[e0].noconv, noconv);
+    }
+  } else if (e >= 0) {
+    if (backup) atomicAdd(&evt[e].backup, backup);
+    if (iters) atomicAdd(&evt[e].newton_iters, iters);
+    if (noconv) atomicAdd(&evt[e].noconv, noconv);
+  }
+}
+
+// neighbour block of a particle: 3^(D-1) contiguous slot ranges (x-rows of cells)
+template <int D>
+struct Block {
+  int32_t lo[D == 3 ? 9 : 3], hi[D == 3 ? 9 : 3];
+  int nr;
+};
+
+template <int D>
+__device__ __forceinline__ void neighbour_block(const BatchDev& b, const EventDev& E, int32_t key, Block<D>& blk) {
+  const int nx = E.nc[0], ny = E.nc[1], nz = D == 3 ? E.nc[2] : 1;
+  const int ix = key % nx;
+  const int iy = (key / nx) % ny;
+  const int iz = D == 3 ? key / (nx * ny) : 0;
+  const int x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < nx ? ix + 1 : nx - 1;
+  blk.nr = 0;
+  const int32_t* cs = b.cell_start + E.c_base;
+  for (int z = (D == 3 ? iz - 1 : 0); z <= (D == 3 ? iz + 1 : 0); ++z) {
+    if (z < 0 || z >= nz) continue;
+    for (int y = iy - 1; y <= iy + 1; ++y) {
+      if (y < 0 || y >= ny) continue;
+      const int c = (z * ny + y) * nx;
+      blk.lo[blk.nr] = cs[c + x0];
+      blk.hi[blk.nr] = cs[c + x1 + 1];
+      ++blk.nr;
+    }
+  }
+}
+
+}  // namespace ccake
