@@ -91,6 +91,70 @@ def run_gpu(B, I, w, eos, precision, steps, warmup):
                 backup=cnt.backup, newton_iters=cnt.newton_iters)
 
 
+def run_serving(B, I, eos, events, steps, precision, rate=None, max_particles=4_000_000, max_events=256):
+    """Continuous batching of the given events through the server.  rate None:
+    all submitted at once (capacity); otherwise Poisson arrivals at that rate
+    (events/s), submitted in real time.  Returns latencies and throughput."""
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, precision=precision, ncharge=3, h=events[0].h,
+                   eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02)
+    srv = B.Server(cfg, eos, budget_bytes=64 << 30, max_particles=max_particles, max_events=max_events,
+                   dt=events[0].dt)
+    arrivals = [0.0] * len(events) if rate is None else list(I.poisson_arrivals(len(events), rate))
+    results = []
+    start = time.perf_counter()
+    for w, ta in zip(events, arrivals):
+        delay = ta - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        srv.submit(w.t0, w.t0 + steps * w.dt, w.xi, w.u, w.dens_kind, w.dens, tag=len(results))
+        results += srv.poll(256)
+    srv.drain()
+    results += srv.poll(1024)
+    st = srv.stats()
+    srv.close()
+    bad = [r for r in results if r["status"] != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} served events failed (status {bad[0]['status']})")
+    lat = sorted(r["t_finish"] - r["t_submit"] for r in results)
+    first = min(r["t_submit"] for r in results)
+    last = max(r["t_finish"] for r in results)
+    span = last - first
+    import numpy as np
+    return dict(events=len(results), makespan_s=span, events_per_s=len(results) / span,
+                particle_steps_per_s=st["particle_steps"] / span,
+                p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
+                mean_resident_particles=st["particle_steps"] / max(st["steps"], 1))
+
+
+def run_sequential(B, eos, events, steps, precision, arrivals):
+    """One event at a time through a single simulation each (the same kernels,
+    HIP graph replay); latencies from replaying the arrival trace through a
+    first-in-first-out single server with the measured service times."""
+    import numpy as np
+    import torch
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, precision=precision, ncharge=3, h=events[0].h,
+                   eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02)
+    service = []
+    for w in events:
+        sim = B.Sim(cfg, eos, w.n)
+        sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(w.dt, steps)
+        sim.synchronize()
+        service.append(time.perf_counter() - t0)
+        sim.check()
+        sim.close()
+    finish, lat = 0.0, []
+    for ta, sv in zip(arrivals, service):
+        finish = max(finish, ta) + sv
+        lat.append(finish - ta)
+    lat.sort()
+    return dict(events=len(events), busy_s=sum(service), events_per_s=len(events) / sum(service),
+                particle_steps_per_s=sum(w.n for w in events) * steps / sum(service),
+                p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)))
+
+
 def cpu_baseline_run(I, w, min_seconds):
     """The FP64 oracle on the same event, Heun steps from the initial state
     until at least min_seconds of wall time; OpenMP over particles."""
@@ -123,6 +187,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-events", type=int, default=256, help="serving load: events (0 = skip)")
+    ap.add_argument("--serve-steps", type=int, default=200, help="Heun steps per served event")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
@@ -188,6 +254,29 @@ def main():
         "eos_backup_fraction_last_stage": head["backup"] / w.n,
         "roofline": roof,
     }
+    if args.serve_events > 0:
+        specs = I.serving_events(args.serve_events)
+        events = [I.serving_event(s) for s in specs]
+        cap = run_serving(B, I, eos, events, args.serve_steps, B.MIXED)
+        rate = 0.7 * cap["events_per_s"]
+        load = run_serving(B, I, eos, events, args.serve_steps, B.MIXED, rate=rate)
+        arrivals = list(I.poisson_arrivals(len(events), rate))
+        seq = run_sequential(B, eos, events, args.serve_steps, B.FP64, arrivals)
+        out["serving"] = {
+            "workload": f"{len(events)} lumpy viscous BSQ events, N ~ U[5000, 80000] (total "
+                        f"{sum(e.n for e in events)} particles), {args.serve_steps} Heun steps each, mixed precision",
+            "capacity_events_per_s": cap["events_per_s"],
+            "capacity_particle_steps_per_s": cap["particle_steps_per_s"],
+            "poisson_rate_events_per_s": rate,
+            "events_per_s": load["events_per_s"],
+            "particle_steps_per_s": load["particle_steps_per_s"],
+            "p50_latency_s": load["p50_latency_s"],
+            "p99_latency_s": load["p99_latency_s"],
+            "mean_resident_particles": load["mean_resident_particles"],
+            "fp64_sequential": seq,
+        }
+        print(f"[bench] serving: capacity {cap['events_per_s']:.1f} ev/s, p99 {load['p99_latency_s']:.3f} s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_run(I, w, args.cpu_seconds)
     print(json.dumps(out))

@@ -330,3 +330,31 @@ def test_rejects_bad_input(B, O):
     with pytest.raises(B.CcakeError) as e:
         sim.step(1.0, 1)  # dt larger than the binning skin allows
     assert e.value.status == B.E_ARG
+
+
+def test_viscous_gubser_trajectory_fp64(B, O):
+    """Viscous Gubser initial state (full shear tensor), 100 Heun steps:
+    GPU == oracle to 1e-9; the oracle itself is pinned to the semi-analytic
+    solution in the CPU suite."""
+    from test_oracle_physics import ETAS_G, FSTAR, viscous_gubser_solution, viscous_gubser_state
+    sol = viscous_gubser_solution((10.0 / I.HBARC / FSTAR) ** 0.25)
+    w = I.gubser_workload(t_end=1.5)
+    e, ux, uy, pi = viscous_gubser_state(sol, 1.0, w.xi[0], w.xi[1])
+    dens = np.zeros((4, w.n))
+    dens[0] = e
+    prm = O.params(dim=2, hyperbolic=True, viscous=True, ncharge=0, h=w.h, eta_over_s=ETAS_G, zeta_peak=0.0,
+                   use_cells=1)
+    oe = O.eos_conformal(FSTAR)
+    y = O.init(prm, oe, 1.0, w.xi, np.stack([ux, uy]), 1, dens)
+    _, aux, _ = O.rhs(prm, oe, 1.0, y)
+    sigma = aux[O.A_SIGSTAR] / aux[O.A_GAMMA]
+    for row, p in zip((O.V_P11, O.V_P12, O.V_P22, O.V_P33), pi):
+        y[row] = p / sigma
+    _, yo, _ = O.evolve(prm, oe, 1.0, w.dt, w.nsteps, y)
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=0, h=w.h, eta_over_s=ETAS_G, zeta_peak=0.0)
+    sim = sim_from_state(B, cfg, B.Eos.conformal(FSTAR), y, 1.0)
+    sim.step(w.dt, w.nsteps)
+    sim.check()
+    yg = sim.get_state()
+    for r in (O.V_X1, O.V_U1, O.V_U2, O.V_S, O.V_P11, O.V_P12, O.V_P22, O.V_P33):
+        assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))

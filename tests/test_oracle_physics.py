@@ -13,6 +13,7 @@ mathematics fix independently of it:
   pressure forces summing to zero, and energy / momentum drift of second
   order in dt (the paper attributes energy loss to the integrator).
 """
+import functools
 import math
 
 import numpy as np
@@ -176,3 +177,85 @@ def test_cartesian_conservation_smoothed_density(oracle_mod):
         res.append(abs(dE))
     assert res[0] < 0.02
     assert res[1] < 0.5 * res[0]
+
+
+# ---------------------------------------------------------------------------
+# Viscous Gubser flow (conformal, shear only).  In the Weyl-rescaled frame the
+# minimal Israel-Stewart equations reduce to ODEs in rho (the paper's
+# eq. EoS2-evol at zero chemical potential, written here in the mostly-minus
+# convention: pibar = pi^eta_eta / w, which is minus the paper's pibar, and
+# eta/(tau_pi w) = 1/5 for tau_pi = 5 eta / w):
+#   dThat/drho  = That (-pibar - 2)/3 tanh(rho)
+#   dpibar/drho = -pibar/tauhat - (4/15) tanh(rho) + (4/3) pibar^2 tanh(rho),
+#   tauhat = 5 (eta/s) / That.
+# The Milne-frame state follows from T = That/tau, the ideal Gubser flow, and
+# the tensor structure pi^eta_eta = pibar w, pi^theta_theta = pi^phi_phi =
+# -pibar w / 2 with pi orthogonal to u.
+# ---------------------------------------------------------------------------
+FSTAR, ETAS_G = 11.0, 0.2
+
+
+@functools.lru_cache(maxsize=4)
+def viscous_gubser_solution(That0, rho_min=-5.0, rho_max=2.5):
+    from scipy.optimize import brentq
+
+    def ode(rho, Y):
+        That, pib = Y
+        th = math.tanh(rho)
+        return [That * (-pib - 2) / 3 * th, -pib * That / (5 * ETAS_G) - 4 / 15 * th + 4 / 3 * pib * pib * th]
+
+    def miss(lT):
+        s = solve_ivp(ode, (rho_min, 0.0), [math.exp(lT), 0.0], rtol=1e-10, atol=1e-12)
+        return math.log(s.y[0, -1]) - math.log(That0)
+
+    lT = brentq(miss, math.log(That0) - 8, math.log(That0) + 1, xtol=1e-12)
+    return solve_ivp(ode, (rho_min, rho_max), [math.exp(lT), 0.0], rtol=1e-10, atol=1e-12, dense_output=True).sol
+
+
+def viscous_gubser_state(sol, tau, x, y, q=1.0):
+    r = np.hypot(x, y)
+    rho = np.arcsinh((q * q * (tau * tau - r * r) - 1.0) / (2 * q * tau))
+    That, pib = sol(rho)
+    e = FSTAR * (That / tau) ** 4
+    w = 4 * e / 3
+    den = np.sqrt(1 + 2 * q * q * (tau * tau + r * r) + q ** 4 * (tau * tau - r * r) ** 2)
+    ut = (1 + q * q * (tau * tau + r * r)) / den
+    ur = 2 * q * q * r * tau / den
+    c = np.where(r > 0, x / np.where(r > 0, r, 1), 1.0)
+    s = np.where(r > 0, y / np.where(r > 0, r, 1), 0.0)
+    lam = pib * w / 2
+    pi = (lam * (ut ** 2 * c ** 2 + s ** 2), lam * (ut ** 2 - 1) * c * s, lam * (ut ** 2 * s ** 2 + c ** 2),
+          -pib * w / tau ** 2)
+    return e, ur * c, ur * s, pi
+
+
+def viscous_gubser_errors(O, n_side, spacing, h, t_end):
+    sol = viscous_gubser_solution((10.0 / HBARC / FSTAR) ** 0.25)
+    w = I.gubser_workload(n_side=n_side, spacing=spacing, h=h, t_end=t_end)
+    e, ux, uy, pi = viscous_gubser_state(sol, 1.0, w.xi[0], w.xi[1])
+    dens = np.zeros((4, w.n))
+    dens[0] = e
+    prm = O.params(dim=2, hyperbolic=True, viscous=True, ncharge=0, h=h, eta_over_s=ETAS_G, zeta_peak=0.0,
+                   use_cells=1)
+    eos = O.eos_conformal(FSTAR)
+    y = O.init(prm, eos, 1.0, w.xi, np.stack([ux, uy]), 1, dens)
+    _, aux, _ = O.rhs(prm, eos, 1.0, y)
+    sigma = aux[O.A_SIGSTAR] / aux[O.A_GAMMA]
+    for row, p in zip((O.V_P11, O.V_P12, O.V_P22, O.V_P33), pi):
+        y[row] = p / sigma
+    t, yf, _ = O.evolve(prm, eos, 1.0, w.dt, w.nsteps, y)
+    _, auxf, _ = O.rhs(prm, eos, t, yf)
+    e_ex, _, _, pi_ex = viscous_gubser_state(sol, t, yf[0], yf[1])
+    m = np.hypot(yf[0], yf[1]) < 3.0
+    sig = auxf[O.A_SIGSTAR] / (auxf[O.A_GAMMA] * t)
+    l2 = lambda a, b: np.linalg.norm((a - b)[m]) / np.linalg.norm(b[m])
+    return (l2(auxf[O.A_E], e_ex), l2(sig * yf[O.V_P33], pi_ex[3]), l2(sig * yf[O.V_P12], pi_ex[1]))
+
+
+def test_viscous_gubser(oracle_mod):
+    """Shear relaxation with transverse flow, the Milne Christoffel terms and
+    the viscous momentum coupling against the viscous Gubser solution."""
+    e1, pe1, pxy1 = viscous_gubser_errors(oracle_mod, 51, 0.2, 0.3, 1.5)
+    assert e1 < 0.04 and pe1 < 0.04 and pxy1 < 0.08
+    e2, pe2, pxy2 = viscous_gubser_errors(oracle_mod, 101, 0.1, 0.15, 1.5)
+    assert e2 < 0.5 * e1 and pe2 < 0.5 * pe1 and pxy2 < 0.5 * pxy1
