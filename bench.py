@@ -35,6 +35,42 @@ METRIC = "SPH particle-steps/s (FP64 vs FP32-Kahan) + p50/p99 event latency, 1 G
 
 GROUPS = ["binning", "density_sums", "eos_inversion", "gradient_sums", "eom_update"]
 
+# sources that the stage kernels are compiled from; the measured HBM traffic of
+# a kernel is reported only while these are unchanged since the counters were read
+KERNEL_SOURCES = ["common.h", "sph_device.h", "eos_device.h", "eom_device.h", "stage.hip"]
+TRAFFIC_FILES = {"eos_inversion": "eos_inversion_lumpy2d_40k_traffic.txt"}
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_22852_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(group):
+    """HBM bytes per launch of the group's kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each divided by what the
+    counter reads per byte of a plain device copy), or None when there is none
+    or the kernel sources changed since."""
+    name = TRAFFIC_FILES.get(group)
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != kernel_source_digest():
+        return None
+    fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 / float(kv["copy_fetch_factor"])
+    write = float(kv["write_kib_per_dispatch"]) * 1024 / float(kv["copy_write_factor"])
+    return fetch + write
+
 
 def algorithmic_model(dim, viscous, ncharge, mixed, smoothed=True):
     """Per kernel of one Heun stage: compulsory HBM bytes per particle (each
@@ -180,6 +216,19 @@ def cpu_baseline_run(I, w, min_seconds):
                        f"state in {el:.1f} s (uniform-grid neighbour search, OpenMP over particles)")
 
 
+def copy_calibration(mib):
+    """One device-to-device copy of a known size: the HBM byte counters of this
+    dispatch (read mib MiB, write mib MiB) calibrate those of the SPH kernels."""
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,11 +238,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-events", type=int, default=256, help="serving load: events (0 = skip)")
     ap.add_argument("--serve-steps", type=int, default=200, help="Heun steps per served event")
+    ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both",
+                    help="which precisions to run (counter-collection passes use one)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (reference kernel for the HBM "
+                         "byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
               "note, not a measured path.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     from paper_2511_22852_amd import binding as B
     from paper_2511_22852_amd import inputs as I
@@ -203,8 +260,13 @@ def main():
     eos = B.Eos.table(cols, lo, hi)
     res = {}
     for name, prec in (("fp64", B.FP64), ("mixed", B.MIXED)):
+        if args.precision not in ("both", name):
+            continue
         res[name] = run_gpu(B, I, w, eos, prec, args.steps, args.warmup)
         print(f"[bench] {name}: {args.steps} steps in {res[name]['elapsed']:.3f} s", file=sys.stderr, flush=True)
+    if args.precision != "both":
+        print(json.dumps({k: dict(ms_per_step=v["elapsed"] / args.steps * 1e3) for k, v in res.items()}))
+        return
 
     head = res["mixed"]
     value = w.n * args.steps / head["elapsed"]
@@ -224,7 +286,7 @@ def main():
     else:
         roof = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(names[k])
     roof["kernel"] = names[k]
     roof["avg_launch_us"] = avg_s * 1e6
     roof["algorithmic_bytes_per_launch"] = nbytes

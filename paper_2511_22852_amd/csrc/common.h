@@ -55,7 +55,7 @@ struct EosDev {
   int32_t kind;
   int32_t n[4];
   int32_t max_iter;
-  double lo[4], hi[4], d[4];
+  double lo[4], hi[4], d[4], inv_d[4];  // axis origin, end, spacing, 1/spacing
   double fstar;
   double tol;
   const double* tab;  // node-major [nT][nB][nS][nQ][8]

@@ -70,84 +70,97 @@ __device__ inline void gas_eval(double T, const double mu[3], double* p, double 
   }
 }
 
-__device__ __forceinline__ void tab_locate(const EosDev& e, const double x[4], int i0[4], double f[4]) {
+// Cell of x and its fractional position; node0 is the node index of the
+// lower corner.  The cell index is clamped so that extrapolation off the axes
+// uses the boundary cell.
+__device__ __forceinline__ int64_t tab_locate(const EosDev& e, const double x[4], double f[4]) {
+  int64_t node = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double u = (x[k] - e.lo[k]) / e.d[k];
+    const double u = (x[k] - e.lo[k]) / e.d[k];
     int i = (int)floor(u);
     i = i < 0 ? 0 : (i > e.n[k] - 2 ? e.n[k] - 2 : i);
-    i0[k] = i;
     f[k] = u - (double)i;
+    node = node * e.n[k] + i;
   }
+  return node;
 }
 
-// Quadrilinear interpolant of the four Newton columns (and optionally p/T^4)
-// with its gradient in (T, mu).  Returns values v[0..3] = (s, nB, nS, nQ)/T^3
-// and v[4] = p/T^4 when want_p.
-__device__ inline void tab_interp(const EosDev& e, const double x[4], double v[5], double g[5][4], bool want_p) {
-  int i0[4];
+// Quadrilinear interpolant of NC consecutive columns starting at column C0,
+// and with GRAD its gradient in (T, mu).  The 16 corner loads are issued
+// together and the multilinear form is evaluated axis by axis (last axis
+// first), carrying the partial derivatives of the already-contracted axes:
+// the same polynomial as the sum over corners of weight products, with about
+// a third of the arithmetic.
+template <int C0, int NC, bool GRAD>
+__device__ inline void tab_interp(const EosDev& e, const double x[4], double v[NC], double g[NC][4]) {
   double f[4];
-  tab_locate(e, x, i0, f);
+  const int64_t node0 = tab_locate(e, x, f);
+  const int64_t s2 = e.n[3], s1 = (int64_t)e.n[2] * s2, s0 = (int64_t)e.n[1] * s1;
+  // axis 3: lerp the pairs (b3 = 0, 1), which are adjacent nodes
+  double a[8][NC], a3[8][NC];
 #pragma unroll
-  for (int c = 0; c < 5; ++c) {
-    v[c] = 0.0;
+  for (int m = 0; m < 8; ++m) {
+    const int64_t node = node0 + ((m >> 2) & 1) * s0 + ((m >> 1) & 1) * s1 + (m & 1) * s2;
+    const double* p0 = e.tab + node * TC_STRIDE + C0;
+    const double* p1 = p0 + TC_STRIDE;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) g[c][k] = 0.0;
+    for (int c = 0; c < NC; ++c) {
+      const double lo = p0[c], hi = p1[c];
+      a3[m][c] = hi - lo;
+      a[m][c] = lo + f[3] * a3[m][c];
+    }
   }
-  const int n1 = e.n[1], n2 = e.n[2], n3 = e.n[3];
-  for (int corner = 0; corner < 16; ++corner) {
-    const int b0 = (corner >> 3) & 1, b1 = (corner >> 2) & 1, b2 = (corner >> 1) & 1, b3 = corner & 1;
-    const int64_t node = (((int64_t)(i0[0] + b0) * n1 + (i0[1] + b1)) * n2 + (i0[2] + b2)) * n3 + (i0[3] + b3);
-    const double* base = e.tab + node * TC_STRIDE;
-    const double4 sv = *reinterpret_cast<const double4*>(base);
-    const double pv = want_p ? base[TC_P] : 0.0;
-    const double w0 = b0 ? f[0] : 1.0 - f[0], w1 = b1 ? f[1] : 1.0 - f[1];
-    const double w2 = b2 ? f[2] : 1.0 - f[2], w3 = b3 ? f[3] : 1.0 - f[3];
-    const double s0 = (b0 ? 1.0 : -1.0) / e.d[0], s1 = (b1 ? 1.0 : -1.0) / e.d[1];
-    const double s2 = (b2 ? 1.0 : -1.0) / e.d[2], s3 = (b3 ? 1.0 : -1.0) / e.d[3];
-    const double w = w0 * w1 * w2 * w3;
-    const double dw[4] = {s0 * w1 * w2 * w3, w0 * s1 * w2 * w3, w0 * w1 * s2 * w3, w0 * w1 * w2 * s3};
-    const double cv[5] = {sv.x, sv.y, sv.z, sv.w, pv};
+  // axis 2
+  double b[4][NC], b3[4][NC], b2[4][NC];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      v[c] += w * cv[c];
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) g[c][k] += dw[k] * cv[c];
+    for (int c = 0; c < NC; ++c) {
+      b2[q][c] = a[2 * q + 1][c] - a[2 * q][c];
+      b[q][c] = a[2 * q][c] + f[2] * b2[q][c];
+      if (GRAD) b3[q][c] = a3[2 * q][c] + f[2] * (a3[2 * q + 1][c] - a3[2 * q][c]);
+    }
+  // axis 1
+  double c0v[2][NC], c3[2][NC], c2[2][NC], c1[2][NC];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      c1[r][c] = b[2 * r + 1][c] - b[2 * r][c];
+      c0v[r][c] = b[2 * r][c] + f[1] * c1[r][c];
+      if (GRAD) {
+        c3[r][c] = b3[2 * r][c] + f[1] * (b3[2 * r + 1][c] - b3[2 * r][c]);
+        c2[r][c] = b2[2 * r][c] + f[1] * (b2[2 * r + 1][c] - b2[2 * r][c]);
+      }
+    }
+  // axis 0
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double d0 = c0v[1][c] - c0v[0][c];
+    v[c] = c0v[0][c] + f[0] * d0;
+    if (GRAD) {
+      g[c][0] = d0 * e.inv_d[0];
+      g[c][1] = (c1[0][c] + f[0] * (c1[1][c] - c1[0][c])) * e.inv_d[1];
+      g[c][2] = (c2[0][c] + f[0] * (c2[1][c] - c2[0][c])) * e.inv_d[2];
+      g[c][3] = (c3[0][c] + f[0] * (c3[1][c] - c3[0][c])) * e.inv_d[3];
     }
   }
 }
 
-// scalar columns (p/T^4, cs2, kappa) at x
-__device__ inline void tab_scalars(const EosDev& e, const double x[4], double* ip, double* cs2, double* kap) {
-  int i0[4];
-  double f[4];
-  tab_locate(e, x, i0, f);
-  double a = 0.0, b = 0.0, c = 0.0;
-  const int n1 = e.n[1], n2 = e.n[2], n3 = e.n[3];
-  for (int corner = 0; corner < 16; ++corner) {
-    const int b0 = (corner >> 3) & 1, b1 = (corner >> 2) & 1, b2 = (corner >> 1) & 1, b3 = corner & 1;
-    const int64_t node = (((int64_t)(i0[0] + b0) * n1 + (i0[1] + b1)) * n2 + (i0[2] + b2)) * n3 + (i0[3] + b3);
-    const double* base = e.tab + node * TC_STRIDE;
-    const double w = (b0 ? f[0] : 1.0 - f[0]) * (b1 ? f[1] : 1.0 - f[1]) * (b2 ? f[2] : 1.0 - f[2]) *
-                     (b3 ? f[3] : 1.0 - f[3]);
-    a += w * base[TC_P];
-    b += w * base[TC_CS2];
-    c += w * base[TC_KAP];
-  }
-  *ip = a;
-  *cs2 = b;
-  *kap = c;
-}
-
-// Scaled residual of the inversion.  mode 0: (s, n) targets scaled by s0;
-// mode 1: e scaled by e0, n scaled by e0^(3/4).
+// Scaled residual of the inversion and its Jacobian; sn receives (s, n) at x.
+// mode 0: (s, n) targets scaled by s0; mode 1: e scaled by e0, n scaled by
+// e0^(3/4).
 __device__ inline void inv_resid(const EosDev& e, bool use_table, int mode, const double tgt[4],
-                                 const double x[4], double r[4], double J[4][4]) {
-  double sn[4], Jsn[4][4], p = 0.0, gp[4] = {0.0, 0.0, 0.0, 0.0};
+                                 const double x[4], double r[4], double J[4][4], double sn[4]) {
+  double Jsn[4][4], p = 0.0, gp[4] = {0.0, 0.0, 0.0, 0.0};
   const double T = x[0];
   if (use_table) {
     double v[5], g[5][4];
-    tab_interp(e, x, v, g, mode == 1);
+    if (mode == 1)
+      tab_interp<0, 5, true>(e, x, v, g);
+    else
+      tab_interp<0, 4, true>(e, x, v, g);
     const double T2 = T * T, T3 = T2 * T;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -225,9 +238,10 @@ __device__ inline bool lsolve(double A[4][4], double b[4], double x[4]) {
       b[col] = sw ? c : a;
       b[r] = sw ? a : c;
     }
+    const double ip = 1.0 / A[col][col];
 #pragma unroll
     for (int r = col + 1; r < NU; ++r) {
-      const double fct = A[r][col] / A[col][col];
+      const double fct = A[r][col] * ip;
 #pragma unroll
       for (int j = col; j < NU; ++j) A[r][j] -= fct * A[col][j];
       b[r] -= fct * b[col];
@@ -259,17 +273,17 @@ __device__ __forceinline__ double maxnorm(const double r[4]) {
 // (T, muB, muS, muQ), or T alone without charges.
 template <int NQ>
 __device__ inline bool newton(const EosDev& e, bool use_table, int mode, const double tgt[4], double x[4],
-                              int max_iter, int* iters) {
+                              int max_iter, int* iters, double sn[4]) {
   constexpr int NU = NQ > 0 ? 4 : 1;
   double r[4], J[4][4];
-  inv_resid(e, use_table, mode, tgt, x, r, J);
+  inv_resid(e, use_table, mode, tgt, x, r, J, sn);
   double nr = maxnorm<NU>(r);
   int it = 0;
   for (; it < max_iter; ++it) {
     if (nr <= e.tol) break;
     double rhs[4] = {-r[0], -r[1], -r[2], -r[3]}, dx[4] = {0.0, 0.0, 0.0, 0.0};
     if (!lsolve<NU>(J, rhs, dx)) break;
-    double lam = 1.0, xt[4], rt[4], Jt[4][4], nrt = 0.0;
+    double lam = 1.0, xt[4], rt[4], Jt[4][4], snt[4], nrt = 0.0;
     bool acc = false;
     for (int hv = 0; hv < 40; ++hv) {
 #pragma unroll
@@ -279,7 +293,7 @@ __device__ inline bool newton(const EosDev& e, bool use_table, int mode, const d
 #pragma unroll
         for (int k = 0; k < 4; ++k) xt[k] = fmin(fmax(xt[k], e.lo[k]), e.hi[k]);
       }
-      inv_resid(e, use_table, mode, tgt, xt, rt, Jt);
+      inv_resid(e, use_table, mode, tgt, xt, rt, Jt, snt);
       nrt = maxnorm<NU>(rt);
       if (nrt < nr) {
         acc = true;
@@ -292,6 +306,7 @@ __device__ inline bool newton(const EosDev& e, bool use_table, int mode, const d
     for (int k = 0; k < 4; ++k) {
       x[k] = xt[k];
       r[k] = rt[k];
+      sn[k] = snt[k];
 #pragma unroll
       for (int j = 0; j < 4; ++j) J[k][j] = Jt[k][j];
     }
@@ -309,7 +324,11 @@ __device__ __forceinline__ bool in_axes(const EosDev& e, const double x[4]) {
   return ok;
 }
 
-__device__ inline void thermo_fill(const EosDev& e, bool table, double T, const double mu[3], Thermo& th) {
+// Thermodynamics at (T, mu).  For the table, sn_tab may carry (s, n) at this
+// point from the solve (the interpolant's values there); the remaining
+// columns are interpolated.
+__device__ inline void thermo_fill(const EosDev& e, bool table, double T, const double mu[3], Thermo& th,
+                                   const double* sn_tab = nullptr) {
   th.T = T;
   if (e.kind == EOS_CONFORMAL) {
     th.mu[0] = th.mu[1] = th.mu[2] = 0.0;
@@ -325,17 +344,24 @@ __device__ inline void thermo_fill(const EosDev& e, bool table, double T, const 
   for (int q = 0; q < 3; ++q) th.mu[q] = mu[q];
   if (table) {
     const double x[4] = {T, mu[0], mu[1], mu[2]};
-    double v[5], g[5][4], ip, cs2, kap;
-    tab_interp(e, x, v, g, false);
-    tab_scalars(e, x, &ip, &cs2, &kap);
     const double T3 = T * T * T;
-    th.s = T3 * v[0];
+    if (sn_tab) {
+      th.s = sn_tab[0];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) th.n[q] = T3 * v[1 + q];
-    th.p = T3 * T * ip;
+      for (int q = 0; q < 3; ++q) th.n[q] = sn_tab[1 + q];
+    } else {
+      double v[4];
+      tab_interp<TC_S, 4, false>(e, x, v, nullptr);
+      th.s = T3 * v[0];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) th.n[q] = T3 * v[1 + q];
+    }
+    double w[3];
+    tab_interp<TC_P, 3, false>(e, x, w, nullptr);
+    th.p = T3 * T * w[0];
     th.e = T * th.s + mu[0] * th.n[0] + mu[1] * th.n[1] + mu[2] * th.n[2] - th.p;
-    th.cs2 = cs2;
-    th.kappa = kap;
+    th.cs2 = w[1];
+    th.kappa = w[2];
     return;
   }
   double sn[4];
@@ -375,12 +401,13 @@ __device__ inline void eos_invert(const EosDev& e, int mode, const double in[4],
     x[0] = mode == 0 ? cbrt(in[0] / (4.0 * ag)) : pow(in[0] / (3.0 * ag), 0.25);
     x[1] = x[2] = x[3] = 0.0;
   }
-  bool ok = newton<NQ>(e, false, mode, tgt, x, e.max_iter * 4, &th.iters);
+  double sn[4];
+  bool ok = newton<NQ>(e, false, mode, tgt, x, e.max_iter * 4, &th.iters, sn);
   if (e.kind == EOS_TABLE && ok && in_axes(e, x)) {
     double xt[4] = {x[0], x[1], x[2], x[3]};
-    bool okt = newton<NQ>(e, true, mode, tgt, xt, e.max_iter, &th.iters);
+    bool okt = newton<NQ>(e, true, mode, tgt, xt, e.max_iter, &th.iters, sn);
     if (okt && in_axes(e, xt)) {
-      thermo_fill(e, true, xt[0], xt + 1, th);
+      thermo_fill(e, true, xt[0], xt + 1, th, sn);
       th.in_table = 1;
       return;
     }

@@ -239,6 +239,7 @@ extern "C" ccake_status ccake_eos_create_table(ccake_eos** out, const int32_t n[
     e->dev.lo[k] = lo[k];
     e->dev.hi[k] = hi[k];
     e->dev.d[k] = (hi[k] - lo[k]) / (double)(n[k] - 1);
+    e->dev.inv_d[k] = 1.0 / e->dev.d[k];
   }
   e->dev.tab = e->d_tab;
   return CCAKE_OK;
