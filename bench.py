@@ -75,8 +75,13 @@ def measured_traffic(group):
 def algorithmic_model(dim, viscous, ncharge, mixed, smoothed=True):
     """Per kernel of one Heun stage: compulsory HBM bytes per particle (each
     array the kernel must touch, read or written once; neighbour data reused
-    on chip is not counted) and flops per accepted neighbour pair.  The
-    derivation is in DESIGN.md."""
+    on chip is not counted) and flops per accepted neighbour pair.  Bytes:
+    density sums read positions (and S, N for smoothed densities) and the
+    cell index, and write the six sums; the EoS pass reads the sums, the state
+    it needs and the warm start, and writes thermodynamics, the neighbour
+    record and the new warm start; the gradient pass reads positions, the
+    record and sigma*, and writes its sums; the update reads the sums, the
+    thermodynamics and two state copies and writes one."""
     nP = (6 if dim == 3 else 4) if viscous else 0
     state = 2 * dim + 1 + ncharge + (1 + nP if viscous else 0)
     rec = 1 + (dim * dim if viscous else 0) + 2 * dim

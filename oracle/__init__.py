@@ -57,7 +57,35 @@ class Params(ctypes.Structure):
         ("tauPi_ratio", ctypes.c_double), ("c_PiPi", ctypes.c_double),
         ("c_Pipi", ctypes.c_double), ("c_pipi", ctypes.c_double),
         ("c_piPi", ctypes.c_double),
+        ("nsrc", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("src", ctypes.c_void_p),
     ]
+
+
+class Source(ctypes.Structure):
+    """External source (eq. conservation_source): normalised Gaussian of the
+    given widths around a centre moving with velocity vel, active for
+    t_on <= x0 < t_off, depositing dp^mu/dx0 and dN_q/dx0."""
+    _fields_ = [
+        ("x0", ctypes.c_double * 3), ("vel", ctypes.c_double * 3), ("width", ctypes.c_double * 3),
+        ("t_on", ctypes.c_double), ("t_off", ctypes.c_double),
+        ("dpdt", ctypes.c_double * 4), ("dndt", ctypes.c_double * 3),
+    ]
+
+
+def sources(specs):
+    """ctypes array of Source from dicts with keys x0, vel, width, t_on,
+    t_off, dpdt, dndt (missing vectors are zero)."""
+    arr = (Source * max(1, len(specs)))()
+    for k, sp in enumerate(specs):
+        S = arr[k]
+        for name, m in (("x0", 3), ("vel", 3), ("width", 3), ("dpdt", 4), ("dndt", 3)):
+            vals = list(sp.get(name, [0.0] * m)) + [0.0] * m
+            for i in range(m):
+                getattr(S, name)[i] = float(vals[i])
+        S.t_on = float(sp.get("t_on", -1e300))
+        S.t_off = float(sp.get("t_off", 1e300))
+    return arr
 
 
 class EosC(ctypes.Structure):
@@ -123,8 +151,13 @@ def _f64(a):
 def params(dim=2, hyperbolic=True, viscous=False, ncharge=0, h=0.3, eta_over_s=0.0,
            zeta_peak=0.0, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, taupi_coeff=5.0,
            tauPi_ratio=1.0, c_PiPi=1.0, c_Pipi=0.0, c_pipi=4.0 / 3.0, c_piPi=0.0,
-           use_cells=None, nthreads=0, density_mode=0) -> Params:
+           use_cells=None, nthreads=0, density_mode=0, source_specs=None) -> Params:
     p = Params()
+    if source_specs:
+        arr = sources(source_specs)
+        p.nsrc = len(source_specs)
+        p.src = ctypes.cast(arr, ctypes.c_void_p)
+        p._keep_sources = arr
     p.dim, p.hyperbolic, p.viscous, p.ncharge = dim, int(hyperbolic), int(viscous), ncharge
     p.use_cells = 0 if use_cells is None else int(use_cells)
     p.nthreads = nthreads

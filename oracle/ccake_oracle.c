@@ -28,8 +28,8 @@
  *   online EoS inverter + backup ....... "EoS inverter", backup-EoS chain
  *   modified conformal EoS ............. Appendix "Modified EoS to permit lower eps_min"
  *
- * Readings where the paper is silent or garbled are listed in the design doc and
- * restated at the point of use below.
+ * Readings where the paper is silent or garbled are restated at the point
+ * of use below.
  */
 #include <math.h>
 #include <stdint.h>
@@ -73,7 +73,27 @@ typedef struct {
   double c_Pipi;       /* lambda_Pipi / tau_Pi (minimal IS: 0)   */
   double c_pipi;       /* delta_pipi / tau_pi  (minimal IS: 4/3) */
   double c_piPi;       /* lambda_piPi / tau_pi (minimal IS: 0)   */
+  int32_t nsrc;        /* external sources (eq. conservation_source), 0 = isolated */
+  int32_t pad1;
+  const struct orc_source *src;
 } orc_params;
+
+/* One external source of energy-momentum and charge (eq. conservation_source;
+ * deposition smeared over the fluid as for the partons of the dynamical
+ * initialisation).  Reading: a normalised Gaussian of widths w_k in the
+ * particle coordinates (the third one is eta times 1 fm, as in the kernel
+ * distance) whose centre moves with constant coordinate velocity, active for
+ * t_on <= x0 < t_off.  The densities are
+ *     I^mu = (dp^mu/dx0) G / sqrt(-g),   I_q = (dN_q/dx0) G / sqrt(-g),
+ * so that the deposited totals per unit x0 are dp/dx0 and dN/dx0.  */
+typedef struct orc_source {
+  double x0[3];       /* centre at x0 = t_on */
+  double vel[3];      /* d centre / dx0 */
+  double width[3];    /* Gaussian widths */
+  double t_on, t_off;
+  double dpdt[4];     /* contravariant dp^mu/dx0 */
+  double dndt[3];     /* dN_q/dx0 */
+} orc_source;
 
 enum { EOS_CONFORMAL = 0, EOS_TABLE = 1, EOS_GAS = 2, EOS_MODCONF = 3 };
 
@@ -700,8 +720,14 @@ static void geom_at(int hyperbolic, double t, geom *m)
  *     gamma d(pi^ij/sigma)/dx0 = (1/sigma)[(2 eta sigma^ij - pi^ij)/tau_pi
  *         + (1 - c_pipi) pi^ij theta + c_piPi Pi sigma^ij
  *         - (u^i pi^{jl} + u^j pi^{il}) Du_l - u^l (Gam^i_lk pi^kj + Gam^j_lk pi^ik)]
- * Entropy (eq. dsdnrewr without sources / diffusion):
- *     gamma sigma T dS/dx0 = -Pi theta + pi:sigma.
+ * Entropy (eq. dsdnrewr, no diffusion):
+ *     gamma sigma T dS/dx0 = u.I - mu_q I_q - Pi theta + pi:sigma.
+ * External sources (eq. conservation_source): u.I adds to D eps (eq.
+ * e_conservation), the covariant spatial components of I^nu to the momentum
+ * balance, d/dx0 [M_i/(sigma gamma)] = -sqrt(-g) F_i + G_i I^i/(sigma gamma),
+ * and I_q to the charges (eq. charge_conservation), dN_q/dx0 = I_q/(gamma sigma).
+ * In Dp the source heats at fixed n: Dp gains (dp/de)_n u.I; the charge
+ * source's (dp/dn_q)_e I_q is taken as zero (reading; exact for p = eps/3).
  * ======================================================================== */
 typedef struct {
   int D, viscous;
@@ -714,11 +740,12 @@ typedef struct {
   double pi[4][4];   /* pi^{mu nu} */
   double P[4][4];    /* pi^{ij} / sigma (spatial) */
   double cPiPi, cPipi, cpipi, cpiPi;
+  double I[4], Iq[3], mu[3]; /* source densities I^mu, I_q; chemical potentials */
 } pctx;
 
 typedef struct {
   double R[4];
-  double dS, dB, dP[4][4], theta, pisig;
+  double dS, dB, dN[3], dP[4][4], theta, pisig;
 } pout;
 
 static void eom_eval(const pctx *c, const double a[4], pout *o)
@@ -761,7 +788,9 @@ static void eom_eval(const pctx *c, const double a[4], pout *o)
     for (int nu = 0; nu < 4; ++nu) pisig += c->pi[mu][nu] * m->g[mu] * m->g[nu] * sig[mu][nu];
   double DPi = 0.0;
   if (c->viscous) DPi = -(c->Pi + c->zeta * theta) / c->tauPi - c->cPiPi * c->Pi * theta + c->cPipi * pisig;
-  double Dp = -c->cs2 * c->w * theta + c->kappa * (-c->Pi * theta + pisig);
+  double uI = 0.0;
+  for (int mu = 0; mu < 4; ++mu) uI += m->g[mu] * u[mu] * c->I[mu];
+  double Dp = -c->cs2 * c->w * theta + c->kappa * (-c->Pi * theta + pisig + uI);
   memset(o->dP, 0, sizeof o->dP);
   if (c->viscous) {
     for (int i = 1; i < 4; ++i)
@@ -778,9 +807,11 @@ static void eom_eval(const pctx *c, const double a[4], pout *o)
   }
   o->theta = theta;
   o->pisig = pisig;
-  o->dS = c->viscous ? (-c->Pi * theta + pisig) / (gam * c->sigma * c->T) : 0.0;
+  double heat = uI - (c->mu[0] * c->Iq[0] + c->mu[1] * c->Iq[1] + c->mu[2] * c->Iq[2]);
+  o->dS = ((c->viscous ? -c->Pi * theta + pisig : 0.0) + heat) / (gam * c->sigma * c->T);
   o->dB = c->viscous ? (DPi + c->Pi * theta) / (gam * c->sigma) : 0.0;
-  double dwPs = (pisig + Dp + DPi) / (c->sigma * gam);
+  for (int q = 0; q < 3; ++q) o->dN[q] = c->Iq[q] / (gam * c->sigma);
+  double dwPs = (pisig + Dp + DPi + uI) / (c->sigma * gam);
   for (int i = 0; i < 4; ++i) o->R[i] = 0.0;
   for (int i = 1; i <= c->D; ++i) {
     double Qi = m->G[i] * u[i];
@@ -792,7 +823,8 @@ static void eom_eval(const pctx *c, const double a[4], pout *o)
     }
     double dX = m->Gdot[i] / (gam * gam) * sQP - 2.0 * m->G[i] / (gam * gam * gam) * dgam * sQP
               + m->G[i] / (gam * gam) * dsQP;
-    o->R[i] = (c->w + c->Pi) / c->sigma * dQ + Qi * dwPs + dX + m->sqrtg * c->F[i];
+    o->R[i] = (c->w + c->Pi) / c->sigma * dQ + Qi * dwPs + dX + m->sqrtg * c->F[i]
+            - m->G[i] * c->I[i] / (gam * c->sigma);
   }
 }
 
@@ -809,6 +841,26 @@ typedef struct {
   double A_over_s2[4][4];   /* (pi^{ji} - v^j pi^{0i})/sigma*^2, [j][i] */
   int nnb;
 } pass1_t;
+
+/* Source densities at particle a and time t (see orc_source). */
+static void sources_at(const orc_params *prm, const geom *m, double t, const double *y, int64_t n, int64_t a,
+                       double I[4], double Iq[3])
+{
+  for (int k = 0; k < 4; ++k) I[k] = 0.0;
+  for (int k = 0; k < 3; ++k) Iq[k] = 0.0;
+  for (int k = 0; k < prm->nsrc; ++k) {
+    const orc_source *S = &prm->src[k];
+    if (!(t >= S->t_on && t < S->t_off)) continue;
+    double G = 1.0;
+    for (int d = 0; d < prm->dim; ++d) {
+      double centre = S->x0[d] + S->vel[d] * (t - S->t_on);
+      double dx = y[(V_X1 + d) * n + a] - centre;
+      G *= exp(-dx * dx / (2.0 * S->width[d] * S->width[d])) / (sqrt(2.0 * M_PI) * S->width[d]);
+    }
+    for (int mu = 0; mu < 4; ++mu) I[mu] += S->dpdt[mu] * G / m->sqrtg;
+    for (int q = 0; q < 3; ++q) Iq[q] += S->dndt[q] * G / m->sqrtg;
+  }
+}
 
 static double gamma_of(const geom *m, const double u[4])
 {
@@ -957,6 +1009,11 @@ int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
       c.cPipi = prm->c_Pipi;
       c.cpipi = prm->c_pipi;
       c.cpiPi = prm->c_piPi;
+      sources_at(prm, &m, t, y, n, a, c.I, c.Iq);
+      for (int q = 0; q < 3; ++q) {
+        c.mu[q] = q < prm->ncharge ? qa->th.mu[q] : 0.0;
+        if (q >= prm->ncharge) c.Iq[q] = 0.0;
+      }
 
       double zero[4] = {0, 0, 0, 0}, M[4][4], rhs[4], acc_u[4] = {0, 0, 0, 0};
       pout o0, oj;
@@ -980,6 +1037,7 @@ int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
         dydt[(V_U1 + k - 1) * n + a] = acc_u[k];
       }
       dydt[V_S * n + a] = o.dS;
+      for (int q = 0; q < prm->ncharge; ++q) dydt[(V_NB + q) * n + a] = o.dN[q];
       if (prm->viscous) {
         dydt[V_B * n + a] = o.dB;
         dydt[V_P11 * n + a] = o.dP[1][1];
