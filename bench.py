@@ -132,6 +132,35 @@ def run_gpu(B, I, w, eos, precision, steps, warmup):
                 backup=cnt.backup, newton_iters=cnt.newton_iters)
 
 
+def run_3d(B, w, eos, precision, steps, warmup, sources=None):
+    """Throughput of a 3+1D hyperbolic viscous BSQ event (same transport and
+    EoS as the headline run): warm-up steps, re-initialisation, then timed
+    steps of the whole path."""
+    import torch
+    cfg = B.config(dim=3, hyperbolic=True, viscous=True, precision=precision, ncharge=3, h=w.h,
+                   eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02)
+    sim = B.Sim(cfg, eos, w.n)
+    if sources:
+        sim.set_sources(sources)
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    if warmup:
+        sim.step(w.dt, warmup)
+        sim.check()
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    nnb = float(sim.read(B.AUX_NNB).mean())
+    torch.cuda.synchronize()
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w.dt, steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sim.check()
+    sim.close()
+    return dict(particle_steps_per_s=w.n * steps / elapsed, ms_per_step=elapsed / steps * 1e3, steps=steps,
+                particles=w.n, mean_neighbours=nnb)
+
+
 def run_serving(B, I, eos, events, steps, precision, rate=None, max_particles=4_000_000, max_events=256):
     """Continuous batching of the given events through the server.  rate None:
     all submitted at once (capacity); otherwise Poisson arrivals at that rate
@@ -243,6 +272,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-events", type=int, default=256, help="serving load: events (0 = skip)")
     ap.add_argument("--serve-steps", type=int, default=200, help="Heun steps per served event")
+    ap.add_argument("--steps-3d", type=int, default=10,
+                    help="timed steps of each 3+1D configuration (0 = skip them)")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both",
                     help="which precisions to run (counter-collection passes use one)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -321,6 +352,20 @@ def main():
         "eos_backup_fraction_last_stage": head["backup"] / w.n,
         "roofline": roof,
     }
+    if args.steps_3d > 0:
+        w2 = I.lumpy_3d_workload()
+        other = {}
+        for name, prec in (("fp64", B.FP64), ("mixed", B.MIXED)):
+            other[f"lumpy_3d_viscous_bsq_1.2M_{name}"] = run_3d(B, w2, eos, prec, args.steps_3d, 2)
+            print(f"[bench] 3D 1.2M {name}: {other[f'lumpy_3d_viscous_bsq_1.2M_{name}']['ms_per_step']:.2f} ms/step",
+                  file=sys.stderr, flush=True)
+        del w2
+        w4 = I.lumpy_3d_source_workload()
+        other["lumpy_3d_viscous_bsq_4M_jets_mixed"] = run_3d(B, w4, eos, B.MIXED, args.steps_3d, 2,
+                                                             sources=I.jet_sources())
+        print(f"[bench] 3D 4M jets: {other['lumpy_3d_viscous_bsq_4M_jets_mixed']['ms_per_step']:.2f} ms/step",
+              file=sys.stderr, flush=True)
+        out["other_configs"] = other
     if args.serve_events > 0:
         specs = I.serving_events(args.serve_events)
         events = [I.serving_event(s) for s in specs]

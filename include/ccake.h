@@ -183,6 +183,35 @@ ccake_status ccake_time(const ccake_sim* sim, double* t);
  * CCAKE_E_CAPACITY) already observed from an earlier call.                   */
 ccake_status ccake_step(ccake_sim* sim, double dt, int32_t nsteps);
 
+/* External sources of energy-momentum and charge, I^nu and I_q of
+ * eq. conservation_source, deposited as in the smeared parton source of the
+ * dynamical-initialisation section: each source is a normalised Gaussian in
+ * the particle coordinates (the third one is eta times 1 fm, as in the kernel
+ * distance) whose centre moves with constant coordinate velocity, active for
+ * t_on <= x0 < t_off, with densities
+ *     I^mu = (dp^mu/dx0) G / sqrt(-g),    I_q = (dN_q/dx0) G / sqrt(-g),
+ * so that the deposited totals per unit x0 are dpdt and dndt (per unit
+ * rapidity in 2+1D hyperbolic runs).  They enter the energy equation through
+ * u.I, the momentum balance through the spatial components, the entropy
+ * through (u.I - mu_q I_q)/T (eq. dsdnrewr) and the charges through
+ * dN_q/dx0 = I_q/(gamma sigma).                                              */
+typedef struct ccake_source {
+  double x0[3];     /* centre at x0 = t_on (fm; eta for the third axis of hyperbolic runs) */
+  double vel[3];    /* d centre / dx0 */
+  double width[3];  /* Gaussian widths (> 0 on the dim axes used) */
+  double t_on, t_off;
+  double dpdt[4];   /* contravariant dp^mu/dx0 deposited, fm^-2 */
+  double dndt[3];   /* dN_q/dx0 deposited (B, S, Q), fm^-1 */
+} ccake_source;
+
+enum { CCAKE_MAX_SOURCES = 16 };
+
+/* Replaces the simulation's sources (nsrc = 0 removes them).  Copied to the
+ * device on the simulation's stream, ordered after the steps already enqueued
+ * and before later ones; synchronises.  CCAKE_E_ARG when nsrc exceeds
+ * CCAKE_MAX_SOURCES or a width on a used axis is not positive.               */
+ccake_status ccake_set_sources(ccake_sim* sim, int32_t nsrc, const ccake_source* src);
+
 /* Synchronises and reports the sticky per-particle error state.             */
 ccake_status ccake_check(ccake_sim* sim);
 

@@ -33,7 +33,7 @@ EXPORTS = [
     "ccake_eos_create_conformal", "ccake_eos_create_gas", "ccake_eos_create_table",
     "ccake_eos_destroy", "ccake_eos_invert", "ccake_workspace_bytes", "ccake_create",
     "ccake_init_particles", "ccake_set_state", "ccake_get_state", "ccake_time", "ccake_step",
-    "ccake_check", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
+    "ccake_check", "ccake_set_sources", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
     "ccake_destroy", "ccake_server_create", "ccake_server_submit", "ccake_server_poll",
     "ccake_server_drain", "ccake_server_release", "ccake_server_stats", "ccake_server_destroy",
     "ccake_last_error",
@@ -56,6 +56,17 @@ class Config(ctypes.Structure):
         ("c_PiPi", ctypes.c_double), ("c_Pipi", ctypes.c_double), ("c_pipi", ctypes.c_double),
         ("c_piPi", ctypes.c_double), ("skin", ctypes.c_double),
     ]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [
+        ("x0", ctypes.c_double * 3), ("vel", ctypes.c_double * 3), ("width", ctypes.c_double * 3),
+        ("t_on", ctypes.c_double), ("t_off", ctypes.c_double),
+        ("dpdt", ctypes.c_double * 4), ("dndt", ctypes.c_double * 3),
+    ]
+
+
+MAX_SOURCES = 16
 
 
 class Counters(ctypes.Structure):
@@ -107,6 +118,7 @@ def lib():
             "ccake_time": [vp, dp],
             "ccake_step": [vp, dbl, i32],
             "ccake_check": [vp],
+            "ccake_set_sources": [vp, i32, ctypes.POINTER(Source)],
             "ccake_set_profiling": [vp, i32],
             "ccake_kernel_times": [vp, dp, ctypes.POINTER(i64)],
             "ccake_rhs": [vp, vp, vp, i32],
@@ -257,6 +269,20 @@ class Sim:
     # -- evolution -------------------------------------------------------------
     def step(self, dt, nsteps=1):
         _check(lib().ccake_step(self.h, dt, nsteps), self.h)
+
+    def set_sources(self, specs):
+        """External sources: dicts with x0, vel, width, t_on, t_off, dpdt, dndt
+        (vectors default to zero, the window to always-on)."""
+        arr = (Source * max(1, len(specs)))()
+        for k, sp in enumerate(specs):
+            S = arr[k]
+            for name, m in (("x0", 3), ("vel", 3), ("width", 3), ("dpdt", 4), ("dndt", 3)):
+                vals = list(sp.get(name, [0.0] * m)) + [0.0] * m
+                for i in range(m):
+                    getattr(S, name)[i] = float(vals[i])
+            S.t_on = float(sp.get("t_on", -1e300))
+            S.t_off = float(sp.get("t_off", 1e300))
+        _check(lib().ccake_set_sources(self.h, len(specs), arr), self.h)
 
     def check(self):
         _check(lib().ccake_check(self.h), self.h)

@@ -61,6 +61,22 @@ struct EosDev {
   const double* tab;  // node-major [nT][nB][nS][nQ][8]
 };
 
+// one external source, widths folded into 1/(2 w^2) and the normalisation of
+// the Gaussian over the dim axes
+struct SourceDev {
+  double c0[3], vel[3], iw2[3];
+  double norm;
+  double t_on, t_off;
+  double dpdt[4], dndt[3];
+};
+
+constexpr int MAX_SOURCES = 16;
+
+struct SourceSet {
+  int32_t n, pad;
+  SourceDev s[MAX_SOURCES];
+};
+
 struct Params {
   int32_t dim, hyperbolic, viscous, ncharge, density_mode, mixed;
   double h;
@@ -68,6 +84,7 @@ struct Params {
   double taupi_coeff, tauPi_ratio;
   double c_PiPi, c_Pipi, c_pipi, c_piPi;
   double cell_edge;   // >= 2h + skin
+  const SourceSet* src = nullptr;  // external sources (device), or none
 };
 
 // one event of a batch (device-resident table)

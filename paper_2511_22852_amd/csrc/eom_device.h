@@ -13,9 +13,14 @@
 //   gamma d(pi^{ij}/sigma)/dx0 = (1/sigma)[(2 eta sigma^{ij} - pi^{ij})/tau_pi
 //         + (1 - c_pipi) pi^{ij} theta + c_piPi Pi sigma^{ij}
 //         - (u^i pi^{jl} + u^j pi^{il}) Du_l - Christoffel terms]   (eq. min_she_rel)
-//   Dp = -c_s^2 w theta + (dp/de)_n (-Pi theta + pi:sigma)
-//   momentum: d/dx0[(w+Pi) Q_i/sigma + G_i pi^{0i}/(sigma gamma)] = -sqrt(-g) F_i
-//   entropy:  gamma sigma T dS/dx0 = -Pi theta + pi:sigma          (eq. dsdnrewr)
+//   Dp = -c_s^2 w theta + (dp/de)_n (-Pi theta + pi:sigma + u.I)
+//   momentum: d/dx0[(w+Pi) Q_i/sigma + G_i pi^{0i}/(sigma gamma)]
+//             = -sqrt(-g) F_i + G_i I^i/(gamma sigma)
+//   entropy:  gamma sigma T dS/dx0 = u.I - mu_q I_q - Pi theta + pi:sigma   (eq. dsdnrewr)
+//   charges:  dN_q/dx0 = I_q/(gamma sigma)
+// I^mu, I_q are the external source densities of eq. conservation_source;
+// D eps gains u.I (eq. e_conservation).  The charge source does not enter Dp
+// ((dp/dn_q)_e = 0, exact for p = eps/3 equations of state).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -43,11 +48,14 @@ struct EomIn {
   double F[4];        // SPH force sums, i = 1..D
   double sigma, w, Pi, T, cs2, kappa, eta, zeta, taupi, tauPi;
   double pi[4][4];    // pi^{mu nu}
+  double I[4], Iq[3]; // source densities (zero without sources)
+  double mu[3];       // chemical potentials (zero without charges)
 };
 
 struct EomOut {
   double a[4];        // du^i/dx0
   double dS, dB, theta;
+  double dN[3];       // dN_q/dx0
   double dP[4][4];    // d(pi^{ij}/sigma)/dx0
 };
 
@@ -125,9 +133,10 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
       for (int n = 0; n < 4; ++n) pisig = pisig + (in.pi[m][n] * g[m] * g[n]) * sg[m][n];
   }
   const double Pi = VISC ? in.Pi : 0.0;
+  const double uI = gam * in.I[0] - (u[1] * in.I[1] + u[2] * in.I[2] + G[3] * u3 * in.I[3]);
   Aff DPi = aff(0.0);
   if (VISC) DPi = (-1.0 / in.tauPi) * (in.zeta * theta + Pi) - (prm.c_PiPi * Pi) * theta + prm.c_Pipi * pisig;
-  Aff Dp = (-in.cs2 * in.w) * theta + in.kappa * ((-Pi) * theta + pisig);
+  Aff Dp = (-in.cs2 * in.w) * theta + in.kappa * ((-Pi) * theta + pisig + uI);
 
   // relaxation of pi^{ij}/sigma
   Aff dP[4][4];
@@ -152,13 +161,13 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
 
   // momentum balance rows
   const double wP = in.w + Pi;
-  Aff dwPs = (1.0 / (in.sigma * gam)) * (pisig + Dp + DPi);
+  Aff dwPs = (1.0 / (in.sigma * gam)) * (pisig + Dp + DPi + uI);
   Aff R[4];
 #pragma unroll
   for (int i = 1; i <= D; ++i) {
     const double Qi = G[i] * uu[i];
     Aff dQ = G[i] * A[i] + Gd[i] * uu[i];
-    Aff r = (wP / in.sigma) * dQ + Qi * dwPs + sqrtg * in.F[i];
+    Aff r = (wP / in.sigma) * dQ + Qi * dwPs + (sqrtg * in.F[i] - G[i] * in.I[i] * igs);
     if (VISC) {
       double sQP = 0.0;
       Aff dsQP = aff(0.0);
@@ -210,16 +219,19 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
 #pragma unroll
   for (int k = 0; k < 4; ++k) out.a[k] = a[k];
   out.theta = at(theta, a);
+  const double heat = uI - (in.mu[0] * in.Iq[0] + in.mu[1] * in.Iq[1] + in.mu[2] * in.Iq[2]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out.dN[q] = in.Iq[q] * igs;
   if (VISC) {
     const double ps = at(pisig, a), th = out.theta;
-    out.dS = (-Pi * th + ps) / (gam * in.sigma * in.T);
+    out.dS = (-Pi * th + ps + heat) / (gam * in.sigma * in.T);
     out.dB = (at(DPi, a) + Pi * th) * igs;
 #pragma unroll
     for (int i = 1; i < 4; ++i)
 #pragma unroll
       for (int j = 1; j < 4; ++j) out.dP[i][j] = at(dP[i][j], a);
   } else {
-    out.dS = 0.0;
+    out.dS = heat / (gam * in.sigma * in.T);
     out.dB = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)

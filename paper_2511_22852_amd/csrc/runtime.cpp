@@ -120,6 +120,7 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.cf = take(&o, I4 * (ccap + 1));
   L.evt = take(&o, sizeof(EventDev) * nev);
   L.scratch = take(&o, 64 + D8 * 8 * nev);
+  L.src = take(&o, sizeof(SourceSet));
   L.total = o;
   return L;
 }
@@ -300,16 +301,20 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
   s->b = bind_batch(s->base, L, n, ccap, 1);
   s->stream = (hipStream_t)stream;
   s->use_graph = getenv("CCAKE_NO_GRAPH") == nullptr && stream != nullptr;
+  s->prm.src = (const SourceSet*)(s->base + L.src);
   if (hipHostMalloc((void**)&s->h_evt, sizeof(EventDev), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&s->h_src, sizeof(SourceSet), hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&s->evt_done, hipEventDisableTiming) != hipSuccess) {
-    delete s;
+    ccake_destroy(s);
     return CCAKE_E_NOMEM;
   }
+  memset(s->h_src, 0, sizeof(SourceSet));
   // slot -> event map: every slot belongs to event 0; cell counts start at zero
   // (the binning leaves them zero after every use)
   std::vector<int32_t> ev((size_t)n, 0);
   hipError_t he = hipMemcpy(s->b.ev, ev.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (ccap + 1));
+  if (he == hipSuccess) he = hipMemset(s->base + L.src, 0, sizeof(SourceSet));
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) {
     ccake_destroy(s);
@@ -565,6 +570,41 @@ extern "C" ccake_status ccake_step(ccake_sim* s, double dt, int32_t nsteps) {
   return CCAKE_OK;
 }
 
+static_assert(CCAKE_MAX_SOURCES == MAX_SOURCES, "source table size");
+
+extern "C" ccake_status ccake_set_sources(ccake_sim* s, int32_t nsrc, const ccake_source* src) {
+  if (!s) return CCAKE_E_ARG;
+  if (nsrc < 0 || nsrc > CCAKE_MAX_SOURCES || (nsrc > 0 && !src))
+    return fail(s, CCAKE_E_ARG, "ccake_set_sources: nsrc must be in [0, %d]", CCAKE_MAX_SOURCES);
+  const int D = s->prm.dim;
+  for (int k = 0; k < nsrc; ++k) {
+    for (int d = 0; d < D; ++d)
+      if (!(src[k].width[d] > 0.0) || !std::isfinite(src[k].width[d]))
+        return fail(s, CCAKE_E_ARG, "ccake_set_sources: source %d has a non-positive width", k);
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));  // the staging buffer may still feed an earlier copy
+  SourceSet& S = *s->h_src;
+  memset(&S, 0, sizeof S);
+  S.n = nsrc;
+  for (int k = 0; k < nsrc; ++k) {
+    SourceDev& d = S.s[k];
+    d.norm = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      d.c0[a] = src[k].x0[a];
+      d.vel[a] = src[k].vel[a];
+      d.iw2[a] = a < D ? 1.0 / (2.0 * src[k].width[a] * src[k].width[a]) : 0.0;
+      if (a < D) d.norm /= std::sqrt(2.0 * 3.14159265358979323846) * src[k].width[a];
+    }
+    d.t_on = src[k].t_on;
+    d.t_off = src[k].t_off;
+    for (int m = 0; m < 4; ++m) d.dpdt[m] = src[k].dpdt[m];
+    for (int q = 0; q < 3; ++q) d.dndt[q] = q < s->prm.ncharge ? src[k].dndt[q] : 0.0;
+  }
+  HIPCHK(s, hipMemcpyAsync(s->base + s->L.src, &S, sizeof S, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return CCAKE_OK;
+}
+
 extern "C" ccake_status ccake_check(ccake_sim* s) {
   if (!s) return CCAKE_E_ARG;
   ccake_status st = fetch_event(s);
@@ -650,6 +690,7 @@ extern "C" ccake_status ccake_destroy(ccake_sim* s) {
   if (s->evt_done) (void)hipEventDestroy(s->evt_done);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->h_evt) (void)hipHostFree(s->h_evt);
+  if (s->h_src) (void)hipHostFree(s->h_src);
   delete s;
   return CCAKE_OK;
 }

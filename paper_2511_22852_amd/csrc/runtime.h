@@ -19,7 +19,8 @@ struct Handle {
 
 // byte offsets of the arrays of one batch inside its workspace
 struct Layout {
-  size_t Y0, Ys, Y1, th, rec, recf, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, cs, cf, evt, scratch, total;
+  size_t Y0, Ys, Y1, th, rec, recf, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, cs, cf, evt, scratch, src,
+      total;
 };
 
 ccake_status fail(Handle* h, ccake_status code, const char* fmt, ...);
@@ -48,6 +49,7 @@ struct ccake_sim : ccake::Handle {
   int64_t n = 0, ccap = 0;
   hipStream_t stream = nullptr;
   double t = 0.0, dt_host = 0.0;
+  ccake::SourceSet* h_src = nullptr;  // pinned staging of the source table
   bool initialised = false;
   bool use_graph = false, graph_ready = false, pending = false;
   hipGraphExec_t graph = nullptr;

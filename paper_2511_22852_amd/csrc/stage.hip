@@ -436,6 +436,31 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   }
 }
 
+// Source densities I^mu, I_q at position x and time t: sum over the active
+// sources of the rates times the normalised Gaussian around the moving
+// centre, divided by sqrt(-g) (eq. conservation_source with the smeared
+// deposition of the dynamical initialisation).
+template <int D>
+__device__ inline void source_density(const SourceSet& S, double t, double sqg, const double x[3], double I[4],
+                                      double Iq[3]) {
+  const int ns = S.n;
+  for (int k = 0; k < ns; ++k) {
+    const SourceDev& s = S.s[k];
+    if (!(t >= s.t_on && t < s.t_off)) continue;
+    double arg = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double dx = x[d] - (s.c0[d] + s.vel[d] * (t - s.t_on));
+      arg += dx * dx * s.iw2[d];
+    }
+    const double g = s.norm * exp(-arg) / sqg;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) I[m] += s.dpdt[m] * g;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Iq[q] += s.dndt[q] * g;
+  }
+}
+
 // ---------------------------------------------------------------------------
 //   mode 0: Y1 = Ys + dt f(Ys)
 //   mode 1: Y0 = (Ys + Y1 + dt f(Y1)) / 2, carry ids and warm starts home
@@ -518,6 +543,20 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
     for (int i = 1; i < 4; ++i) acc += Gk[i] * in.u[i] * in.pi[0][i];
     in.pi[0][0] = acc / gam;
   }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) in.I[k] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    in.Iq[q] = 0.0;
+    in.mu[q] = q < prm.ncharge ? T_[(int64_t)(T_MUB + q) * cap + j] : 0.0;
+  }
+  if (prm.src) {
+    double x[3];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = row(Y, cap, R_X1 + k, j);
+    source_density<D>(*prm.src, t, sqg, x, in.I, in.Iq);
+    if (prm.ncharge == 0) in.Iq[0] = in.Iq[1] = in.Iq[2] = 0.0;
+  }
   EomOut o;
   eom_solve<D, VISC>(prm, in, o);
 
@@ -530,6 +569,8 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
     f[R_U1 + k - 1] = o.a[k];
   }
   f[R_S] = o.dS;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) f[R_NB + q] = q < prm.ncharge ? o.dN[q] : 0.0;
   if (VISC) {
     f[R_B] = o.dB;
     f[R_P11] = o.dP[1][1];

@@ -203,6 +203,50 @@ def lumpy_3d_workload(nxy=160, dxy=0.1, neta=48, deta=0.125, h=0.3, seed=2, n_ho
                     {"seed": seed})
 
 
+def jet_sources(seed=4, n_jets=4, E_GeV=20.0, t_on=0.6, duration=2.0, width=0.3, radius=3.0,
+                eta_range=1.0, dim=3):
+    """External energy-momentum sources for jets: n_jets/2 back-to-back pairs
+    from seeded production points (transverse ~ N(0, radius^2) per axis, eta
+    ~ U(-eta_range, eta_range) in 3D), directions phi ~ U(0, 2 pi) and phi + pi,
+    moving transversely at the speed of light.  Each deposits E_GeV uniformly
+    over [t_on, t_on + duration) through a Gaussian of the given width, with
+    the momentum of a massless particle at its own rapidity (p^eta = 0).
+    Returns source dicts (x0, vel, width, t_on, t_off, dpdt, dndt)."""
+    rng = np.random.default_rng(seed)
+    rate = E_GeV / HBARC / duration
+    specs = []
+    for _ in range(n_jets // 2):
+        x, y = rng.normal(0.0, radius, 2)
+        eta = rng.uniform(-eta_range, eta_range) if dim == 3 else 0.0
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        for ph in (phi, phi + np.pi):
+            c, sn = float(np.cos(ph)), float(np.sin(ph))
+            specs.append(dict(x0=[float(x), float(y), float(eta)], vel=[c, sn, 0.0], width=[width] * 3,
+                              t_on=t_on, t_off=t_on + duration, dpdt=[rate, rate * c, rate * sn, 0.0],
+                              dndt=[0.0, 0.0, 0.0]))
+    return specs
+
+
+def baryon_stopping_sources(n_baryons=100.0, eta0=1.0, width_eta=0.3, radius=3.0, t_on=0.6, duration=2.0,
+                            E_per_baryon_GeV=0.94):
+    """Stopped-baryon variant: baryon number deposited at rest on the sheets
+    eta_s = +-eta0 (Gaussian in eta of width width_eta, transverse Gaussian of
+    width radius), n_baryons in total over [t_on, t_on + duration), each with
+    the nucleon rest energy.  Returns source dicts."""
+    rate_B = 0.5 * n_baryons / duration
+    rate_E = rate_B * E_per_baryon_GeV / HBARC
+    return [dict(x0=[0.0, 0.0, sgn * eta0], vel=[0.0, 0.0, 0.0], width=[radius, radius, width_eta], t_on=t_on,
+                 t_off=t_on + duration, dpdt=[rate_E, 0.0, 0.0, 0.0], dndt=[rate_B, 0.0, 0.0])
+            for sgn in (1.0, -1.0)]
+
+
+def lumpy_3d_source_workload(nxy=200, dxy=0.1, neta=100, deta=0.06, h=0.3, seed=4, **kw):
+    """The 4.0 M-particle 3+1D event of the jet-source runs: the lumpy profile
+    on [-10, 10)^2 at 0.1 fm times the eta plateau, eta on [-3, 3) at 0.06."""
+    return lumpy_3d_workload(nxy=nxy, dxy=dxy, neta=neta, deta=deta, h=h, seed=seed,
+                             name="lumpy_3d_sources", **kw)
+
+
 # ---------------------------------------------------------------------------
 # Synthetic 4D EoS table: massless u, d, s quarks + gluons
 # ---------------------------------------------------------------------------

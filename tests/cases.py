@@ -19,12 +19,12 @@ def table(size="small"):
 
 
 def make(O, B, *, dim=2, hyperbolic=True, viscous=False, ncharge=0, h=0.3, eos="conformal",
-         density_mode=0, precision=0, table_size="small", coeffs=None, skin=None):
+         density_mode=0, precision=0, table_size="small", coeffs=None, skin=None, sources=None):
     tr = dict(TRANSPORT) if viscous else {}
     if coeffs:
         tr.update(coeffs)
     prm = O.params(dim=dim, hyperbolic=hyperbolic, viscous=viscous, ncharge=ncharge, h=h, use_cells=1,
-                   density_mode=density_mode, **tr)
+                   density_mode=density_mode, source_specs=sources, **tr)
     cfg = B.config(dim=dim, hyperbolic=hyperbolic, viscous=viscous, precision=precision, ncharge=ncharge,
                    density_mode=density_mode, h=h, skin=skin, **tr)
     if eos == "conformal":
