@@ -92,7 +92,7 @@ def algorithmic_model(dim, viscous, ncharge, mixed, smoothed=True):
     return {
         "density_sums": dict(bytes=8 * dens_in + 4 + 8 * 6,
                              pair_flops=5 + 1 + 1 + 7 + 1 + (2 * (1 + ncharge) if smoothed else 0)),
-        "eos_inversion": dict(bytes=8 * 5 + 8 * (state - dim) + 8 * 4 * 2 + 8 * nth + recb * rec, pair_flops=0),
+        "eos_inversion": dict(bytes=8 * 5 + 8 * (state - dim) + 8 * 8 * 2 + 8 * nth + recb * rec, pair_flops=0),
         "gradient_sums": dict(bytes=8 * dim + 4 + recb * rec + 8 + 8 * ngs,
                               pair_flops=5 + 1 + 1 + 5 + 1 + dim + 1 + 2 * dim + 4 * dim * dim + 3 * dim
                               + ((4 * dim * dim + dim) if viscous else 0)),

@@ -123,6 +123,9 @@ def lib():
         L.orc_rhs.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
                               ctypes.c_int64, dp, dp, dp]
         L.orc_heun_step.restype = ctypes.c_int
+        L.orc_rhs_targets.restype = ctypes.c_int
+        L.orc_rhs_targets.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
+                                      ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), dp, dp]
         L.orc_heun_step.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int64, dp, dp]
         L.orc_init.restype = ctypes.c_int
@@ -267,6 +270,20 @@ def rhs(prm: Params, eos: Eos, t: float, y):
     dy = np.zeros((NVAR, n))
     aux = np.zeros((NAUX, n))
     bad = lib().orc_rhs(ctypes.byref(prm), ctypes.byref(eos.c), t, n, _dp(y), _dp(dy), _dp(aux))
+    return dy, aux, bad
+
+
+def rhs_targets(prm: Params, eos: Eos, t: float, y, targets):
+    """Rates and diagnostics at the listed particles only (columns in the
+    order of targets)."""
+    y = _f64(y)
+    n = y.shape[1]
+    tg = np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+    nt = tg.shape[0]
+    dy = np.zeros((NVAR, nt))
+    aux = np.zeros((NAUX, nt))
+    bad = lib().orc_rhs_targets(ctypes.byref(prm), ctypes.byref(eos.c), t, n, _dp(y), nt,
+                                tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(dy), _dp(aux))
     return dy, aux, bad
 
 

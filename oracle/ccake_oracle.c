@@ -867,8 +867,12 @@ static double gamma_of(const geom *m, const double u[4])
   return sqrt(1.0 + m->G[1] * u[1] * u[1] + m->G[2] * u[2] * u[2] + m->G[3] * u[3] * u[3]);
 }
 
-int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
-            const double *y, double *dydt, double *aux)
+/* Right-hand side at every particle (targets == NULL; outputs [row][n]) or at
+ * the listed target particles only (outputs [row][nt], in the order of the
+ * list).  For targets, pass 1 runs on the targets and their neighbours,
+ * which is all that their pass 2 reads. */
+static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t n, const double *y,
+                    int64_t nt, const int64_t *targets, double *dydt, double *aux)
 {
   const int D = prm->dim;
   geom m;
@@ -879,6 +883,18 @@ int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
   pass1_t *P1 = (pass1_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(pass1_t));
   int nthr = nthreads_of(prm);
   int bad = 0;
+  const int64_t nout = targets ? nt : n;
+  char *need1 = NULL;
+  if (targets) {
+    need1 = (char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t *buf = NULL, cap = 0;
+    for (int64_t ti = 0; ti < nt; ++ti) {
+      int64_t cnt = neighbours(prm, &g, y, n, targets[ti], &buf, &cap);
+      for (int64_t j = 0; j < cnt; ++j) need1[buf[j]] = 1;
+      need1[targets[ti]] = 1;
+    }
+    free(buf);
+  }
 
   /* ---- pass 1: density sums, EoS, transport, dissipative tensors ---- */
 #pragma omp parallel num_threads(nthr) reduction(+:bad)
@@ -886,6 +902,7 @@ int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
     int64_t *buf = NULL, cap = 0;
 #pragma omp for schedule(dynamic, 64)
     for (int64_t a = 0; a < n; ++a) {
+      if (need1 && !need1[a]) continue;
       pass1_t *q = &P1[a];
       int64_t cnt = neighbours(prm, &g, y, n, a, &buf, &cap);
       double ss = 0.0, st = 0.0, nt[3] = {0.0, 0.0, 0.0};
@@ -953,7 +970,8 @@ int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
   {
     int64_t *buf = NULL, cap = 0;
 #pragma omp for schedule(dynamic, 64)
-    for (int64_t a = 0; a < n; ++a) {
+    for (int64_t oi = 0; oi < nout; ++oi) {
+      const int64_t a = targets ? targets[oi] : oi;
       const pass1_t *qa = &P1[a];
       int64_t cnt = neighbours(prm, &g, y, n, a, &buf, &cap);
       double F[4] = {0, 0, 0, 0}, dudx[4][4], divv = 0.0;
@@ -1031,43 +1049,56 @@ int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
       pout o;
       eom_eval(&c, acc_u, &o);
 
-      for (int v = 0; v < NVAR; ++v) dydt[v * n + a] = 0.0;
+      for (int v = 0; v < NVAR; ++v) dydt[v * nout + oi] = 0.0;
       for (int k = 1; k <= D; ++k) {
-        dydt[(V_X1 + k - 1) * n + a] = c.v[k];
-        dydt[(V_U1 + k - 1) * n + a] = acc_u[k];
+        dydt[(V_X1 + k - 1) * nout + oi] = c.v[k];
+        dydt[(V_U1 + k - 1) * nout + oi] = acc_u[k];
       }
-      dydt[V_S * n + a] = o.dS;
-      for (int q = 0; q < prm->ncharge; ++q) dydt[(V_NB + q) * n + a] = o.dN[q];
+      dydt[V_S * nout + oi] = o.dS;
+      for (int q = 0; q < prm->ncharge; ++q) dydt[(V_NB + q) * nout + oi] = o.dN[q];
       if (prm->viscous) {
-        dydt[V_B * n + a] = o.dB;
-        dydt[V_P11 * n + a] = o.dP[1][1];
-        dydt[V_P12 * n + a] = o.dP[1][2];
-        dydt[V_P13 * n + a] = o.dP[1][3];
-        dydt[V_P22 * n + a] = o.dP[2][2];
-        dydt[V_P23 * n + a] = o.dP[2][3];
-        dydt[V_P33 * n + a] = o.dP[3][3];
+        dydt[V_B * nout + oi] = o.dB;
+        dydt[V_P11 * nout + oi] = o.dP[1][1];
+        dydt[V_P12 * nout + oi] = o.dP[1][2];
+        dydt[V_P13 * nout + oi] = o.dP[1][3];
+        dydt[V_P22 * nout + oi] = o.dP[2][2];
+        dydt[V_P23 * nout + oi] = o.dP[2][3];
+        dydt[V_P33 * nout + oi] = o.dP[3][3];
       }
       if (aux) {
-        aux[A_SIGSTAR * n + a] = qa->sigstar;
-        aux[A_S * n + a] = qa->s;
-        for (int k = 0; k < 3; ++k) aux[(A_NB + k) * n + a] = qa->n[k];
-        aux[A_T * n + a] = qa->th.T;
-        for (int k = 0; k < 3; ++k) aux[(A_MUB + k) * n + a] = qa->th.mu[k];
-        aux[A_P * n + a] = qa->th.p;
-        aux[A_E * n + a] = qa->th.e;
-        aux[A_CS2 * n + a] = qa->th.cs2;
-        aux[A_INTABLE * n + a] = qa->th.in_table;
-        aux[A_GAMMA * n + a] = qa->gam;
-        aux[A_THETA * n + a] = o.theta;
-        aux[A_NNB * n + a] = qa->nnb;
-        for (int i = 1; i <= 3; ++i) aux[(A_F1 + i - 1) * n + a] = F[i];
+        aux[A_SIGSTAR * nout + oi] = qa->sigstar;
+        aux[A_S * nout + oi] = qa->s;
+        for (int k = 0; k < 3; ++k) aux[(A_NB + k) * nout + oi] = qa->n[k];
+        aux[A_T * nout + oi] = qa->th.T;
+        for (int k = 0; k < 3; ++k) aux[(A_MUB + k) * nout + oi] = qa->th.mu[k];
+        aux[A_P * nout + oi] = qa->th.p;
+        aux[A_E * nout + oi] = qa->th.e;
+        aux[A_CS2 * nout + oi] = qa->th.cs2;
+        aux[A_INTABLE * nout + oi] = qa->th.in_table;
+        aux[A_GAMMA * nout + oi] = qa->gam;
+        aux[A_THETA * nout + oi] = o.theta;
+        aux[A_NNB * nout + oi] = qa->nnb;
+        for (int i = 1; i <= 3; ++i) aux[(A_F1 + i - 1) * nout + oi] = F[i];
       }
     }
     free(buf);
   }
   free(P1);
+  free(need1);
   if (prm->use_cells) grid_free(&g);
   return bad;
+}
+
+int orc_rhs(const orc_params *prm, const orc_eos *eos, double t, int64_t n,
+            const double *y, double *dydt, double *aux)
+{
+  return rhs_impl(prm, eos, t, n, y, 0, NULL, dydt, aux);
+}
+
+int orc_rhs_targets(const orc_params *prm, const orc_eos *eos, double t, int64_t n, const double *y,
+                    int64_t nt, const int64_t *targets, double *dydt, double *aux)
+{
+  return rhs_impl(prm, eos, t, n, y, nt, targets, dydt, aux);
 }
 
 /* Heun (second-order Runge-Kutta) step, the reading of the paper's

@@ -21,8 +21,10 @@
 namespace ccake {
 
 __global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslots) {
+  __shared__ double s_lo[4][3], s_hi[4][3];
+  __shared__ int s_e[4];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int e = i < nslots ? b.ev[i] : -1;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   if (e >= 0) {
@@ -34,23 +36,15 @@ __global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslot
       }
     }
   }
-  // is the whole wave on one event?
+  // waves on one event reduce in registers; the others add lane by lane
   const int e0 = __shfl(e, 0, 64);
   const bool uniform = __all(e == e0);
   if (uniform) {
-    if (e0 < 0) return;
     for (int k = 0; k < dim; ++k) {
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
         lo[k] = fmin(lo[k], __shfl_xor(lo[k], off, 64));
         hi[k] = fmax(hi[k], __shfl_xor(hi[k], off, 64));
-      }
-    }
-    if (lane == 0) {
-      EventDev* E = b.evt + e0;
-      for (int k = 0; k < dim; ++k) {
-        if (isfinite(lo[k])) atomicMin(&E->bb_min[k], ordered_bits(lo[k]));
-        if (isfinite(hi[k])) atomicMax(&E->bb_max[k], ordered_bits(hi[k]));
       }
     }
   } else if (e >= 0) {
@@ -60,12 +54,46 @@ __global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslot
       if (isfinite(hi[k])) atomicMax(&E->bb_max[k], ordered_bits(hi[k]));
     }
   }
+  if (lane == 0) {
+    s_e[w] = uniform ? e0 : -1;
+    for (int k = 0; k < 3; ++k) {
+      s_lo[w][k] = lo[k];
+      s_hi[w][k] = hi[k];
+    }
+  }
+  __syncthreads();
+  // one thread merges the block's uniform waves: one atomic per axis when
+  // they share an event, one per wave otherwise
+  if (threadIdx.x == 0) {
+    const int nw = (int)(blockDim.x >> 6);
+    for (int a = 0; a < nw; ++a) {
+      const int ea = s_e[a];
+      if (ea < 0) continue;
+      double l[3] = {s_lo[a][0], s_lo[a][1], s_lo[a][2]}, h[3] = {s_hi[a][0], s_hi[a][1], s_hi[a][2]};
+      for (int c = a + 1; c < nw; ++c) {
+        if (s_e[c] != ea) continue;
+        for (int k = 0; k < 3; ++k) {
+          l[k] = fmin(l[k], s_lo[c][k]);
+          h[k] = fmax(h[k], s_hi[c][k]);
+        }
+        s_e[c] = -1;
+      }
+      EventDev* E = b.evt + ea;
+      for (int k = 0; k < dim; ++k) {
+        if (isfinite(l[k])) atomicMin(&E->bb_min[k], ordered_bits(l[k]));
+        if (isfinite(h[k])) atomicMax(&E->bb_max[k], ordered_bits(h[k]));
+      }
+    }
+  }
 }
 
 __global__ void k_grid(BatchDev b, Params prm, int dim) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= b.max_events) return;
   EventDev* E = b.evt + e;
+  // per-step EoS counters start from zero (the stage kernels add to them)
+  E->backup = 0;
+  E->newton_iters = 0;
   if (!E->active) return;
   double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
   bool empty = false;
@@ -106,22 +134,44 @@ __global__ void k_grid(BatchDev b, Params prm, int dim) {
   E->edge = edge;
 }
 
+// Runs of equal (event, cell) among the lanes of a wave.  Particles arrive in
+// the previous step's cell order, so runs are long and one atomic per run
+// replaces one per particle.  Returns the lane of this lane's run head and the
+// run length (for the head); lanes with tag < 0 form runs of their own.
+__device__ __forceinline__ void wave_runs(int64_t tag, int lane, int* head, int* len) {
+  const int64_t prev = __shfl_up(tag, 1, 64);
+  const bool is_head = lane == 0 || tag < 0 || prev != tag;
+  const unsigned long long heads = __ballot(is_head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  *head = 63 - __clzll((long long)(heads & upto));
+  const unsigned long long after = heads & ~upto;
+  const int next = after ? __ffsll((long long)after) - 1 : 64;
+  *len = next - *head;
+}
+
 __global__ void __launch_bounds__(256) k_count(BatchDev b, int dim, int64_t nslots) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nslots) return;
-  const int e = b.ev[i];
-  if (e < 0) return;
-  const EventDev& E = b.evt[e];
-  int32_t key = 0, stride = 1;
-  for (int k = 0; k < dim; ++k) {
-    const double u = (row(b.Y0, b.cap, R_X1 + k, i) - E.lo[k]) / E.edge;
-    int c = (int)floor(u);
-    c = c < 0 ? 0 : (c >= E.nc[k] ? E.nc[k] - 1 : c);
-    key += c * stride;
-    stride *= E.nc[k];
+  const int lane = threadIdx.x & 63;
+  const int e = i < nslots ? b.ev[i] : -1;
+  int64_t tag = -1;
+  int32_t cell = 0;
+  if (e >= 0) {
+    const EventDev& E = b.evt[e];
+    int32_t key = 0, stride = 1;
+    for (int k = 0; k < dim; ++k) {
+      const double u = (row(b.Y0, b.cap, R_X1 + k, i) - E.lo[k]) / E.edge;
+      int c = (int)floor(u);
+      c = c < 0 ? 0 : (c >= E.nc[k] ? E.nc[k] - 1 : c);
+      key += c * stride;
+      stride *= E.nc[k];
+    }
+    b.key[i] = key;
+    cell = E.c_base + key;
+    tag = cell;
   }
-  b.key[i] = key;
-  atomicAdd(&b.cell_fill[E.c_base + key], 1);
+  int head, len;
+  wave_runs(tag, lane, &head, &len);
+  if (e >= 0 && head == lane) atomicAdd(&b.cell_fill[cell], len);
 }
 
 // exclusive scan of the cell counts of one event (one 1024-thread block per event)
@@ -159,11 +209,16 @@ __global__ void __launch_bounds__(1024) k_scan(BatchDev b, int dim) {
 
 __global__ void __launch_bounds__(256) k_scatter(BatchDev b, int64_t nslots) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nslots) return;
-  const int e = b.ev[i];
-  if (e < 0) return;
-  const int32_t slot = atomicAdd(&b.cell_fill[b.evt[e].c_base + b.key[i]], 1);
-  b.perm[slot] = (int32_t)i;
+  const int lane = threadIdx.x & 63;
+  const int e = i < nslots ? b.ev[i] : -1;
+  const int32_t cell = e >= 0 ? b.evt[e].c_base + b.key[i] : 0;
+  int head, len;
+  wave_runs(e >= 0 ? (int64_t)cell : -1, lane, &head, &len);
+  // the run head reserves len slots; the order inside a cell is fixed later
+  int32_t base = 0;
+  if (e >= 0 && head == lane) base = atomicAdd(&b.cell_fill[cell], len);
+  base = __shfl(base, head, 64);
+  if (e >= 0) b.perm[base + (lane - head)] = (int32_t)i;
 }
 
 // one wave per cell: the rank of each member is the number of members with a

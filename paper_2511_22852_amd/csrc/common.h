@@ -22,7 +22,7 @@ enum Row {
 // auxiliary per-particle outputs of a right-hand-side evaluation (debug/parity)
 enum Aux {
   X_SIGSTAR, X_S, X_NB, X_NS, X_NQ, X_T, X_MUB, X_MUS, X_MUQ, X_P, X_E,
-  X_CS2, X_INTABLE, X_GAMMA, X_THETA, X_NNB, X_F1, X_F2, X_F3, NAUXROW
+  X_CS2, X_INTABLE, X_GAMMA, X_THETA, X_NNB, X_F1, X_F2, X_F3, X_NEWTON, NAUXROW
 };
 
 // per-particle thermodynamic record written by pass 1, read (own particle) by pass 2
@@ -36,8 +36,10 @@ enum Th {
 enum Rec { Q_PP, Q_A11, Q_A12, Q_A13, Q_A21, Q_A22, Q_A23, Q_A31, Q_A32, Q_A33,
            Q_U1, Q_U2, Q_U3, Q_V1, Q_V2, Q_V3, NREC };
 
-// warm-start record of the EoS inversion (carried with the particle)
-enum Warm { W_T, W_MUB, W_MUS, W_MUQ, NWARM };
+// warm-start record of the EoS inversion (carried with the particle): the
+// last root of the analytic backup EoS and, when the table answered, the last
+// root of the table interpolant (W_TT = 0 when there is none)
+enum Warm { W_GT, W_GMUB, W_GMUS, W_GMUQ, W_TT, W_TMUB, W_TMUS, W_TMUQ, NWARM };
 
 // density sums of a particle (lab frame, kernel normalisation applied) and its neighbour count
 enum DSum { DS_SIG, DS_S, DS_NB, DS_NS, DS_NQ, DS_NNB, NDSUM };

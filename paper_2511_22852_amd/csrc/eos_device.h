@@ -374,12 +374,23 @@ __device__ inline void thermo_fill(const EosDev& e, bool table, double T, const 
   th.kappa = 1.0 / 3.0;
 }
 
-// Invert (s or e, nB, nS, nQ) -> (T, mu).  The analytic gas is solved first
-// (from the warm start when given); if its root lies inside the table axes the
-// table interpolant is solved from that root and accepted when it converges
-// inside; otherwise the gas is the backup.  Conformal: closed form.
+__device__ __forceinline__ bool finite4(const double* x) {
+  return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(x[3]);
+}
+
+// Invert (s or e, nB, nS, nQ) -> (T, mu).  The analytic gas is solved first;
+// if its root lies inside the table axes the table interpolant is solved and
+// accepted when it converges inside; otherwise the gas is the backup.
+// Conformal: closed form.
+// Warm start (warm[NWARM] or null): the gas solve starts from the last gas
+// root; the table solve starts from the last table root moved by the change
+// of the gas root since then (the two roots differ by the interpolation
+// error, which varies slowly), else from the gas root.  Both solves converge
+// to the same roots from any start inside their basins; the starts only save
+// iterations.  warm_out (or null) receives the new record.
 template <int NQ>
-__device__ inline void eos_invert(const EosDev& e, int mode, const double in[4], const double* warm, Thermo& th) {
+__device__ inline void eos_invert(const EosDev& e, int mode, const double in[4], const double* warm, Thermo& th,
+                                  double* warm_out = nullptr) {
   th.iters = 0;
   th.in_table = 0;
   th.ok = 1;
@@ -387,28 +398,52 @@ __device__ inline void eos_invert(const EosDev& e, int mode, const double in[4],
   if (e.kind == EOS_CONFORMAL) {
     const double T = mode == 0 ? cbrt(3.0 * in[0] / (4.0 * e.fstar)) : pow(in[0] / e.fstar, 0.25);
     thermo_fill(e, false, T, zero, th);
+    if (warm_out) {
+      warm_out[W_GT] = T;
+      warm_out[W_GMUB] = warm_out[W_GMUS] = warm_out[W_GMUQ] = 0.0;
+      warm_out[W_TT] = warm_out[W_TMUB] = warm_out[W_TMUS] = warm_out[W_TMUQ] = 0.0;
+    }
     return;
   }
   const double ag = 19.0 * CCAKE_PI * CCAKE_PI / 36.0;
   double tgt[4] = {in[0], NQ > 0 ? in[1] : 0.0, NQ > 0 ? in[2] : 0.0, NQ > 0 ? in[3] : 0.0};
+  const bool warm_gas = warm && warm[W_GT] > 0.0 && finite4(warm + W_GT);
   double x[4];
-  if (warm && warm[0] > 0.0 && isfinite(warm[0]) && isfinite(warm[1]) && isfinite(warm[2]) && isfinite(warm[3])) {
-    x[0] = warm[0];
-    x[1] = NQ > 0 ? warm[1] : 0.0;
-    x[2] = NQ > 0 ? warm[2] : 0.0;
-    x[3] = NQ > 0 ? warm[3] : 0.0;
+  if (warm_gas) {
+    x[0] = warm[W_GT];
+    x[1] = NQ > 0 ? warm[W_GMUB] : 0.0;
+    x[2] = NQ > 0 ? warm[W_GMUS] : 0.0;
+    x[3] = NQ > 0 ? warm[W_GMUQ] : 0.0;
   } else {
     x[0] = mode == 0 ? cbrt(in[0] / (4.0 * ag)) : pow(in[0] / (3.0 * ag), 0.25);
     x[1] = x[2] = x[3] = 0.0;
   }
   double sn[4];
   bool ok = newton<NQ>(e, false, mode, tgt, x, e.max_iter * 4, &th.iters, sn);
+  if (warm_out) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) warm_out[W_GT + k] = x[k];
+    warm_out[W_TT] = warm_out[W_TMUB] = warm_out[W_TMUS] = warm_out[W_TMUQ] = 0.0;
+  }
   if (e.kind == EOS_TABLE && ok && in_axes(e, x)) {
     double xt[4] = {x[0], x[1], x[2], x[3]};
+    if (warm_gas && warm[W_TT] > 0.0 && finite4(warm + W_TT)) {
+      double xs[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) xs[k] = warm[W_TT + k] + (x[k] - warm[W_GT + k]);
+      if (xs[0] > 0.0 && in_axes(e, xs)) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xt[k] = NQ > 0 || k == 0 ? xs[k] : 0.0;
+      }
+    }
     bool okt = newton<NQ>(e, true, mode, tgt, xt, e.max_iter, &th.iters, sn);
     if (okt && in_axes(e, xt)) {
       thermo_fill(e, true, xt[0], xt + 1, th, sn);
       th.in_table = 1;
+      if (warm_out) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) warm_out[W_TT + k] = xt[k];
+      }
       return;
     }
   }

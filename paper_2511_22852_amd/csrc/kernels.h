@@ -14,7 +14,6 @@ hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t
 hipError_t launch_passes(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, int which,
                          double* fout, double* aux, hipStream_t s, const hipEvent_t* marks = nullptr);
 hipError_t launch_advance(const BatchDev& b, hipStream_t s);
-hipError_t launch_reset_stage_counters(const BatchDev& b, hipStream_t s);
 // only_event >= 0 restricts the initialisation to that event
 hipError_t launch_init(const BatchDev& b, const Params& prm, const EosDev& eos, int dens_kind, const double* dens,
                        int64_t nslots, hipStream_t s, int only_event = -1);

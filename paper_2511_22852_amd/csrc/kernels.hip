@@ -17,13 +17,6 @@ __global__ void k_advance(BatchDev b) {
   b.evt[e].t += b.evt[e].dt;
 }
 
-__global__ void k_reset_stage_counters(BatchDev b) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= b.max_events) return;
-  b.evt[e].backup = 0;
-  b.evt[e].newton_iters = 0;
-}
-
 // Initialisation with m_b = 1 ("SPH interpretation of a fluid element"):
 // sigma*_a = sum_b W_ab, S_a = s_a gamma_a sqrt(-g) / sigma*_a, N_a likewise,
 // Pi = pi = 0 (sorted order; only_event >= 0 restricts to one event)
@@ -200,11 +193,6 @@ static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs
 
 hipError_t launch_advance(const BatchDev& b, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(blocks_for(b.max_events, 64)), dim3(64), 0, s, b);
-  return hipGetLastError();
-}
-
-hipError_t launch_reset_stage_counters(const BatchDev& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_stage_counters, dim3(blocks_for(b.max_events, 64)), dim3(64), 0, s, b);
   return hipGetLastError();
 }
 

@@ -447,7 +447,6 @@ extern "C" ccake_status ccake_time(const ccake_sim* s, double* t) {
 static const int PROF_MARKS = 12;  // 2 around the binning, 5 around each stage's kernels
 
 static ccake_status enqueue_step(ccake_sim* s, const hipEvent_t* marks) {
-  HIPCHK(s, launch_reset_stage_counters(s->b, s->stream));
   HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream, marks));
   HIPCHK(s, launch_passes(s->b, s->prm, s->eos, s->n, 0, nullptr, nullptr, s->stream, marks ? marks + 2 : nullptr));
   HIPCHK(s, launch_advance(s->b, s->stream));
@@ -571,6 +570,7 @@ extern "C" ccake_status ccake_step(ccake_sim* s, double dt, int32_t nsteps) {
 }
 
 static_assert(CCAKE_MAX_SOURCES == MAX_SOURCES, "source table size");
+static_assert(CCAKE_NAUX == NAUXROW, "diagnostic rows");
 
 extern "C" ccake_status ccake_set_sources(ccake_sim* s, int32_t nsrc, const ccake_source* src) {
   if (!s) return CCAKE_E_ARG;
@@ -618,7 +618,6 @@ static ccake_status evaluate(ccake_sim* s, bool rates) {
   if (!s->initialised) return fail(s, CCAKE_E_STATE, "not initialised");
   double* aux = (double*)(s->base + s->L.aux);
   HIPCHK(s, hipMemsetAsync(aux, 0, sizeof(double) * NAUXROW * s->n, s->stream));
-  HIPCHK(s, launch_reset_stage_counters(s->b, s->stream));
   HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream));
   HIPCHK(s, launch_passes(s->b, s->prm, s->eos, s->n, 1, rates ? s->b.Y1 : nullptr, aux, s->stream));
   return CCAKE_OK;

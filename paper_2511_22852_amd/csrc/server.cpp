@@ -299,8 +299,7 @@ static void worker_loop(ccake_server* s) {
       }
     if (!any) continue;
     const int64_t nslots = s->palloc.high_water();
-    hipError_t he = launch_reset_stage_counters(s->b, s->stream);
-    if (he == hipSuccess) he = launch_bin(s->b, s->prm, s->max_events, nslots, live_rows(s->prm), s->stream);
+    hipError_t he = launch_bin(s->b, s->prm, s->max_events, nslots, live_rows(s->prm), s->stream);
     if (he == hipSuccess) he = launch_passes(s->b, s->prm, s->eos, nslots, 0, nullptr, nullptr, s->stream);
     if (he == hipSuccess) he = launch_advance(s->b, s->stream);
     s->steps += 1;

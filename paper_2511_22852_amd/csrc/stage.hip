@@ -21,6 +21,8 @@
 // the pair test itself is always the exact FP64 one.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "eom_device.h"
 #include "eos_device.h"
@@ -29,9 +31,28 @@
 
 namespace ccake {
 
+// lanes per particle in the pair loops (2D, 3D)
+#ifndef CCAKE_TEAM2
+#define CCAKE_TEAM2 8
+#endif
+#ifndef CCAKE_TEAM3
+#define CCAKE_TEAM3 16
+#endif
 template <int D>
 struct Team {
-  static constexpr int L = D == 2 ? 8 : 16;
+  static constexpr int L = D == 2 ? CCAKE_TEAM2 : CCAKE_TEAM3;
+};
+
+// candidates each lane of a team loads ahead in the pair loops (2D, 3D)
+#ifndef CCAKE_PAIR_U2
+#define CCAKE_PAIR_U2 4
+#endif
+#ifndef CCAKE_PAIR_U3
+#define CCAKE_PAIR_U3 2
+#endif
+template <int D>
+struct PairU {
+  static constexpr int U = D == 2 ? CCAKE_PAIR_U2 : CCAKE_PAIR_U3;
 };
 
 // first candidate of this lane in range [lo, hi) given acc candidates before it
@@ -72,6 +93,7 @@ template <int D, bool MIXED>
 __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const double* __restrict__ Y,
                                                  int64_t nslots) {
   constexpr int L = Team<D>::L;
+  constexpr int PAIR_U = PairU<D>::U;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
   const int lane = (int)(tid % L);
@@ -91,31 +113,47 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   int nnb = 0, acc = 0;
   for (int r = 0; r < blk.nr; ++r) {
     const int32_t lo = blk.lo[r], hi = blk.hi[r];
-    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
-      const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
-      const double d2 = dist2<D>(xa, xb);
-      if (!(d2 < r2max)) continue;
-      ++nnb;
-      if (MIXED) {
-        const float W = spline_wf(sqrtf((float)d2) * (float)ih);
-        ks.add(W);
-        if (smoothed) {
-          kt.add((float)row(Y, cap, R_S, k) * W);
-          if (nq) {
-            kn0.add((float)row(Y, cap, R_NB, k) * W);
-            kn1.add((float)row(Y, cap, R_NS, k) * W);
-            kn2.add((float)row(Y, cap, R_NQ, k) * W);
+    // U candidates per lane per pass: all their loads are issued before any
+    // is used (indices past the range re-read the last slot and are dropped),
+    // and the candidates are then accumulated in the same order as singly
+    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += PAIR_U * L) {
+      double xb[PAIR_U][3], sb[PAIR_U], nb[PAIR_U][3];
+#pragma unroll
+      for (int u = 0; u < PAIR_U; ++u) {
+        const int32_t kk = min(k + u * L, hi - 1);
+        xb[u][0] = row(Y, cap, R_X1, kk);
+        xb[u][1] = row(Y, cap, R_X2, kk);
+        xb[u][2] = D == 3 ? row(Y, cap, R_X3, kk) : 0.0;
+        sb[u] = smoothed ? row(Y, cap, R_S, kk) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) nb[u][q] = nq ? row(Y, cap, R_NB + q, kk) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PAIR_U; ++u) {
+        const double d2 = dist2<D>(xa, xb[u]);
+        if (!(k + u * L < hi && d2 < r2max)) continue;
+        ++nnb;
+        if (MIXED) {
+          const float W = spline_wf(sqrtf((float)d2) * (float)ih);
+          ks.add(W);
+          if (smoothed) {
+            kt.add((float)sb[u] * W);
+            if (nq) {
+              kn0.add((float)nb[u][0] * W);
+              kn1.add((float)nb[u][1] * W);
+              kn2.add((float)nb[u][2] * W);
+            }
           }
-        }
-      } else {
-        const double W = spline_w(sqrt(d2) * ih);
-        ss += W;
-        if (smoothed) {
-          st += row(Y, cap, R_S, k) * W;
-          if (nq) {
-            sn0 += row(Y, cap, R_NB, k) * W;
-            sn1 += row(Y, cap, R_NS, k) * W;
-            sn2 += row(Y, cap, R_NQ, k) * W;
+        } else {
+          const double W = spline_w(sqrt(d2) * ih);
+          ss += W;
+          if (smoothed) {
+            st += sb[u] * W;
+            if (nq) {
+              sn0 += nb[u][0] * W;
+              sn1 += nb[u][1] * W;
+              sn2 += nb[u][2] * W;
+            }
           }
         }
       }
@@ -183,15 +221,14 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
       for (int q = 0; q < 3; ++q) dens[1 + q] = row(Y, cap, R_NB + q, j) * sigma;
   }
 
-  // EoS inversion (s, n) -> (T, mu), warm-started from the particle's last root
-  double warm[4];
+  // EoS inversion (s, n) -> (T, mu), warm-started from the particle's last roots
+  double warm[NWARM], wnew[NWARM];
 #pragma unroll
-  for (int w = 0; w < 4; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
+  for (int w = 0; w < NWARM; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
   Thermo th;
-  eos_invert<NQ>(eos, 0, dens, warm, th);
-  b.warms[(int64_t)W_T * cap + j] = th.T;
+  eos_invert<NQ>(eos, 0, dens, warm, th, wnew);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) b.warms[(int64_t)(W_MUB + q) * cap + j] = th.mu[q];
+  for (int w = 0; w < NWARM; ++w) b.warms[(int64_t)w * cap + j] = wnew[w];
   c_noconv = th.ok ? 0u : 1u;
   c_backup = (!th.in_table && eos.kind == EOS_TABLE) ? 1u : 0u;
   c_iters = (uint32_t)th.iters;
@@ -284,6 +321,7 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
     aux[X_INTABLE * n + ii] = th.in_table;
     aux[X_GAMMA * n + ii] = gam;
     aux[X_NNB * n + ii] = b.dsum[(int64_t)DS_NNB * cap + j];
+    aux[X_NEWTON * n + ii] = th.iters;
   }
 }
 
@@ -305,6 +343,7 @@ template <int D, bool VISC, bool MIXED>
 __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
                                               int64_t nslots) {
   constexpr int L = Team<D>::L;
+  constexpr int PAIR_U = PairU<D>::U;
   constexpr int NA = D * D;  // viscous components A^{ji}
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
@@ -351,65 +390,90 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
     }
   }
   int acc = 0;
+  // neighbour record of a candidate in the pass's precision
+  using RT = typename std::conditional<MIXED, float, double>::type;
+  const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
   for (int r = 0; r < blk.nr; ++r) {
     const int32_t lo = blk.lo[r], hi = blk.hi[r];
-    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
-      const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
-      const double d2 = dist2<D>(xa, xb);
-      if (!(d2 < r2max)) continue;
-      if (MIXED) {
-        const float rr = sqrtf((float)d2);
-        if (!(rr > 0.0f)) continue;
-        const float f = spline_dwf(rr * (float)ih) / rr;
-        float dW[3];
+    // U candidates per lane per pass, loads first (see k_density)
+    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += PAIR_U * L) {
+      double xb[PAIR_U][3];
+      RT bpp[PAIR_U], bA[PAIR_U][3][3], bU[PAIR_U][3], bV[PAIR_U][3];
 #pragma unroll
-        for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[q]) * f;
-        const float pp = (float)aPP + b.recf[(int64_t)Q_PP * cap + k];
+      for (int u = 0; u < PAIR_U; ++u) {
+        const int64_t kk = min(k + u * L, hi - 1);
+        xb[u][0] = row(Y, cap, R_X1, kk);
+        xb[u][1] = row(Y, cap, R_X2, kk);
+        xb[u][2] = D == 3 ? row(Y, cap, R_X3, kk) : 0.0;
+        bpp[u] = rb[(int64_t)Q_PP * cap + kk];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-          float val = pp * dW[i];
-          if (VISC) {
-            float vis = 0.f;
+        for (int q = 0; q < D; ++q) {
+          bU[u][q] = rb[(int64_t)(Q_U1 + q) * cap + kk];
+          bV[u][q] = rb[(int64_t)(Q_V1 + q) * cap + kk];
+        }
+        if (VISC) {
 #pragma unroll
-            for (int jj = 0; jj < D; ++jj)
-              vis += ((float)aA[jj][i] + b.recf[(int64_t)(Q_A11 + jj * 3 + i) * cap + k]) * dW[jj];
-            val += (float)Gk[i + 1] * vis;
+          for (int jj = 0; jj < D; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < D; ++ii) bA[u][jj][ii] = rb[(int64_t)(Q_A11 + jj * 3 + ii) * cap + kk];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PAIR_U; ++u) {
+        const double d2 = dist2<D>(xa, xb[u]);
+        if (!(k + u * L < hi && d2 < r2max)) continue;
+        if (MIXED) {
+          const float rr = sqrtf((float)d2);
+          if (!(rr > 0.0f)) continue;
+          const float f = spline_dwf(rr * (float)ih) / rr;
+          float dW[3];
+#pragma unroll
+          for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[u][q]) * f;
+          const float pp = (float)aPP + bpp[u];
+#pragma unroll
+          for (int i = 0; i < D; ++i) {
+            float val = pp * dW[i];
+            if (VISC) {
+              float vis = 0.f;
+#pragma unroll
+              for (int jj = 0; jj < D; ++jj) vis += ((float)aA[jj][i] + bA[u][jj][i]) * dW[jj];
+              val += (float)Gk[i + 1] * vis;
+            }
+            kF[i].add(val);
           }
-          kF[i].add(val);
-        }
-        float dvv = 0.f;
+          float dvv = 0.f;
 #pragma unroll
-        for (int kk = 0; kk < D; ++kk) {
+          for (int kk = 0; kk < D; ++kk) {
 #pragma unroll
-          for (int nu = 0; nu < D; ++nu)
-            kdu[kk][nu].add((b.recf[(int64_t)(Q_U1 + nu) * cap + k] - (float)aU[nu]) * dW[kk]);
-          dvv += (b.recf[(int64_t)(Q_V1 + kk) * cap + k] - (float)aV[kk]) * dW[kk];
-        }
-        kdv.add(dvv);
-      } else {
-        const double rr = sqrt(d2);
-        if (!(rr > 0.0)) continue;
-        const double f = spline_dw(rr * ih) / rr;
-        double dW[3];
-#pragma unroll
-        for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[q]) * f;
-        const double pp = aPP + b.rec[(int64_t)Q_PP * cap + k];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-          double val = pp * dW[i];
-          if (VISC) {
-            double vis = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < D; ++jj) vis += (aA[jj][i] + b.rec[(int64_t)(Q_A11 + jj * 3 + i) * cap + k]) * dW[jj];
-            val += Gk[i + 1] * vis;
+            for (int nu = 0; nu < D; ++nu) kdu[kk][nu].add((bU[u][nu] - (float)aU[nu]) * dW[kk]);
+            dvv += (bV[u][kk] - (float)aV[kk]) * dW[kk];
           }
-          F[i] += val;
-        }
+          kdv.add(dvv);
+        } else {
+          const double rr = sqrt(d2);
+          if (!(rr > 0.0)) continue;
+          const double f = spline_dw(rr * ih) / rr;
+          double dW[3];
 #pragma unroll
-        for (int kk = 0; kk < D; ++kk) {
+          for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[u][q]) * f;
+          const double pp = aPP + bpp[u];
 #pragma unroll
-          for (int nu = 0; nu < D; ++nu) du[kk][nu] += (b.rec[(int64_t)(Q_U1 + nu) * cap + k] - aU[nu]) * dW[kk];
-          dv += (b.rec[(int64_t)(Q_V1 + kk) * cap + k] - aV[kk]) * dW[kk];
+          for (int i = 0; i < D; ++i) {
+            double val = pp * dW[i];
+            if (VISC) {
+              double vis = 0.0;
+#pragma unroll
+              for (int jj = 0; jj < D; ++jj) vis += (aA[jj][i] + bA[u][jj][i]) * dW[jj];
+              val += Gk[i + 1] * vis;
+            }
+            F[i] += val;
+          }
+#pragma unroll
+          for (int kk = 0; kk < D; ++kk) {
+#pragma unroll
+            for (int nu = 0; nu < D; ++nu) du[kk][nu] += (bU[u][nu] - aU[nu]) * dW[kk];
+            dv += (bV[u][kk] - aV[kk]) * dW[kk];
+          }
         }
       }
     }
