@@ -231,12 +231,17 @@ class Eos:
 class Sim:
     """One SPH event on the GPU: workspace from torch, its own HIP stream."""
 
-    def __init__(self, cfg: Config, eos: Eos, n: int, device="cuda:0"):
+    def __init__(self, cfg: Config, eos: Eos, n: int, device="cuda:0", fill=None):
+        """fill: optional byte value written over the whole workspace before
+        the simulation is created (results must not depend on it)."""
         import torch
         self.cfg, self.eos, self.n, self.device = cfg, eos, int(n), torch.device(device)
         nb = ctypes.c_size_t()
         _check(lib().ccake_workspace_bytes(ctypes.byref(cfg), self.n, ctypes.byref(nb)), what="workspace_bytes")
         self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        if fill is not None:
+            self.ws.fill_(int(fill))
+            torch.cuda.synchronize(self.device)
         base = self.ws.data_ptr()
         self.base = (base + 255) & ~255
         self.stream = torch.cuda.Stream(device=self.device)

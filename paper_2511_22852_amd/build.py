@@ -13,6 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libccake_hip.so")
+DRIVER = os.path.join(PKG, "ccake_bench")
 SOURCES = ["binning.hip", "stage.hip", "kernels.hip", "runtime.cpp", "server.cpp"]
 ARCH = os.environ.get("CCAKE_OFFLOAD_ARCH", "gfx950")
 
@@ -45,6 +46,11 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
+    # native driver of the C ABI (no Python in the process), linked to the library
+    tmp = DRIVER + ".tmp"
+    _run(["hipcc", *HIPCC_FLAGS, "-o", tmp, os.path.join(CSRC, "ccake_bench.cpp"), f"-L{PKG}", "-lccake_hip",
+          "-Wl,-rpath,$ORIGIN"])
+    os.replace(tmp, DRIVER)
     return LIB
 
 

@@ -275,6 +275,10 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
   T_[(int64_t)T_E * cap + j] = th.e;
   T_[(int64_t)T_CS2 * cap + j] = th.cs2;
   T_[(int64_t)T_KAP * cap + j] = th.kappa;
+  if (NQ) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) T_[(int64_t)(T_MUB + q) * cap + j] = th.mu[q];
+  }
   if (VISC) {
     T_[(int64_t)T_PI * cap + j] = Pi;
     T_[(int64_t)T_ETA * cap + j] = eta;
@@ -612,9 +616,12 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     in.Iq[q] = 0.0;
-    in.mu[q] = q < prm.ncharge ? T_[(int64_t)(T_MUB + q) * cap + j] : 0.0;
+    in.mu[q] = 0.0;
   }
-  if (prm.src) {
+  // the chemical potentials enter only through the charge sources
+  if (prm.src && prm.src->n > 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) in.mu[q] = q < prm.ncharge ? T_[(int64_t)(T_MUB + q) * cap + j] : 0.0;
     double x[3];
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = row(Y, cap, R_X1 + k, j);

@@ -358,3 +358,22 @@ def test_viscous_gubser_trajectory_fp64(B, O):
     yg = sim.get_state()
     for r in (O.V_X1, O.V_U1, O.V_U2, O.V_S, O.V_P11, O.V_P12, O.V_P22, O.V_P33):
         assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_workspace_contents_do_not_matter(B, O, precision):
+    """A workspace full of NaN bit patterns (0xFF bytes) and a zeroed one give
+    bit-identical rates and steps: nothing is read before it is written."""
+    prm, oe, cfg, ge, y, t0 = prepared(B, O, "lumpy2d_visc_table_backup", precision=precision)
+    out = []
+    for fill in (0xFF, 0x00):
+        sim = B.Sim(cfg, ge, y.shape[1], fill=fill)
+        sim.set_state(t0, y)
+        f, aux = sim.rhs()
+        sim.step(0.005, 3)
+        sim.check()
+        out.append((f, aux, sim.get_state()))
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.isfinite(a).all()
+        assert np.array_equal(a, b)
