@@ -263,6 +263,28 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes": n}))
 
 
+def write_inputs(path):
+    """The headline workload in the native driver's file format (see
+    paper_2511_22852_amd/csrc/ccake_bench.cpp)."""
+    import struct
+    import numpy as np
+    from paper_2511_22852_amd import binding as B
+    from paper_2511_22852_amd import inputs as I
+    w = I.lumpy_2d_workload()
+    cols, lo, hi = I.massless_gas_table()
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, precision=B.MIXED, ncharge=3, h=w.h,
+                   eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02)
+    with open(path, "wb") as f:
+        f.write(b"CCAKEBN1")
+        f.write(bytes(cfg))
+        f.write(struct.pack("<qddii", w.n, w.t0, w.dt, w.dens_kind, 0))
+        f.write(struct.pack("<4i", *cols.shape[1:]))
+        f.write(np.asarray(lo, dtype="<f8").tobytes() + np.asarray(hi, dtype="<f8").tobytes())
+        for a in (cols, w.xi, w.u, w.dens):
+            f.write(np.ascontiguousarray(a, dtype="<f8").tobytes())
+    print(json.dumps({"workload_file": path, "particles": w.n}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +298,9 @@ def main():
                     help="timed steps of each 3+1D configuration (0 = skip them)")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both",
                     help="which precisions to run (counter-collection passes use one)")
+    ap.add_argument("--write-inputs", metavar="PATH",
+                    help="only write the headline workload (mixed precision) for the native driver "
+                         "paper_2511_22852_amd/ccake_bench and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (reference kernel for the HBM "
                          "byte counters) and exit")
@@ -286,6 +311,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.write_inputs:
+        write_inputs(args.write_inputs)
         return
 
     from paper_2511_22852_amd import binding as B
@@ -349,7 +377,9 @@ def main():
         "kernel_ms_per_step": {"mixed": [m / args.steps for m in head["ms"]],
                                "fp64": [m / args.steps for m in res["fp64"]["ms"]],
                                "groups": names},
-        "eos_backup_fraction_last_stage": head["backup"] / w.n,
+        # counters of the last step: both Heun stages invert every particle once
+        "eos_backup_fraction_last_step": head["backup"] / (2 * w.n),
+        "eos_mean_newton_iterations_last_step": head["newton_iters"] / (2 * w.n),
         "roofline": roof,
     }
     if args.steps_3d > 0:

@@ -111,7 +111,7 @@ __global__ void k_grid(BatchDev b, Params prm, int dim) {
     for (int k = 0; k < 3; ++k) lo[k] = hi[k] = 0.0;
     if (E->n > 0) E->capacity_err += 1;  // every coordinate non-finite
   }
-  double edge = prm.cell_edge;
+  double edge = prm.cell_edge / SUBCELLS;
   int64_t nc[3] = {1, 1, 1}, tot = 1;
   // coarsen the grid (never below the cutoff) until it fits the capacity
   for (int it = 0; it < 64; ++it) {

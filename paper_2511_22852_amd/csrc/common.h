@@ -79,6 +79,13 @@ struct SourceSet {
   SourceDev s[MAX_SOURCES];
 };
 
+// cells per kernel support along an axis: the grid cell edge is
+// (2h + skin) / SUBCELLS and a particle's candidates lie within SUBCELLS cells
+#ifndef CCAKE_SUBCELLS
+#define CCAKE_SUBCELLS 2
+#endif
+constexpr int SUBCELLS = CCAKE_SUBCELLS;
+
 struct Params {
   int32_t dim, hyperbolic, viscous, ncharge, density_mode, mixed;
   double h;

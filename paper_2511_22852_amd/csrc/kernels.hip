@@ -33,15 +33,14 @@ __global__ void __launch_bounds__(128) k_init(BatchDev b, Params prm, EosDev eos
   const double* Y = b.Ys;
   const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
   const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
-  Block<D> blk;
-  neighbour_block<D>(b, E, b.keys[j], blk);
   double ss = 0.0;
-  for (int r = 0; r < blk.nr; ++r)
-    for (int32_t k = blk.lo[r]; k < blk.hi[r]; ++k) {
+  for_each_row<D>(b, E, b.keys[j], xa, prm.cell_edge, [&](int32_t lo, int32_t hi) {
+    for (int32_t k = lo; k < hi; ++k) {
       const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
       const double d2 = dist2<D>(xa, xb);
       if (d2 < r2max) ss += spline_w(sqrt(d2) * ih);
     }
+  });
   ss *= sigma_d<D>(h);
   const double G3 = metric_G3(prm, t);
   const double u1 = row(Y, cap, R_U1, j), u2 = row(Y, cap, R_U2, j), u3 = D == 3 ? row(Y, cap, R_U3, j) : 0.0;
@@ -75,10 +74,8 @@ __global__ void __launch_bounds__(256) k_pairs(BatchDev b, Params prm, int e, in
   const double* Y = b.Ys;
   const double h = prm.h, r2max = (2.0 * h) * (2.0 * h);
   const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
-  Block<D> blk;
-  neighbour_block<D>(b, E, b.keys[j], blk);
-  for (int r = 0; r < blk.nr; ++r)
-    for (int32_t k = blk.lo[r]; k < blk.hi[r]; ++k) {
+  for_each_row<D>(b, E, b.keys[j], xa, prm.cell_edge, [&](int32_t lo, int32_t hi) {
+    for (int32_t k = lo; k < hi; ++k) {
       const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
       if (dist2<D>(xa, xb) < r2max) {
         const int64_t slot = (int64_t)atomicAdd((unsigned long long*)counter, 1ull);
@@ -88,6 +85,7 @@ __global__ void __launch_bounds__(256) k_pairs(BatchDev b, Params prm, int e, in
         }
       }
     }
+  });
 }
 
 // state rows of one event in the caller's order

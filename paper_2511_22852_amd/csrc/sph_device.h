@@ -126,30 +126,49 @@ __device__ inline void wave_count_eos(EventDev* evt, int e, uint32_t backup, uin
   }
 }
 
-// neighbour block of a particle: 3^(D-1) contiguous slot ranges (x-rows of cells)
-template <int D>
-struct Block {
-  int32_t lo[D == 3 ? 9 : 3], hi[D == 3 ? 9 : 3];
-  int nr;
-};
+// Distance from v to the interval [c0, c0 + e] (zero inside).
+__device__ __forceinline__ double interval_gap(double v, double c0, double e) {
+  const double below = c0 - v, above = v - (c0 + e);
+  return below > 0.0 ? below : (above > 0.0 ? above : 0.0);
+}
 
-template <int D>
-__device__ __forceinline__ void neighbour_block(const BatchDev& b, const EventDev& E, int32_t key, Block<D>& blk) {
+// Candidate slot ranges of a particle at xa whose binning cell is key: the
+// x-rows of cells within SUBCELLS cells in y (and z), each row trimmed to the
+// cells that intersect the ball of radius reach around xa.  Cells of a row
+// are contiguous in slot order (x is the fastest axis of the key), so each
+// row is one range [lo, hi).  reach must cover the kernel support plus the
+// displacement allowed since binning (the skin); the exact pair test is made
+// on every candidate, so the trimming only has to be conservative, which the
+// relative margin on reach guarantees against rounding.  f(lo, hi) is called
+// for every non-empty row in increasing slot order.
+template <int D, class F>
+__device__ __forceinline__ void for_each_row(const BatchDev& b, const EventDev& E, int32_t key, const double xa[3],
+                                             double reach, F&& f) {
   const int nx = E.nc[0], ny = E.nc[1], nz = D == 3 ? E.nc[2] : 1;
   const int ix = key % nx;
   const int iy = (key / nx) % ny;
   const int iz = D == 3 ? key / (nx * ny) : 0;
-  const int x0 = ix > 0 ? ix - 1 : 0, x1 = ix + 1 < nx ? ix + 1 : nx - 1;
-  blk.nr = 0;
+  const double e = E.edge, ie = 1.0 / e;
+  const double R = reach * (1.0 + 1e-9);
+  const double R2 = R * R;
   const int32_t* cs = b.cell_start + E.c_base;
-  for (int z = (D == 3 ? iz - 1 : 0); z <= (D == 3 ? iz + 1 : 0); ++z) {
+  for (int dz = (D == 3 ? -SUBCELLS : 0); dz <= (D == 3 ? SUBCELLS : 0); ++dz) {
+    const int z = iz + dz;
     if (z < 0 || z >= nz) continue;
-    for (int y = iy - 1; y <= iy + 1; ++y) {
+    const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
+    for (int dy = -SUBCELLS; dy <= SUBCELLS; ++dy) {
+      const int y = iy + dy;
       if (y < 0 || y >= ny) continue;
+      const double gy = interval_gap(xa[1], E.lo[1] + y * e, e);
+      const double r2 = R2 - gy * gy - gz * gz;
+      if (!(r2 >= 0.0)) continue;
+      const double rx = sqrt(r2) * (1.0 + 1e-9);
+      int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
+      x0 = max(x0, max(ix - SUBCELLS, 0));
+      x1 = min(x1, min(ix + SUBCELLS, nx - 1));
+      if (x0 > x1) continue;
       const int c = (z * ny + y) * nx;
-      blk.lo[blk.nr] = cs[c + x0];
-      blk.hi[blk.nr] = cs[c + x1 + 1];
-      ++blk.nr;
+      f(cs[c + x0], cs[c + x1 + 1]);
     }
   }
 }

@@ -21,8 +21,6 @@
 // the pair test itself is always the exact FP64 one.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "common.h"
 #include "eom_device.h"
 #include "eos_device.h"
@@ -33,7 +31,7 @@ namespace ccake {
 
 // lanes per particle in the pair loops (2D, 3D)
 #ifndef CCAKE_TEAM2
-#define CCAKE_TEAM2 8
+#define CCAKE_TEAM2 16
 #endif
 #ifndef CCAKE_TEAM3
 #define CCAKE_TEAM3 16
@@ -41,18 +39,6 @@ namespace ccake {
 template <int D>
 struct Team {
   static constexpr int L = D == 2 ? CCAKE_TEAM2 : CCAKE_TEAM3;
-};
-
-// candidates each lane of a team loads ahead in the pair loops (2D, 3D)
-#ifndef CCAKE_PAIR_U2
-#define CCAKE_PAIR_U2 4
-#endif
-#ifndef CCAKE_PAIR_U3
-#define CCAKE_PAIR_U3 2
-#endif
-template <int D>
-struct PairU {
-  static constexpr int U = D == 2 ? CCAKE_PAIR_U2 : CCAKE_PAIR_U3;
 };
 
 // first candidate of this lane in range [lo, hi) given acc candidates before it
@@ -93,7 +79,6 @@ template <int D, bool MIXED>
 __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const double* __restrict__ Y,
                                                  int64_t nslots) {
   constexpr int L = Team<D>::L;
-  constexpr int PAIR_U = PairU<D>::U;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
   const int lane = (int)(tid % L);
@@ -106,60 +91,41 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   const bool smoothed = prm.density_mode == 0;
   const int nq = smoothed ? prm.ncharge : 0;
   const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
-  Block<D> blk;
-  neighbour_block<D>(b, E, b.keys[j], blk);
   double ss = 0.0, st = 0.0, sn0 = 0.0, sn1 = 0.0, sn2 = 0.0;
   Kahan ks{0.f, 0.f}, kt{0.f, 0.f}, kn0{0.f, 0.f}, kn1{0.f, 0.f}, kn2{0.f, 0.f};
   int nnb = 0, acc = 0;
-  for (int r = 0; r < blk.nr; ++r) {
-    const int32_t lo = blk.lo[r], hi = blk.hi[r];
-    // U candidates per lane per pass: all their loads are issued before any
-    // is used (indices past the range re-read the last slot and are dropped),
-    // and the candidates are then accumulated in the same order as singly
-    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += PAIR_U * L) {
-      double xb[PAIR_U][3], sb[PAIR_U], nb[PAIR_U][3];
-#pragma unroll
-      for (int u = 0; u < PAIR_U; ++u) {
-        const int32_t kk = min(k + u * L, hi - 1);
-        xb[u][0] = row(Y, cap, R_X1, kk);
-        xb[u][1] = row(Y, cap, R_X2, kk);
-        xb[u][2] = D == 3 ? row(Y, cap, R_X3, kk) : 0.0;
-        sb[u] = smoothed ? row(Y, cap, R_S, kk) : 0.0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) nb[u][q] = nq ? row(Y, cap, R_NB + q, kk) : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < PAIR_U; ++u) {
-        const double d2 = dist2<D>(xa, xb[u]);
-        if (!(k + u * L < hi && d2 < r2max)) continue;
-        ++nnb;
-        if (MIXED) {
-          const float W = spline_wf(sqrtf((float)d2) * (float)ih);
-          ks.add(W);
-          if (smoothed) {
-            kt.add((float)sb[u] * W);
-            if (nq) {
-              kn0.add((float)nb[u][0] * W);
-              kn1.add((float)nb[u][1] * W);
-              kn2.add((float)nb[u][2] * W);
-            }
+  for_each_row<D>(b, E, b.keys[j], xa, prm.cell_edge, [&](int32_t lo, int32_t hi) {
+    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
+      const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
+      const double d2 = dist2<D>(xa, xb);
+      if (!(d2 < r2max)) continue;
+      ++nnb;
+      if (MIXED) {
+        const float W = spline_wf(sqrtf((float)d2) * (float)ih);
+        ks.add(W);
+        if (smoothed) {
+          kt.add((float)row(Y, cap, R_S, k) * W);
+          if (nq) {
+            kn0.add((float)row(Y, cap, R_NB, k) * W);
+            kn1.add((float)row(Y, cap, R_NS, k) * W);
+            kn2.add((float)row(Y, cap, R_NQ, k) * W);
           }
-        } else {
-          const double W = spline_w(sqrt(d2) * ih);
-          ss += W;
-          if (smoothed) {
-            st += sb[u] * W;
-            if (nq) {
-              sn0 += nb[u][0] * W;
-              sn1 += nb[u][1] * W;
-              sn2 += nb[u][2] * W;
-            }
+        }
+      } else {
+        const double W = spline_w(sqrt(d2) * ih);
+        ss += W;
+        if (smoothed) {
+          st += row(Y, cap, R_S, k) * W;
+          if (nq) {
+            sn0 += row(Y, cap, R_NB, k) * W;
+            sn1 += row(Y, cap, R_NS, k) * W;
+            sn2 += row(Y, cap, R_NQ, k) * W;
           }
         }
       }
     }
     acc += hi - lo;
-  }
+  });
   if (MIXED) {
     ss = team_sum_k<L>(ks);
     if (smoothed) {
@@ -347,7 +313,6 @@ template <int D, bool VISC, bool MIXED>
 __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
                                               int64_t nslots) {
   constexpr int L = Team<D>::L;
-  constexpr int PAIR_U = PairU<D>::U;
   constexpr int NA = D * D;  // viscous components A^{ji}
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
@@ -380,8 +345,6 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       for (int ii = 0; ii < D; ++ii) aA[jj][ii] = recv(Q_A11 + jj * 3 + ii, j);
   }
 
-  Block<D> blk;
-  neighbour_block<D>(b, E, b.keys[j], blk);
   double F[3] = {0.0, 0.0, 0.0}, du[3][3], dv = 0.0;
   Kahan kF[3], kdu[3][3], kdv{0.f, 0.f};
 #pragma unroll
@@ -394,95 +357,69 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
     }
   }
   int acc = 0;
-  // neighbour record of a candidate in the pass's precision
-  using RT = typename std::conditional<MIXED, float, double>::type;
-  const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
-  for (int r = 0; r < blk.nr; ++r) {
-    const int32_t lo = blk.lo[r], hi = blk.hi[r];
-    // U candidates per lane per pass, loads first (see k_density)
-    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += PAIR_U * L) {
-      double xb[PAIR_U][3];
-      RT bpp[PAIR_U], bA[PAIR_U][3][3], bU[PAIR_U][3], bV[PAIR_U][3];
+  for_each_row<D>(b, E, b.keys[j], xa, prm.cell_edge, [&](int32_t lo, int32_t hi) {
+    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
+      const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
+      const double d2 = dist2<D>(xa, xb);
+      if (!(d2 < r2max)) continue;
+      if (MIXED) {
+        const float rr = sqrtf((float)d2);
+        if (!(rr > 0.0f)) continue;
+        const float f = spline_dwf(rr * (float)ih) / rr;
+        float dW[3];
 #pragma unroll
-      for (int u = 0; u < PAIR_U; ++u) {
-        const int64_t kk = min(k + u * L, hi - 1);
-        xb[u][0] = row(Y, cap, R_X1, kk);
-        xb[u][1] = row(Y, cap, R_X2, kk);
-        xb[u][2] = D == 3 ? row(Y, cap, R_X3, kk) : 0.0;
-        bpp[u] = rb[(int64_t)Q_PP * cap + kk];
+        for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[q]) * f;
+        const float pp = (float)aPP + b.recf[(int64_t)Q_PP * cap + k];
 #pragma unroll
-        for (int q = 0; q < D; ++q) {
-          bU[u][q] = rb[(int64_t)(Q_U1 + q) * cap + kk];
-          bV[u][q] = rb[(int64_t)(Q_V1 + q) * cap + kk];
+        for (int i = 0; i < D; ++i) {
+          float val = pp * dW[i];
+          if (VISC) {
+            float vis = 0.f;
+#pragma unroll
+            for (int jj = 0; jj < D; ++jj)
+              vis += ((float)aA[jj][i] + b.recf[(int64_t)(Q_A11 + jj * 3 + i) * cap + k]) * dW[jj];
+            val += (float)Gk[i + 1] * vis;
+          }
+          kF[i].add(val);
         }
-        if (VISC) {
+        float dvv = 0.f;
 #pragma unroll
-          for (int jj = 0; jj < D; ++jj)
+        for (int kk = 0; kk < D; ++kk) {
 #pragma unroll
-            for (int ii = 0; ii < D; ++ii) bA[u][jj][ii] = rb[(int64_t)(Q_A11 + jj * 3 + ii) * cap + kk];
+          for (int nu = 0; nu < D; ++nu)
+            kdu[kk][nu].add((b.recf[(int64_t)(Q_U1 + nu) * cap + k] - (float)aU[nu]) * dW[kk]);
+          dvv += (b.recf[(int64_t)(Q_V1 + kk) * cap + k] - (float)aV[kk]) * dW[kk];
         }
-      }
+        kdv.add(dvv);
+      } else {
+        const double rr = sqrt(d2);
+        if (!(rr > 0.0)) continue;
+        const double f = spline_dw(rr * ih) / rr;
+        double dW[3];
 #pragma unroll
-      for (int u = 0; u < PAIR_U; ++u) {
-        const double d2 = dist2<D>(xa, xb[u]);
-        if (!(k + u * L < hi && d2 < r2max)) continue;
-        if (MIXED) {
-          const float rr = sqrtf((float)d2);
-          if (!(rr > 0.0f)) continue;
-          const float f = spline_dwf(rr * (float)ih) / rr;
-          float dW[3];
+        for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[q]) * f;
+        const double pp = aPP + b.rec[(int64_t)Q_PP * cap + k];
 #pragma unroll
-          for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[u][q]) * f;
-          const float pp = (float)aPP + bpp[u];
+        for (int i = 0; i < D; ++i) {
+          double val = pp * dW[i];
+          if (VISC) {
+            double vis = 0.0;
 #pragma unroll
-          for (int i = 0; i < D; ++i) {
-            float val = pp * dW[i];
-            if (VISC) {
-              float vis = 0.f;
-#pragma unroll
-              for (int jj = 0; jj < D; ++jj) vis += ((float)aA[jj][i] + bA[u][jj][i]) * dW[jj];
-              val += (float)Gk[i + 1] * vis;
-            }
-            kF[i].add(val);
+            for (int jj = 0; jj < D; ++jj) vis += (aA[jj][i] + b.rec[(int64_t)(Q_A11 + jj * 3 + i) * cap + k]) * dW[jj];
+            val += Gk[i + 1] * vis;
           }
-          float dvv = 0.f;
+          F[i] += val;
+        }
 #pragma unroll
-          for (int kk = 0; kk < D; ++kk) {
+        for (int kk = 0; kk < D; ++kk) {
 #pragma unroll
-            for (int nu = 0; nu < D; ++nu) kdu[kk][nu].add((bU[u][nu] - (float)aU[nu]) * dW[kk]);
-            dvv += (bV[u][kk] - (float)aV[kk]) * dW[kk];
-          }
-          kdv.add(dvv);
-        } else {
-          const double rr = sqrt(d2);
-          if (!(rr > 0.0)) continue;
-          const double f = spline_dw(rr * ih) / rr;
-          double dW[3];
-#pragma unroll
-          for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[u][q]) * f;
-          const double pp = aPP + bpp[u];
-#pragma unroll
-          for (int i = 0; i < D; ++i) {
-            double val = pp * dW[i];
-            if (VISC) {
-              double vis = 0.0;
-#pragma unroll
-              for (int jj = 0; jj < D; ++jj) vis += (aA[jj][i] + bA[u][jj][i]) * dW[jj];
-              val += Gk[i + 1] * vis;
-            }
-            F[i] += val;
-          }
-#pragma unroll
-          for (int kk = 0; kk < D; ++kk) {
-#pragma unroll
-            for (int nu = 0; nu < D; ++nu) du[kk][nu] += (bU[u][nu] - aU[nu]) * dW[kk];
-            dv += (bV[u][kk] - aV[kk]) * dW[kk];
-          }
+          for (int nu = 0; nu < D; ++nu) du[kk][nu] += (b.rec[(int64_t)(Q_U1 + nu) * cap + k] - aU[nu]) * dW[kk];
+          dv += (b.rec[(int64_t)(Q_V1 + kk) * cap + k] - aV[kk]) * dW[kk];
         }
       }
     }
     acc += hi - lo;
-  }
+  });
   (void)NA;
 #pragma unroll
   for (int i = 0; i < D; ++i) F[i] = MIXED ? team_sum_k<L>(kF[i]) : team_sum<L>(F[i]);
