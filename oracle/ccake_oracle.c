@@ -374,8 +374,8 @@ static void mc_eval(const orc_eos *e, double T, const double mu[3], double *p, d
 
 /* Quadrilinear interpolation of table column c at x = (T, muB, muS, muQ);
  * value and gradient with respect to x.  Cells are located by floor and
- * clamped to the grid, so outside the grid the edge cell is extrapolated
- * (callers keep x inside). */
+ * clamped to the grid, so outside the grid the edge cell continues linearly
+ * (the Newton iterates may pass there; accepted roots lie inside). */
 static void tab_interp(const orc_eos *e, int c, const double x[4], double *val, double grad[4])
 {
   const int nn[4] = {e->nT, e->nB, e->nS, e->nQ};
@@ -548,12 +548,13 @@ static double maxabs4(const double r[4])
 }
 
 /* Damped Newton: full step, halved until the max-norm of the scaled residual
- * decreases; iterates clamped to the box when box != 0.  Unknowns are
- * (T, muB, muS, muQ); with nq = 0 only T is solved (mu = 0).
- * Returns 1 when the residual is below tol. */
-static int newton(const inv_ctx *c, double x[4], int box, int nq, int max_iter, double tol, int *iters)
+ * decreases.  Unknowns are (T, muB, muS, muQ); with nq = 0 only T is solved
+ * (mu = 0).  Table iterates are not confined to the axes: outside them the
+ * interpolant continues linearly from the boundary cells, so a root that lies
+ * outside is found as such (and then rejected by the caller) instead of
+ * stalling against the boundary.  Returns 1 when the residual is below tol. */
+static int newton(const inv_ctx *c, double x[4], int nq, int max_iter, double tol, int *iters)
 {
-  const orc_eos *e = c->e;
   int nu = nq > 0 ? 4 : 1;
   double r[4], J[4][4];
   inv_resid(c, x, r, J);
@@ -569,7 +570,6 @@ static int newton(const inv_ctx *c, double x[4], int box, int nq, int max_iter, 
     for (int hv = 0; hv < 40; ++hv) {
       for (int k = 0; k < 4; ++k) xt[k] = x[k] + (k < nu ? lam * dx[k] : 0.0);
       if (xt[0] <= 0.0) xt[0] = 0.5 * x[0];
-      if (box) for (int k = 0; k < 4; ++k) { if (xt[k] < e->lo[k]) xt[k] = e->lo[k]; if (xt[k] > e->hi[k]) xt[k] = e->hi[k]; }
       inv_resid(c, xt, rt, Jt);
       nrt = nq > 0 ? maxabs4(rt) : fabs(rt[0]);
       if (nrt < nr) { accepted = 1; break; }
@@ -617,12 +617,12 @@ static void invert(const orc_eos *e, int mode, int ncharge, const double in[4], 
   double a0 = e->kind == EOS_MODCONF ? e->A0 : 19.0 * M_PI * M_PI / 36.0;
   double x[4] = {mode == 0 ? cbrt(in[0] / (4.0 * a0)) : pow(in[0] / (3.0 * a0), 0.25), 0.0, 0.0, 0.0};
   c.use_table = 0;
-  int ok = newton(&c, x, 0, nq, e->max_iter * 4, e->tol, &th->iters);
+  int ok = newton(&c, x, nq, e->max_iter * 4, e->tol, &th->iters);
   if (e->kind == EOS_TABLE && ok && inside_table(e, x)) {
     double xt[4];
     memcpy(xt, x, sizeof xt);
     c.use_table = 1;
-    int okt = newton(&c, xt, 1, nq, e->max_iter, e->tol, &th->iters);
+    int okt = newton(&c, xt, nq, e->max_iter, e->tol, &th->iters);
     if (okt && inside_table(e, xt)) {
       thermo_at(e, 1, xt[0], xt + 1, th);
       th->in_table = 1;
