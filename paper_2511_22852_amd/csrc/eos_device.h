@@ -19,7 +19,7 @@ namespace ccake {
 
 struct Thermo {
   double T, mu[3], p, e, s, n[3], cs2, kappa;
-  int in_table, iters, ok;
+  int in_table, iters, evals, ok;  // evals: residual evaluations (halvings included)
 };
 
 // flavour charges (B, S, Q) of u, d, s
@@ -269,14 +269,17 @@ __device__ __forceinline__ double maxnorm(const double r[4]) {
 }
 
 // Damped Newton: full step halved until the max-norm of the scaled residual
-// decreases; the table solve keeps iterates inside the table axes.  Unknowns
-// (T, muB, muS, muQ), or T alone without charges.
+// decreases.  Unknowns (T, muB, muS, muQ), or T alone without charges.  Table
+// iterates are not confined to the axes (the interpolant continues linearly
+// from the boundary cells), so a root outside the axes is found as such and
+// rejected by the caller rather than stalling against the boundary.
 template <int NQ>
 __device__ inline bool newton(const EosDev& e, bool use_table, int mode, const double tgt[4], double x[4],
-                              int max_iter, int* iters, double sn[4]) {
+                              int max_iter, int* iters, double sn[4], int* evals) {
   constexpr int NU = NQ > 0 ? 4 : 1;
   double r[4], J[4][4];
   inv_resid(e, use_table, mode, tgt, x, r, J, sn);
+  int nev = 1;
   double nr = maxnorm<NU>(r);
   int it = 0;
   for (; it < max_iter; ++it) {
@@ -289,11 +292,8 @@ __device__ inline bool newton(const EosDev& e, bool use_table, int mode, const d
 #pragma unroll
       for (int k = 0; k < 4; ++k) xt[k] = x[k] + (k < NU ? lam * dx[k] : 0.0);
       if (xt[0] <= 0.0) xt[0] = 0.5 * x[0];
-      if (use_table) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) xt[k] = fmin(fmax(xt[k], e.lo[k]), e.hi[k]);
-      }
       inv_resid(e, use_table, mode, tgt, xt, rt, Jt, snt);
+      ++nev;
       nrt = maxnorm<NU>(rt);
       if (nrt < nr) {
         acc = true;
@@ -313,6 +313,7 @@ __device__ inline bool newton(const EosDev& e, bool use_table, int mode, const d
     nr = nrt;
   }
   *iters += it;
+  *evals += nev;
   return nr <= e.tol;
 }
 
@@ -392,6 +393,7 @@ template <int NQ>
 __device__ inline void eos_invert(const EosDev& e, int mode, const double in[4], const double* warm, Thermo& th,
                                   double* warm_out = nullptr) {
   th.iters = 0;
+  th.evals = 0;
   th.in_table = 0;
   th.ok = 1;
   const double zero[3] = {0.0, 0.0, 0.0};
@@ -419,7 +421,7 @@ __device__ inline void eos_invert(const EosDev& e, int mode, const double in[4],
     x[1] = x[2] = x[3] = 0.0;
   }
   double sn[4];
-  bool ok = newton<NQ>(e, false, mode, tgt, x, e.max_iter * 4, &th.iters, sn);
+  bool ok = newton<NQ>(e, false, mode, tgt, x, e.max_iter * 4, &th.iters, sn, &th.evals);
   if (warm_out) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) warm_out[W_GT + k] = x[k];
@@ -436,7 +438,7 @@ __device__ inline void eos_invert(const EosDev& e, int mode, const double in[4],
         for (int k = 0; k < 4; ++k) xt[k] = NQ > 0 || k == 0 ? xs[k] : 0.0;
       }
     }
-    bool okt = newton<NQ>(e, true, mode, tgt, xt, e.max_iter, &th.iters, sn);
+    bool okt = newton<NQ>(e, true, mode, tgt, xt, e.max_iter, &th.iters, sn, &th.evals);
     if (okt && in_axes(e, xt)) {
       thermo_fill(e, true, xt[0], xt + 1, th, sn);
       th.in_table = 1;

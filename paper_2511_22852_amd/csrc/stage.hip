@@ -292,6 +292,7 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
     aux[X_GAMMA * n + ii] = gam;
     aux[X_NNB * n + ii] = b.dsum[(int64_t)DS_NNB * cap + j];
     aux[X_NEWTON * n + ii] = th.iters;
+    aux[X_EOS_EVALS * n + ii] = th.evals;
   }
 }
 
