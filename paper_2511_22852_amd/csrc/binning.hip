@@ -26,6 +26,7 @@ __global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslot
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int e = i < nslots ? b.ev[i] : -1;
+  if (e >= 0 && !b.evt[e].rebin) e = -1;  // keeps its cells this step
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   if (e >= 0) {
     for (int k = 0; k < dim; ++k) {
@@ -94,7 +95,7 @@ __global__ void k_grid(BatchDev b, Params prm, int dim) {
   // per-step EoS counters start from zero (the stage kernels add to them)
   E->backup = 0;
   E->newton_iters = 0;
-  if (!E->active) return;
+  if (!E->active || !E->rebin) return;
   double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
   bool empty = false;
   for (int k = 0; k < dim; ++k) {
@@ -152,7 +153,8 @@ __device__ __forceinline__ void wave_runs(int64_t tag, int lane, int* head, int*
 __global__ void __launch_bounds__(256) k_count(BatchDev b, int dim, int64_t nslots) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  const int e = i < nslots ? b.ev[i] : -1;
+  int e = i < nslots ? b.ev[i] : -1;
+  if (e >= 0 && !b.evt[e].rebin) e = -1;
   int64_t tag = -1;
   int32_t cell = 0;
   if (e >= 0) {
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(256) k_count(BatchDev b, int dim, int64_t nslo
 __global__ void __launch_bounds__(1024) k_scan(BatchDev b, int dim) {
   const int e = blockIdx.x;
   const EventDev& E = b.evt[e];
-  if (!E.active) return;
+  if (!E.active || !E.rebin) return;
   int64_t ncell = 1;
   for (int k = 0; k < dim; ++k) ncell *= E.nc[k];
   __shared__ int32_t part[1024];
@@ -210,7 +212,8 @@ __global__ void __launch_bounds__(1024) k_scan(BatchDev b, int dim) {
 __global__ void __launch_bounds__(256) k_scatter(BatchDev b, int64_t nslots) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  const int e = i < nslots ? b.ev[i] : -1;
+  int e = i < nslots ? b.ev[i] : -1;
+  if (e >= 0 && !b.evt[e].rebin) e = -1;
   const int32_t cell = e >= 0 ? b.evt[e].c_base + b.key[i] : 0;
   int head, len;
   wave_runs(e >= 0 ? (int64_t)cell : -1, lane, &head, &len);
@@ -229,7 +232,7 @@ __global__ void __launch_bounds__(256) k_cellsort(BatchDev b, int dim) {
   __shared__ int32_t s_p[4][SORT_CAP];
   const int e = blockIdx.y;
   const EventDev& E = b.evt[e];
-  if (!E.active) return;
+  if (!E.active || !E.rebin) return;
   int64_t ncell = 1;
   for (int k = 0; k < dim; ++k) ncell *= E.nc[k];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -273,13 +276,17 @@ __global__ void __launch_bounds__(256) k_cellsort(BatchDev b, int dim) {
 
 __global__ void __launch_bounds__(256) k_permute(BatchDev b, int64_t nslots, uint32_t rowmask) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nslots || b.ev[j] < 0) return;
-  const int64_t src = b.perm[j];
+  if (j >= nslots) return;
+  const int e = b.ev[j];
+  if (e < 0) return;
+  // events that keep their cells are already in cell order: plain copy
+  const bool moved = b.evt[e].rebin != 0;
+  const int64_t src = moved ? b.perm[j] : j;
   for (int r = 0; r < NROW; ++r)
     if (rowmask & (1u << r)) b.Ys[(int64_t)r * b.cap + j] = b.Y0[(int64_t)r * b.cap + src];
   for (int w = 0; w < NWARM; ++w) b.warms[(int64_t)w * b.cap + j] = b.warm[(int64_t)w * b.cap + src];
   b.ids[j] = b.id[src];
-  b.keys[j] = b.key[src];
+  if (moved) b.keys[j] = b.key[src];
 }
 
 // sorted -> home (after an initialisation)
@@ -292,7 +299,45 @@ __global__ void __launch_bounds__(256) k_commit(BatchDev b, int64_t nslots, uint
   b.id[j] = b.ids[j];
 }
 
+// Per-event rebinning schedule of a batch step: an event is binned when it
+// is fresh or when twice its displacement bound since the last binning would
+// exceed the skin after this step (the same rule a single simulation applies
+// on the host).
+__global__ void k_schedule(BatchDev b, double skin, int hyper3d) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b.max_events) return;
+  EventDev* E = b.evt + e;
+  if (!E->active) {
+    E->rebin = 0;
+    return;
+  }
+  const double vmax = hyper3d ? fmax(1.0, 1.0 / E->t) : 1.0;
+  const double d = E->dt * vmax;
+  const int rebin = E->need_bin || 2.0 * (E->disp + d) > skin;
+  if (rebin) E->disp = 0.0;
+  E->disp += d;
+  E->need_bin = 0;
+  E->rebin = rebin;
+}
+
+// only event e is binned by the next launch_bin (admission of a new event)
+__global__ void k_bin_only(BatchDev b, int only) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b.max_events) return;
+  b.evt[e].rebin = e == only ? 1 : 0;
+}
+
 static inline unsigned blocks_of(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_schedule(const BatchDev& b, double skin, bool hyper3d, hipStream_t s) {
+  hipLaunchKernelGGL(k_schedule, dim3(blocks_of(b.max_events, 64)), dim3(64), 0, s, b, skin, hyper3d ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_only(const BatchDev& b, int e, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_only, dim3(blocks_of(b.max_events, 64)), dim3(64), 0, s, b, e);
+  return hipGetLastError();
+}
 
 hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, uint32_t rowmask,
                       hipStream_t s, const hipEvent_t* marks) {

@@ -114,6 +114,9 @@ struct EventDev {
   int32_t first_bad;  // lowest original id with a non-finite update, or -1
   uint32_t capacity_err;
   uint32_t newton_iters; // total Newton iterations (last stage)
+  int32_t rebin;      // this step bins the event (else it keeps its cells and order)
+  int32_t need_bin;   // the next step must bin (fresh state)
+  double disp;        // displacement bound sum(dt max(1, 1/x0)) since the last binning
   // bounding-box accumulators of the next binning: order-preserving integer
   // images of the coordinates (reset to the empty box after every use)
   unsigned long long bb_min[3], bb_max[3];

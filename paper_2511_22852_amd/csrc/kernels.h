@@ -17,6 +17,8 @@ hipError_t launch_advance(const BatchDev& b, hipStream_t s);
 // only_event >= 0 restricts the initialisation to that event
 hipError_t launch_init(const BatchDev& b, const Params& prm, const EosDev& eos, int dens_kind, const double* dens,
                        int64_t nslots, hipStream_t s, int only_event = -1);
+hipError_t launch_schedule(const BatchDev& b, double skin, bool hyper3d, hipStream_t s);
+hipError_t launch_bin_only(const BatchDev& b, int e, hipStream_t s);
 hipError_t launch_commit(const BatchDev& b, int64_t nslots, uint32_t rowmask, hipStream_t s);
 hipError_t launch_pairs(const BatchDev& b, const Params& prm, int e, int64_t n, int64_t* counter, int64_t cap,
                         int32_t* pa, int32_t* pb, hipStream_t s);

@@ -23,7 +23,7 @@ __global__ void k_advance(BatchDev b) {
 template <int D, int NQ>
 __global__ void __launch_bounds__(128) k_init(BatchDev b, Params prm, EosDev eos, int dens_kind,
                                               const double* __restrict__ dens, int64_t nslots, int only_event) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= nslots) return;
   const int e = b.ev[j];
   if (e < 0 || (only_event >= 0 && e != only_event)) return;

@@ -336,6 +336,7 @@ static ccake_status write_event(ccake_sim* s, double t, double dt) {
   E.dt = dt;
   E.first_bad = INT32_MAX;
   E.edge = s->prm.cell_edge;
+  E.rebin = 1;  // a single simulation schedules its binning on the host
   for (int k = 0; k < 3; ++k) {
     E.bb_min[k] = BB_EMPTY_MIN;
     E.bb_max[k] = BB_EMPTY_MAX;
@@ -414,6 +415,7 @@ extern "C" ccake_status ccake_init_particles(ccake_sim* s, double t0, const doub
   if (st) return st;
   s->t = t0;
   s->initialised = true;
+  s->need_bin = true;
   return sticky(s, *s->h_evt);
 }
 
@@ -428,6 +430,7 @@ extern "C" ccake_status ccake_set_state(ccake_sim* s, double t, const double* y,
   HIPCHK(s, hipStreamSynchronize(s->stream));
   s->t = t;
   s->initialised = true;
+  s->need_bin = true;
   return CCAKE_OK;
 }
 
@@ -446,11 +449,39 @@ extern "C" ccake_status ccake_time(const ccake_sim* s, double* t) {
 
 static const int PROF_MARKS = 12;  // 2 around the binning, 5 around each stage's kernels
 
-static ccake_status enqueue_step(ccake_sim* s, const hipEvent_t* marks) {
-  HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream, marks));
-  HIPCHK(s, launch_passes(s->b, s->prm, s->eos, s->n, 0, nullptr, nullptr, s->stream, marks ? marks + 2 : nullptr));
+// One Heun step.  With rebin, the particles are binned and gathered into cell
+// order first.  Without, the step runs on the home arrays, which the previous
+// step left in the cell order of the last binning (its update writes the home
+// state at the sorted slots): the stage kernels get a view of the batch whose
+// step-start state, warm starts and ids are the home ones, updated in place.
+static ccake_status enqueue_step(ccake_sim* s, const hipEvent_t* marks, bool rebin) {
+  BatchDev b = s->b;
+  if (rebin) {
+    HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream, marks));
+  } else {
+    if (marks) {
+      HIPCHK(s, hipEventRecord(marks[0], s->stream));
+      HIPCHK(s, hipEventRecord(marks[1], s->stream));
+    }
+    b.Ys = b.Y0;
+    b.warms = b.warm;
+    b.ids = b.id;
+  }
+  HIPCHK(s, launch_passes(b, s->prm, s->eos, s->n, 0, nullptr, nullptr, s->stream, marks ? marks + 2 : nullptr));
   HIPCHK(s, launch_advance(s->b, s->stream));
   return CCAKE_OK;
+}
+
+// Whether the next step of size dt starting at x0 = t must rebin, and the
+// bookkeeping of the displacement bound.
+static bool next_rebin(ccake_sim* s, double t, double dt) {
+  const double vmax = s->prm.hyperbolic && s->prm.dim == 3 ? std::fmax(1.0, 1.0 / t) : 1.0;
+  const double d = dt * vmax;
+  const bool rebin = s->need_bin || 2.0 * (s->disp_bound + d) > s->cfg.skin;
+  if (rebin) s->disp_bound = 0.0;
+  s->disp_bound += d;
+  s->need_bin = false;
+  return rebin;
 }
 
 // accumulate the kernel durations of nsteps profiled steps (synchronises)
@@ -525,7 +556,8 @@ extern "C" ccake_status ccake_step(ccake_sim* s, double dt, int32_t nsteps) {
       s->prof_ev.push_back(e);
     }
     for (int k = 0; k < nsteps; ++k) {
-      ccake_status st = enqueue_step(s, &s->prof_ev[(size_t)k * PROF_MARKS]);
+      const bool rebin = next_rebin(s, s->t + k * dt, dt);
+      ccake_status st = enqueue_step(s, &s->prof_ev[(size_t)k * PROF_MARKS], rebin);
       if (st) return st;
     }
     ccake_status st = collect_profile(s, nsteps);
@@ -536,29 +568,31 @@ extern "C" ccake_status ccake_step(ccake_sim* s, double dt, int32_t nsteps) {
     s->pending = true;
     return CCAKE_OK;
   }
-  if (s->use_graph && !s->graph_ready) {
-    hipError_t e1 = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
-    if (e1 == hipSuccess) {
-      ccake_status st = enqueue_step(s, nullptr);
-      hipGraph_t g = nullptr;
-      hipError_t e2 = hipStreamEndCapture(s->stream, &g);
-      if (st == CCAKE_OK && e2 == hipSuccess && g &&
-          hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0) == hipSuccess) {
-        s->graph_ready = true;
+  for (int k = 0; k < nsteps; ++k) {
+    const int rebin = next_rebin(s, s->t + k * dt, dt) ? 1 : 0;
+    if (s->use_graph && !s->graph_ready[rebin]) {
+      // capture this kind of step once; later steps replay it
+      hipError_t e1 = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+      if (e1 == hipSuccess) {
+        ccake_status st = enqueue_step(s, nullptr, rebin != 0);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+        if (st == CCAKE_OK && e2 == hipSuccess && g &&
+            hipGraphInstantiate(&s->graph[rebin], g, nullptr, nullptr, 0) == hipSuccess) {
+          s->graph_ready[rebin] = true;
+        } else {
+          s->use_graph = false;
+        }
+        if (g) (void)hipGraphDestroy(g);
       } else {
         s->use_graph = false;
       }
-      if (g) (void)hipGraphDestroy(g);
-    } else {
-      s->use_graph = false;
+      (void)hipGetLastError();
     }
-    (void)hipGetLastError();
-  }
-  for (int k = 0; k < nsteps; ++k) {
-    if (s->graph_ready) {
-      HIPCHK(s, hipGraphLaunch(s->graph, s->stream));
+    if (s->use_graph && s->graph_ready[rebin]) {
+      HIPCHK(s, hipGraphLaunch(s->graph[rebin], s->stream));
     } else {
-      ccake_status st = enqueue_step(s, nullptr);
+      ccake_status st = enqueue_step(s, nullptr, rebin != 0);
       if (st) return st;
     }
   }
@@ -620,6 +654,8 @@ static ccake_status evaluate(ccake_sim* s, bool rates) {
   HIPCHK(s, hipMemsetAsync(aux, 0, sizeof(double) * NAUXROW * s->n, s->stream));
   HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream));
   HIPCHK(s, launch_passes(s->b, s->prm, s->eos, s->n, 1, rates ? s->b.Y1 : nullptr, aux, s->stream));
+  // the home arrays keep their order while the cells now index the sorted copy
+  s->need_bin = true;
   return CCAKE_OK;
 }
 
@@ -675,6 +711,7 @@ extern "C" ccake_status ccake_debug_pairs(ccake_sim* s, int64_t cap, int32_t* a,
   if (!s->initialised) return fail(s, CCAKE_E_STATE, "not initialised");
   int64_t* counter = (int64_t*)(s->base + s->L.scratch);
   HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream));
+  s->need_bin = true;
   HIPCHK(s, hipMemsetAsync(counter, 0, sizeof(int64_t), s->stream));
   HIPCHK(s, launch_pairs(s->b, s->prm, 0, s->n, counter, cap, a, b, s->stream));
   HIPCHK(s, hipMemcpyAsync(npairs, counter, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
@@ -685,7 +722,8 @@ extern "C" ccake_status ccake_debug_pairs(ccake_sim* s, int64_t cap, int32_t* a,
 extern "C" ccake_status ccake_destroy(ccake_sim* s) {
   if (!s) return CCAKE_OK;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  if (s->graph_ready) (void)hipGraphExecDestroy(s->graph);
+  for (int k = 0; k < 2; ++k)
+    if (s->graph_ready[k]) (void)hipGraphExecDestroy(s->graph[k]);
   if (s->evt_done) (void)hipEventDestroy(s->evt_done);
   for (hipEvent_t e : s->prof_ev) (void)hipEventDestroy(e);
   if (s->h_evt) (void)hipHostFree(s->h_evt);

@@ -51,8 +51,14 @@ struct ccake_sim : ccake::Handle {
   double t = 0.0, dt_host = 0.0;
   ccake::SourceSet* h_src = nullptr;  // pinned staging of the source table
   bool initialised = false;
-  bool use_graph = false, graph_ready = false, pending = false;
-  hipGraphExec_t graph = nullptr;
+  bool use_graph = false, pending = false;
+  // graph[1]: a step that rebins first; graph[0]: a step on the last binning
+  bool graph_ready[2] = {false, false};
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // rebinning schedule: the binning is reused while twice the accumulated
+  // displacement bound sum(dt max(1, 1/x0)) since it stays within the skin
+  bool need_bin = true;
+  double disp_bound = 0.0;
   hipEvent_t evt_done = nullptr;
   ccake::EventDev* h_evt = nullptr;  // pinned copy of the event record
   // kernel timing with HIP events on the simulation's stream (profiling mode)

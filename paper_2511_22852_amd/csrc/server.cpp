@@ -166,6 +166,9 @@ static ccake_status admit_and_init(ccake_server* s, std::vector<std::pair<int, P
     E.dt = s->dt;
     E.first_bad = INT32_MAX;
     E.edge = s->prm.cell_edge;
+    E.rebin = 1;
+    E.need_bin = 1;  // its first step bins, as a single simulation's does
+    E.disp = 0.0;
     for (int k = 0; k < 3; ++k) {
       E.bb_min[k] = BB_EMPTY_MIN;
       E.bb_max[k] = BB_EMPTY_MAX;
@@ -179,8 +182,10 @@ static ccake_status admit_and_init(ccake_server* s, std::vector<std::pair<int, P
     if ((st = srv_hip(s, launch_upload(s->b, e, n, s->b.Y1, NROW, s->stream), "k_upload"))) return st;
     // the pageable sources must stay alive until the copies are done
     if ((st = srv_hip(s, hipStreamSynchronize(s->stream), "sync"))) return st;
-    // initialise this event alone: bin (all events), k_init restricted to it
+    // initialise this event alone: bin it (the others keep their cells and
+    // order), k_init restricted to it
     const int64_t nslots = s->palloc.high_water();
+    if ((st = srv_hip(s, launch_bin_only(s->b, e, s->stream), "bin only"))) return st;
     if ((st = srv_hip(s, launch_bin(s->b, s->prm, s->max_events, nslots, 0x1FFFFu, s->stream), "bin"))) return st;
     if ((st = srv_hip(s, launch_init(s->b, s->prm, s->eos, p.dens_kind, s->b.rec, nslots, s->stream, e), "init")))
       return st;
@@ -299,7 +304,8 @@ static void worker_loop(ccake_server* s) {
       }
     if (!any) continue;
     const int64_t nslots = s->palloc.high_water();
-    hipError_t he = launch_bin(s->b, s->prm, s->max_events, nslots, live_rows(s->prm), s->stream);
+    hipError_t he = launch_schedule(s->b, s->cfg.skin, s->prm.hyperbolic && s->prm.dim == 3, s->stream);
+    if (he == hipSuccess) he = launch_bin(s->b, s->prm, s->max_events, nslots, live_rows(s->prm), s->stream);
     if (he == hipSuccess) he = launch_passes(s->b, s->prm, s->eos, nslots, 0, nullptr, nullptr, s->stream);
     if (he == hipSuccess) he = launch_advance(s->b, s->stream);
     s->steps += 1;
@@ -371,6 +377,8 @@ extern "C" ccake_status ccake_server_submit(ccake_server* s, const ccake_event_d
   if (!ev || !ticket || ev->n <= 0 || !ev->xi || !ev->u || !ev->dens || !(ev->t_end >= ev->t0) ||
       (ev->dens_kind != 0 && ev->dens_kind != 1) || (s->prm.hyperbolic && !(ev->t0 > 0.0)))
     return fail(s, CCAKE_E_ARG, "ccake_server_submit: bad event");
+  if (s->prm.hyperbolic && s->prm.dim == 3 && 2.0 * s->dt * std::fmax(1.0, 1.0 / ev->t0) > s->cfg.skin)
+    return fail(s, CCAKE_E_ARG, "ccake_server_submit: skin below 2 dt / tau0 for this event");
   if (ev->n > s->max_particles || event_bytes(s, ev->n) > s->budget)
     return fail(s, CCAKE_E_CAPACITY, "event of %lld particles can never fit", (long long)ev->n);
   const int D = s->prm.dim;

@@ -79,7 +79,7 @@ template <int D, bool MIXED>
 __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const double* __restrict__ Y,
                                                  int64_t nslots) {
   constexpr int L = Team<D>::L;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
   const int lane = (int)(tid % L);
   if (j >= nslots) return;
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
       if (!(d2 < r2max)) continue;
       ++nnb;
       if (MIXED) {
-        const float W = spline_wf(sqrtf((float)d2) * (float)ih);
+        const float W = spline_wf(fast_sqrtf((float)d2) * (float)ih);
         ks.add(W);
         if (smoothed) {
           kt.add((float)row(Y, cap, R_S, k) * W);
@@ -299,7 +299,7 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
 template <int D, bool VISC, bool MIXED, int NQ>
 __global__ void __launch_bounds__(128) k_eos(BatchDev b, Params prm, EosDev eos, const double* __restrict__ Y,
                                              int stage, int64_t nslots, double* aux) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int e = -1;
   uint32_t c_backup = 0, c_iters = 0, c_noconv = 0;
   if (j < nslots) {
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
                                               int64_t nslots) {
   constexpr int L = Team<D>::L;
   constexpr int NA = D * D;  // viscous components A^{ji}
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
   const int lane = (int)(tid % L);
   if (j >= nslots) return;
@@ -364,9 +364,10 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       const double d2 = dist2<D>(xa, xb);
       if (!(d2 < r2max)) continue;
       if (MIXED) {
-        const float rr = sqrtf((float)d2);
-        if (!(rr > 0.0f)) continue;
-        const float f = spline_dwf(rr * (float)ih) / rr;
+        const float d2f = (float)d2;
+        if (!(d2f > 0.0f)) continue;  // self pair: grad W = 0
+        const float ir = fast_rsqf(d2f);
+        const float f = spline_dwf(d2f * ir * (float)ih) * ir;
         float dW[3];
 #pragma unroll
         for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[q]) * f;
