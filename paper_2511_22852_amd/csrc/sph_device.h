@@ -187,4 +187,57 @@ __device__ __forceinline__ void for_each_row(const BatchDev& b, const EventDev& 
   }
 }
 
+// Team version of for_each_row: the L lanes of a team (contiguous lanes of a
+// wave, team_base the first) share the row set-up.  Row r of the block
+// (r = (dz + S)(2S + 1) + dy + S) is trimmed by lane r mod L of the team and
+// broadcast when the loop reaches it, so each lane computes at most
+// ceil(rows / L) ranges instead of all of them.  f(lo, hi) is called by every
+// lane of the team for every non-empty row, in increasing slot order.
+template <int D, int L, class F>
+__device__ __forceinline__ void for_each_row_team(const BatchDev& b, const EventDev& E, int32_t key,
+                                                  const double xa[3], double reach, int lane, int team_base,
+                                                  F&& f) {
+  constexpr int W = 2 * SUBCELLS + 1;
+  constexpr int ROWS = D == 3 ? W * W : W;
+  constexpr int PER = (ROWS + L - 1) / L;
+  const int nx = E.nc[0], ny = E.nc[1], nz = D == 3 ? E.nc[2] : 1;
+  const int ix = key % nx;
+  const int iy = (key / nx) % ny;
+  const int iz = D == 3 ? key / (nx * ny) : 0;
+  const double e = E.edge, ie = 1.0 / e;
+  const double R = reach * (1.0 + 1e-9);
+  const double R2 = R * R;
+  const int32_t* cs = b.cell_start + E.c_base;
+  int32_t mlo[PER], mhi[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int r = lane + q * L;
+    mlo[q] = 0;
+    mhi[q] = 0;
+    if (r >= ROWS) continue;
+    const int dz = D == 3 ? r / W - SUBCELLS : 0, dy = r % W - SUBCELLS;
+    const int z = iz + dz, y = iy + dy;
+    if (z < 0 || z >= nz || y < 0 || y >= ny) continue;
+    const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
+    const double gy = interval_gap(xa[1], E.lo[1] + y * e, e);
+    const double r2 = R2 - gy * gy - gz * gz;
+    if (!(r2 >= 0.0)) continue;
+    const double rx = sqrt(r2) * (1.0 + 1e-9);
+    int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
+    x0 = max(x0, max(ix - SUBCELLS, 0));
+    x1 = min(x1, min(ix + SUBCELLS, nx - 1));
+    if (x0 > x1) continue;
+    const int c = (z * ny + y) * nx;
+    mlo[q] = cs[c + x0];
+    mhi[q] = cs[c + x1 + 1];
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const int q = r / L;
+    const int32_t lo = __shfl(mlo[q], team_base + r % L, 64);
+    const int32_t hi = __shfl(mhi[q], team_base + r % L, 64);
+    if (lo < hi) f(lo, hi);
+  }
+}
+
 }  // namespace ccake

@@ -94,7 +94,8 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   double ss = 0.0, st = 0.0, sn0 = 0.0, sn1 = 0.0, sn2 = 0.0;
   Kahan ks{0.f, 0.f}, kt{0.f, 0.f}, kn0{0.f, 0.f}, kn1{0.f, 0.f}, kn2{0.f, 0.f};
   int nnb = 0, acc = 0;
-  for_each_row<D>(b, E, b.keys[j], xa, prm.cell_edge, [&](int32_t lo, int32_t hi) {
+  const int team_base = (int)(threadIdx.x & 63) - lane;
+  for_each_row_team<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, team_base, [&](int32_t lo, int32_t hi) {
     for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
       const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
       const double d2 = dist2<D>(xa, xb);
@@ -358,7 +359,8 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
     }
   }
   int acc = 0;
-  for_each_row<D>(b, E, b.keys[j], xa, prm.cell_edge, [&](int32_t lo, int32_t hi) {
+  const int team_base = (int)(threadIdx.x & 63) - lane;
+  for_each_row_team<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, team_base, [&](int32_t lo, int32_t hi) {
     for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
       const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
       const double d2 = dist2<D>(xa, xb);
