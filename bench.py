@@ -296,6 +296,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=200, help="Heun steps per served event")
     ap.add_argument("--steps-3d", type=int, default=10,
                     help="timed steps of each 3+1D configuration (0 = skip them)")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="only time the 1.2 M-particle 3+1D event in mixed precision (profiling runs)")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both",
                     help="which precisions to run (counter-collection passes use one)")
     ap.add_argument("--write-inputs", metavar="PATH",
@@ -319,9 +321,13 @@ def main():
     from paper_2511_22852_amd import binding as B
     from paper_2511_22852_amd import inputs as I
 
-    w = I.lumpy_2d_workload()
     cols, lo, hi = I.massless_gas_table()
     eos = B.Eos.table(cols, lo, hi)
+    if args.only_3d:
+        r = run_3d(B, I.lumpy_3d_workload(), eos, B.MIXED, args.steps_3d, 2)
+        print(json.dumps({"lumpy_3d_viscous_bsq_1.2M_mixed": r}))
+        return
+    w = I.lumpy_2d_workload()
     res = {}
     for name, prec in (("fp64", B.FP64), ("mixed", B.MIXED)):
         if args.precision not in ("both", name):

@@ -3,8 +3,8 @@
 // that keeps stage-2 pairs inside the block), stable counting sort of the
 // particles by (cell, original id).  This is the uniform-grid neighbour
 // binning the paper takes from Cabana's VerletList, rebuilt as
-//   k_bbox   grid-stride min/max per event: wave reduction, one atomic per wave
-//            on order-preserving integer images of the coordinates
+//   k_bbox   min/max per event: each block reduces 8192 slots, then one atomic
+//            per axis on order-preserving integer images of the coordinates
 //   k_grid   one thread per event: grid origin, cells per axis, reset of the box
 //   k_count  particle -> cell key, atomic count per cell
 //   k_scan   one block per event: exclusive scan of the counts
@@ -20,70 +20,60 @@
 
 namespace ccake {
 
+// slots per k_bbox block: few blocks, so few atomics on the same addresses
+constexpr int BBOX_PER_THREAD = 32;
+
 __global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslots) {
   __shared__ double s_lo[4][3], s_hi[4][3];
   __shared__ int s_e[4];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int e = i < nslots ? b.ev[i] : -1;
-  if (e >= 0 && !b.evt[e].rebin) e = -1;  // keeps its cells this step
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * BBOX_PER_THREAD;
+  // the block's event: that of its first slot (slots of an event are contiguous)
+  int main = base < nslots ? b.ev[base] : -1;
+  if (main >= 0 && !b.evt[main].rebin) main = -1;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (e >= 0) {
+  for (int q = 0; q < BBOX_PER_THREAD; ++q) {
+    const int64_t i = base + (int64_t)q * blockDim.x + threadIdx.x;
+    if (i >= nslots) break;
+    int e = b.ev[i];
+    if (e < 0 || !b.evt[e].rebin) continue;  // empty slot, or keeps its cells this step
     for (int k = 0; k < dim; ++k) {
       const double x = row(b.Y0, b.cap, R_X1 + k, i);
-      if (isfinite(x)) {
-        lo[k] = x;
-        hi[k] = x;
+      if (!isfinite(x)) continue;
+      if (e == main) {
+        lo[k] = fmin(lo[k], x);
+        hi[k] = fmax(hi[k], x);
+      } else {  // another event inside this block's slots (batches only)
+        atomicMin(&b.evt[e].bb_min[k], ordered_bits(x));
+        atomicMax(&b.evt[e].bb_max[k], ordered_bits(x));
       }
     }
   }
-  // waves on one event reduce in registers; the others add lane by lane
-  const int e0 = __shfl(e, 0, 64);
-  const bool uniform = __all(e == e0);
-  if (uniform) {
-    for (int k = 0; k < dim; ++k) {
+  for (int k = 0; k < dim; ++k) {
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        lo[k] = fmin(lo[k], __shfl_xor(lo[k], off, 64));
-        hi[k] = fmax(hi[k], __shfl_xor(hi[k], off, 64));
-      }
-    }
-  } else if (e >= 0) {
-    EventDev* E = b.evt + e;
-    for (int k = 0; k < dim; ++k) {
-      if (isfinite(lo[k])) atomicMin(&E->bb_min[k], ordered_bits(lo[k]));
-      if (isfinite(hi[k])) atomicMax(&E->bb_max[k], ordered_bits(hi[k]));
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo[k] = fmin(lo[k], __shfl_xor(lo[k], off, 64));
+      hi[k] = fmax(hi[k], __shfl_xor(hi[k], off, 64));
     }
   }
   if (lane == 0) {
-    s_e[w] = uniform ? e0 : -1;
+    s_e[w] = main;
     for (int k = 0; k < 3; ++k) {
       s_lo[w][k] = lo[k];
       s_hi[w][k] = hi[k];
     }
   }
   __syncthreads();
-  // one thread merges the block's uniform waves: one atomic per axis when
-  // they share an event, one per wave otherwise
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && main >= 0) {
     const int nw = (int)(blockDim.x >> 6);
-    for (int a = 0; a < nw; ++a) {
-      const int ea = s_e[a];
-      if (ea < 0) continue;
-      double l[3] = {s_lo[a][0], s_lo[a][1], s_lo[a][2]}, h[3] = {s_hi[a][0], s_hi[a][1], s_hi[a][2]};
-      for (int c = a + 1; c < nw; ++c) {
-        if (s_e[c] != ea) continue;
-        for (int k = 0; k < 3; ++k) {
-          l[k] = fmin(l[k], s_lo[c][k]);
-          h[k] = fmax(h[k], s_hi[c][k]);
-        }
-        s_e[c] = -1;
+    for (int k = 0; k < dim; ++k) {
+      double l = s_lo[0][k], h = s_hi[0][k];
+      for (int a = 1; a < nw; ++a) {
+        l = fmin(l, s_lo[a][k]);
+        h = fmax(h, s_hi[a][k]);
       }
-      EventDev* E = b.evt + ea;
-      for (int k = 0; k < dim; ++k) {
-        if (isfinite(l[k])) atomicMin(&E->bb_min[k], ordered_bits(l[k]));
-        if (isfinite(h[k])) atomicMax(&E->bb_max[k], ordered_bits(h[k]));
-      }
+      if (isfinite(l)) atomicMin(&b.evt[main].bb_min[k], ordered_bits(l));
+      if (isfinite(h)) atomicMax(&b.evt[main].bb_max[k], ordered_bits(h));
     }
   }
 }
@@ -343,7 +333,7 @@ hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t
                       hipStream_t s, const hipEvent_t* marks) {
   if (nslots <= 0 || nevents <= 0) return hipSuccess;
   if (marks) (void)hipEventRecord(marks[0], s);
-  hipLaunchKernelGGL(k_bbox, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, prm.dim, nslots);
+  hipLaunchKernelGGL(k_bbox, dim3(blocks_of(nslots, 256 * BBOX_PER_THREAD)), dim3(256), 0, s, b, prm.dim, nslots);
   hipLaunchKernelGGL(k_grid, dim3(blocks_of(nevents, 64)), dim3(64), 0, s, b, prm, prm.dim);
   hipLaunchKernelGGL(k_count, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, prm.dim, nslots);
   hipLaunchKernelGGL(k_scan, dim3(nevents), dim3(1024), 0, s, b, prm.dim);

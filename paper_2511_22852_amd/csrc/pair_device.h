@@ -1,0 +1,199 @@
+// Per-pair arithmetic of the SPH sums, shared by the kernels that read the
+// candidates from global memory (one team of lanes per particle, any batch)
+// and the kernels that stage a cell's neighbourhood in LDS first (single
+// events).  Both visit the same candidates in the same order per lane and
+// merge the lanes with the same butterfly.  Floating-point contraction is off
+// on the whole pair path and the fused multiply-adds are written out, so the
+// two give the same bits.
+//
+//   density sums ("SPH interpretation of a fluid element"):
+//     sigma* = sum_b W_ab, s* = sum_b S_b W_ab, n*_q = sum_b N_q,b W_ab
+//   gradient sums ("Derivatives in relativistic SPH"):
+//     F_i    = sum_b [(p+Pi)_a/sigma*_a^2 + (p+Pi)_b/sigma*_b^2] d_i W_ab
+//              + G_i sum_b [A^{ji}_a/sigma*_a^2 + A^{ji}_b/sigma*_b^2] d_j W_ab   (n = -1)
+//     d_k u^j = (1/sigma*_a) sum_b (u^j_b - u^j_a) d_k W_ab                      (n = 1)
+//     div v   = (1/sigma*_a) sum_b (v_b - v_a) . grad W_ab
+// In the FP32 (mixed) form every sum is compensated (Kahan) and the kernel
+// uses the hardware square root; the pair test is FP64 in both forms.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "common.h"
+#include "sph_device.h"
+
+namespace ccake {
+
+template <int L>
+__device__ __forceinline__ double team_sum(double v) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ int team_sum_i(int v) {
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ double team_sum_k(Kahan k) {
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) {
+    const float s2 = __shfl_xor(k.s, off, 64);
+    const float c2 = __shfl_xor(k.c, off, 64);
+    k.merge(s2, c2);
+  }
+  return k.value();
+}
+
+// ---------------------------------------------------------------------------
+// NS smoothed scalars per neighbour: 0 (specific densities: sigma* only),
+// 1 (s*), 4 (s*, n*_B, n*_S, n*_Q)
+template <bool MIXED, int NS>
+struct DensAcc {
+  double ss, sv[4];
+  Kahan ks, kv[4];
+  int nnb;
+
+  __device__ __forceinline__ void init() {
+    ss = 0.0;
+    ks = Kahan{0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sv[q] = 0.0;
+      kv[q] = Kahan{0.f, 0.f};
+    }
+    nnb = 0;
+  }
+
+  // one accepted pair at squared distance d2 with the neighbour's scalars v
+  // (S, N_B, N_S, N_Q; the first NS are used)
+  __device__ __forceinline__ void add(double d2, double ih, const double v[4]) {
+#pragma clang fp contract(off)
+    ++nnb;
+    if (MIXED) {
+      const float W = spline_wf(fast_sqrtf((float)d2) * (float)ih);
+      ks.add(W);
+#pragma unroll
+      for (int q = 0; q < NS; ++q) kv[q].add_prod((float)v[q], W);
+    } else {
+      const double W = spline_w(sqrt(d2) * ih);
+      ss += W;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) sv[q] = fma(v[q], W, sv[q]);
+    }
+  }
+
+  // team totals: sigma*, s*, n*_B, n*_S, n*_Q (without sigma_d), neighbours
+  template <int L>
+  __device__ __forceinline__ void reduce(double out[5], int* count) {
+    out[0] = MIXED ? team_sum_k<L>(ks) : team_sum<L>(ss);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[1 + q] = q < NS ? (MIXED ? team_sum_k<L>(kv[q]) : team_sum<L>(sv[q])) : 0.0;
+    *count = team_sum_i<L>(nnb);
+  }
+};
+
+// ---------------------------------------------------------------------------
+template <int D, bool VISC, bool MIXED>
+struct GradAcc {
+  using RT = typename std::conditional<MIXED, float, double>::type;
+  double xa[3], Gk[4], ih;
+  RT aPP, aA[3][3], aU[3], aV[3];
+  double F[3], du[3][3], dv;
+  Kahan kF[3], kdu[3][3], kdv;
+
+  __device__ __forceinline__ void init() {
+    dv = 0.0;
+    kdv = Kahan{0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      F[k] = 0.0;
+      kF[k] = Kahan{0.f, 0.f};
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        du[k][n] = 0.0;
+        kdu[k][n] = Kahan{0.f, 0.f};
+      }
+    }
+  }
+
+  // one accepted pair: neighbour position xb at squared distance d2 and its
+  // record (p+Pi)/sigma*^2, A^{ji}/sigma*^2 ([j][i]), u, v
+  __device__ __forceinline__ void add(const double xb[3], double d2, RT bpp, const RT bA[3][3], const RT bU[3],
+                                      const RT bV[3]) {
+#pragma clang fp contract(off)
+    if (MIXED) {
+      const float d2f = (float)d2;
+      if (!(d2f > 0.0f)) return;  // self pair: grad W = 0
+      const float ir = fast_rsqf(d2f);
+      const float f = spline_dwf(d2f * ir * (float)ih) * ir;
+      float dW[3];
+#pragma unroll
+      for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[q]) * f;
+      const float pp = (float)aPP + (float)bpp;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        if (VISC) {
+          float vis = 0.f;
+#pragma unroll
+          for (int jj = 0; jj < D; ++jj) vis = fmaf((float)aA[jj][i] + (float)bA[jj][i], dW[jj], vis);
+          kF[i].add(fmaf((float)Gk[i + 1], vis, pp * dW[i]));
+        } else {
+          kF[i].add_prod(pp, dW[i]);
+        }
+      }
+      float dvv = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk) {
+#pragma unroll
+        for (int nu = 0; nu < D; ++nu) kdu[kk][nu].add_prod((float)bU[nu] - (float)aU[nu], dW[kk]);
+        dvv = fmaf((float)bV[kk] - (float)aV[kk], dW[kk], dvv);
+      }
+      kdv.add(dvv);
+    } else {
+      const double rr = sqrt(d2);
+      if (!(rr > 0.0)) return;
+      const double f = spline_dw(rr * ih) / rr;
+      double dW[3];
+#pragma unroll
+      for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[q]) * f;
+      const double pp = aPP + (double)bpp;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        if (VISC) {
+          double vis = 0.0;
+#pragma unroll
+          for (int jj = 0; jj < D; ++jj) vis = fma(aA[jj][i] + (double)bA[jj][i], dW[jj], vis);
+          F[i] += fma(Gk[i + 1], vis, pp * dW[i]);
+        } else {
+          F[i] = fma(pp, dW[i], F[i]);
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk) {
+#pragma unroll
+        for (int nu = 0; nu < D; ++nu) du[kk][nu] = fma((double)bU[nu] - aU[nu], dW[kk], du[kk][nu]);
+        dv = fma((double)bV[kk] - aV[kk], dW[kk], dv);
+      }
+    }
+  }
+
+  template <int L>
+  __device__ __forceinline__ void reduce() {
+#pragma unroll
+    for (int i = 0; i < D; ++i) F[i] = MIXED ? team_sum_k<L>(kF[i]) : team_sum<L>(F[i]);
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+      for (int nu = 0; nu < D; ++nu) du[kk][nu] = MIXED ? team_sum_k<L>(kdu[kk][nu]) : team_sum<L>(du[kk][nu]);
+    dv = MIXED ? team_sum_k<L>(kdv) : team_sum<L>(dv);
+  }
+};
+
+}  // namespace ccake

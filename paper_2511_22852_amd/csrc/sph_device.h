@@ -19,33 +19,39 @@ __device__ __forceinline__ double sigma_d(double h) {
 }
 
 // w(q) = 1 - 3/2 q^2 + 3/4 q^3 (q <= 1), (2 - q)^3 / 4 (1 < q <= 2), 0 beyond.
-// Both pieces are evaluated and one is selected (no divergent branches).
+// Both pieces are evaluated and one is selected (no divergent branches).  The
+// polynomials are written in Horner form with explicit fused multiply-adds and
+// contraction off elsewhere, so every caller rounds them the same way.
 __device__ __forceinline__ double spline_w(double q) {
+#pragma clang fp contract(off)
   const double t = 2.0 - q;
-  const double inner = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
-  const double outer = 0.25 * t * t * t;
+  const double inner = fma(q * q, fma(0.75, q, -1.5), 1.0);
+  const double outer = (0.25 * t) * (t * t);
   return q <= 1.0 ? inner : (q <= 2.0 ? outer : 0.0);
 }
 
 // w'(q) = -3 q + 9/4 q^2 (q <= 1), -3/4 (2 - q)^2 (1 < q <= 2), 0 beyond
 __device__ __forceinline__ double spline_dw(double q) {
+#pragma clang fp contract(off)
   const double t = 2.0 - q;
-  const double inner = -3.0 * q + 2.25 * q * q;
-  const double outer = -0.75 * t * t;
+  const double inner = q * fma(2.25, q, -3.0);
+  const double outer = (-0.75 * t) * t;
   return q <= 1.0 ? inner : (q <= 2.0 ? outer : 0.0);
 }
 
 __device__ __forceinline__ float spline_wf(float q) {
+#pragma clang fp contract(off)
   const float t = 2.0f - q;
-  const float inner = 1.0f - 1.5f * q * q + 0.75f * q * q * q;
-  const float outer = 0.25f * t * t * t;
+  const float inner = fmaf(q * q, fmaf(0.75f, q, -1.5f), 1.0f);
+  const float outer = (0.25f * t) * (t * t);
   return q <= 1.0f ? inner : (q <= 2.0f ? outer : 0.0f);
 }
 
 __device__ __forceinline__ float spline_dwf(float q) {
+#pragma clang fp contract(off)
   const float t = 2.0f - q;
-  const float inner = -3.0f * q + 2.25f * q * q;
-  const float outer = -0.75f * t * t;
+  const float inner = q * fmaf(2.25f, q, -3.0f);
+  const float outer = (-0.75f * t) * t;
   return q <= 1.0f ? inner : (q <= 2.0f ? outer : 0.0f);
 }
 
@@ -59,13 +65,23 @@ __device__ __forceinline__ float fast_rsqf(float x) { return __builtin_amdgcn_rs
 struct Kahan {
   float s, c;
   __device__ __forceinline__ void add(float x) {
+#pragma clang fp contract(off)
     float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  // add the product a*b, rounded once together with the compensation
+  __device__ __forceinline__ void add_prod(float a, float b) {
+#pragma clang fp contract(off)
+    float y = fmaf(a, b, -c);
     float t = s + y;
     c = (t - s) - y;
     s = t;
   }
   // merge another compensated sum (TwoSum of the heads, compensations added)
   __device__ __forceinline__ void merge(float s2, float c2) {
+#pragma clang fp contract(off)
     float t = s + s2;
     float bp = t - s;
     float err = (s - (t - bp)) + (s2 - bp);
@@ -187,18 +203,23 @@ __device__ __forceinline__ void for_each_row(const BatchDev& b, const EventDev& 
   }
 }
 
-// Team version of for_each_row: the L lanes of a team (contiguous lanes of a
-// wave, team_base the first) share the row set-up.  Row r of the block
-// (r = (dz + S)(2S + 1) + dy + S) is trimmed by lane r mod L of the team and
-// broadcast when the loop reaches it, so each lane computes at most
-// ceil(rows / L) ranges instead of all of them.  f(lo, hi) is called by every
-// lane of the team for every non-empty row, in increasing slot order.
-template <int D, int L, class F>
-__device__ __forceinline__ void for_each_row_team(const BatchDev& b, const EventDev& E, int32_t key,
-                                                  const double xa[3], double reach, int lane, int team_base,
-                                                  F&& f) {
-  constexpr int W = 2 * SUBCELLS + 1;
-  constexpr int ROWS = D == 3 ? W * W : W;
+// Team version of for_each_row, with the rows kept in LDS.  The L lanes of a
+// team (contiguous lanes of one wave) share the row set-up: row r of the block
+// (r = (dz + S)(2S + 1) + dy + S) is trimmed by lane r mod L and its slot range
+// stored at lo[r], hi[r] (empty rows as lo = hi).  The team then walks the
+// concatenation of its rows with RowCursor below.
+template <int D>
+struct RowBlock {
+  static constexpr int W = 2 * SUBCELLS + 1;
+  static constexpr int ROWS = D == 3 ? W * W : W;
+};
+
+template <int D, int L>
+__device__ __forceinline__ void team_rows(const BatchDev& b, const EventDev& E, int32_t key, const double xa[3],
+                                          double reach, int lane, int32_t* __restrict__ lo,
+                                          int32_t* __restrict__ hi) {
+  constexpr int W = RowBlock<D>::W;
+  constexpr int ROWS = RowBlock<D>::ROWS;
   constexpr int PER = (ROWS + L - 1) / L;
   const int nx = E.nc[0], ny = E.nc[1], nz = D == 3 ? E.nc[2] : 1;
   const int ix = key % nx;
@@ -208,36 +229,73 @@ __device__ __forceinline__ void for_each_row_team(const BatchDev& b, const Event
   const double R = reach * (1.0 + 1e-9);
   const double R2 = R * R;
   const int32_t* cs = b.cell_start + E.c_base;
-  int32_t mlo[PER], mhi[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int r = lane + q * L;
-    mlo[q] = 0;
-    mhi[q] = 0;
     if (r >= ROWS) continue;
+    int32_t rlo = 0, rhi = 0;
     const int dz = D == 3 ? r / W - SUBCELLS : 0, dy = r % W - SUBCELLS;
     const int z = iz + dz, y = iy + dy;
-    if (z < 0 || z >= nz || y < 0 || y >= ny) continue;
-    const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
-    const double gy = interval_gap(xa[1], E.lo[1] + y * e, e);
-    const double r2 = R2 - gy * gy - gz * gz;
-    if (!(r2 >= 0.0)) continue;
-    const double rx = sqrt(r2) * (1.0 + 1e-9);
-    int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
-    x0 = max(x0, max(ix - SUBCELLS, 0));
-    x1 = min(x1, min(ix + SUBCELLS, nx - 1));
-    if (x0 > x1) continue;
-    const int c = (z * ny + y) * nx;
-    mlo[q] = cs[c + x0];
-    mhi[q] = cs[c + x1 + 1];
+    if (z >= 0 && z < nz && y >= 0 && y < ny) {
+      const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
+      const double gy = interval_gap(xa[1], E.lo[1] + y * e, e);
+      const double r2 = R2 - gy * gy - gz * gz;
+      if (r2 >= 0.0) {
+        const double rx = sqrt(r2) * (1.0 + 1e-9);
+        int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
+        x0 = max(x0, max(ix - SUBCELLS, 0));
+        x1 = min(x1, min(ix + SUBCELLS, nx - 1));
+        if (x0 <= x1) {
+          const int c = (z * ny + y) * nx;
+          rlo = cs[c + x0];
+          rhi = cs[c + x1 + 1];
+        }
+      }
+    }
+    lo[r] = rlo;
+    hi[r] = rhi;
   }
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r) {
-    const int q = r / L;
-    const int32_t lo = __shfl(mlo[q], team_base + r % L, 64);
-    const int32_t hi = __shfl(mhi[q], team_base + r % L, 64);
-    if (lo < hi) f(lo, hi);
-  }
+  // the rows are read back by other lanes of the same wave
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Walk of one lane of a team over the concatenation of the team's rows: the
+// lane takes positions lane, lane + L, lane + 2L, ... of that sequence, so
+// that the L lanes together visit every candidate exactly once, each lane in
+// increasing slot order.  A step past the end of a row continues in the next
+// non-empty row with the overshoot carried.
+template <int L, int ROWS>
+struct RowCursor {
+  const int32_t* lo;
+  const int32_t* hi;
+  int r;
+  int32_t k, h;
+
+  __device__ __forceinline__ void start(const int32_t* lo_, const int32_t* hi_, int lane) {
+    lo = lo_;
+    hi = hi_;
+    r = 0;
+    k = lo[0] + lane;
+    h = hi[0];
+    settle();
+  }
+  __device__ __forceinline__ void settle() {
+    while (k >= h && r + 1 < ROWS) {
+      ++r;
+      const int32_t over = k - h;
+      k = lo[r] + over;
+      h = hi[r];
+    }
+  }
+  __device__ __forceinline__ bool valid() const { return k < h; }
+  __device__ __forceinline__ int32_t next() {
+    const int32_t c = k;
+    k += L;
+    settle();
+    return c;
+  }
+};
 
 }  // namespace ccake

@@ -13,10 +13,13 @@
 //              rates, Heun update
 //
 // The neighbour loops give each of L consecutive lanes every L-th candidate
-// of the particle's 3^D-cell block and combine the partial sums with a fixed
-// butterfly of lane shuffles, so the result is deterministic.  Candidates of
-// particles in the same cell coincide, so the lanes of a wave read the same
-// addresses.  In mixed precision the pair terms are formed and accumulated in
+// of the particle's trimmed cell rows and combine the partial sums with a
+// fixed butterfly of lane shuffles, so the result is deterministic.  Each lane
+// takes its candidates PAIR_U at a time: the positions of all PAIR_U are
+// loaded together, then the operands of the accepted ones, so that a lane has
+// several loads in flight across row boundaries instead of one dependent
+// round trip per candidate.  Candidates of particles in the same cell
+// coincide, so the lanes of a wave read the same addresses.  In mixed precision the pair terms are formed and accumulated in
 // FP32 with Kahan compensation per lane and compensated merges across lanes;
 // the pair test itself is always the exact FP64 one.
 #include <hip/hip_runtime.h>
@@ -25,6 +28,7 @@
 #include "eom_device.h"
 #include "eos_device.h"
 #include "kernels.h"
+#include "pair_device.h"
 #include "sph_device.h"
 
 namespace ccake {
@@ -39,46 +43,48 @@ namespace ccake {
 template <int D>
 struct Team {
   static constexpr int L = D == 2 ? CCAKE_TEAM2 : CCAKE_TEAM3;
+  static constexpr int PER_BLOCK = 256 / L;
 };
+// candidates per lane in flight in the pair loops
+#ifndef CCAKE_PAIR_U
+#define CCAKE_PAIR_U 2
+#endif
+constexpr int PAIR_U = CCAKE_PAIR_U;
 
-// first candidate of this lane in range [lo, hi) given acc candidates before it
-template <int L>
-__device__ __forceinline__ int32_t first_of(int32_t lo, int acc, int lane) {
-  int skip = (lane - acc) % L;
-  skip += skip < 0 ? L : 0;
-  return lo + skip;
-}
-
-template <int L>
-__device__ __forceinline__ double team_sum(double v) {
+// Takes this lane's next PAIR_U candidates from the cursor: slot k[u] and
+// whether it exists (v[u]); missing ones point at the lane's own particle,
+// so every load stays in bounds.
+template <class Cursor>
+__device__ __forceinline__ void take(Cursor& cur, int32_t self, int32_t k[PAIR_U], bool v[PAIR_U]) {
 #pragma unroll
-  for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-template <int L>
-__device__ __forceinline__ int team_sum_i(int v) {
-#pragma unroll
-  for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-template <int L>
-__device__ __forceinline__ double team_sum_k(Kahan k) {
-#pragma unroll
-  for (int off = L / 2; off >= 1; off >>= 1) {
-    const float s2 = __shfl_xor(k.s, off, 64);
-    const float c2 = __shfl_xor(k.c, off, 64);
-    k.merge(s2, c2);
+  for (int u = 0; u < PAIR_U; ++u) {
+    v[u] = cur.valid();
+    k[u] = self;
+    if (v[u]) k[u] = cur.next();
   }
-  return k.value();
+}
+
+template <int D>
+__device__ __forceinline__ void write_density(const BatchDev& b, const Params& prm, int64_t j, const double sums[5],
+                                              int nnb) {
+  const int64_t cap = b.cap;
+  const double sd = sigma_d<D>(prm.h);
+  b.dsum[(int64_t)DS_SIG * cap + j] = sums[0] * sd;
+  b.dsum[(int64_t)DS_S * cap + j] = sums[1] * sd;
+  b.dsum[(int64_t)DS_NB * cap + j] = sums[2] * sd;
+  b.dsum[(int64_t)DS_NS * cap + j] = sums[3] * sd;
+  b.dsum[(int64_t)DS_NQ * cap + j] = sums[4] * sd;
+  b.dsum[(int64_t)DS_NNB * cap + j] = (double)nnb;
 }
 
 // ---------------------------------------------------------------------------
-template <int D, bool MIXED>
+// NS: smoothed scalars per neighbour (0 specific densities, 1 s*, 4 s* and n*)
+template <int D, bool MIXED, int NS>
 __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const double* __restrict__ Y,
                                                  int64_t nslots) {
   constexpr int L = Team<D>::L;
+  constexpr int ROWS = RowBlock<D>::ROWS;
+  __shared__ int32_t s_lo[Team<D>::PER_BLOCK][ROWS], s_hi[Team<D>::PER_BLOCK][ROWS];
   const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
   const int lane = (int)(tid % L);
@@ -88,76 +94,42 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   const EventDev& E = b.evt[e];
   const int64_t cap = b.cap;
   const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
-  const bool smoothed = prm.density_mode == 0;
-  const int nq = smoothed ? prm.ncharge : 0;
   const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
-  double ss = 0.0, st = 0.0, sn0 = 0.0, sn1 = 0.0, sn2 = 0.0;
-  Kahan ks{0.f, 0.f}, kt{0.f, 0.f}, kn0{0.f, 0.f}, kn1{0.f, 0.f}, kn2{0.f, 0.f};
-  int nnb = 0, acc = 0;
-  const int team_base = (int)(threadIdx.x & 63) - lane;
-  for_each_row_team<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, team_base, [&](int32_t lo, int32_t hi) {
-    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
-      const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
-      const double d2 = dist2<D>(xa, xb);
-      if (!(d2 < r2max)) continue;
-      ++nnb;
-      if (MIXED) {
-        const float W = spline_wf(fast_sqrtf((float)d2) * (float)ih);
-        ks.add(W);
-        if (smoothed) {
-          kt.add((float)row(Y, cap, R_S, k) * W);
-          if (nq) {
-            kn0.add((float)row(Y, cap, R_NB, k) * W);
-            kn1.add((float)row(Y, cap, R_NS, k) * W);
-            kn2.add((float)row(Y, cap, R_NQ, k) * W);
-          }
-        }
-      } else {
-        const double W = spline_w(sqrt(d2) * ih);
-        ss += W;
-        if (smoothed) {
-          st += row(Y, cap, R_S, k) * W;
-          if (nq) {
-            sn0 += row(Y, cap, R_NB, k) * W;
-            sn1 += row(Y, cap, R_NS, k) * W;
-            sn2 += row(Y, cap, R_NQ, k) * W;
-          }
-        }
-      }
+  const int team = (int)threadIdx.x / L;
+  team_rows<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+  RowCursor<L, ROWS> cur;
+  cur.start(s_lo[team], s_hi[team], lane);
+  DensAcc<MIXED, NS> A;
+  A.init();
+  const int32_t self = (int32_t)j;
+  for (;;) {
+    int32_t k[PAIR_U];
+    bool v[PAIR_U];
+    take(cur, self, k, v);
+    if (!v[0]) break;
+    double d2[PAIR_U];
+    bool ok[PAIR_U];
+#pragma unroll
+    for (int u = 0; u < PAIR_U; ++u) {
+      const double xb[3] = {row(Y, cap, R_X1, k[u]), row(Y, cap, R_X2, k[u]),
+                            D == 3 ? row(Y, cap, R_X3, k[u]) : 0.0};
+      d2[u] = dist2<D>(xa, xb);
+      ok[u] = v[u] && d2[u] < r2max;
     }
-    acc += hi - lo;
-  });
-  if (MIXED) {
-    ss = team_sum_k<L>(ks);
-    if (smoothed) {
-      st = team_sum_k<L>(kt);
-      if (nq) {
-        sn0 = team_sum_k<L>(kn0);
-        sn1 = team_sum_k<L>(kn1);
-        sn2 = team_sum_k<L>(kn2);
-      }
+#pragma unroll
+    for (int u = 0; u < PAIR_U; ++u) {
+      const int32_t m = ok[u] ? k[u] : self;
+      double sc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sc[q] = q < NS ? row(Y, cap, R_S + q, m) : 0.0;
+      if (ok[u]) A.add(d2[u], ih, sc);
     }
-  } else {
-    ss = team_sum<L>(ss);
-    if (smoothed) {
-      st = team_sum<L>(st);
-      if (nq) {
-        sn0 = team_sum<L>(sn0);
-        sn1 = team_sum<L>(sn1);
-        sn2 = team_sum<L>(sn2);
-      }
-    }
+    if (!v[PAIR_U - 1]) break;
   }
-  nnb = team_sum_i<L>(nnb);
-  if (lane == 0) {
-    const double sd = sigma_d<D>(h);
-    b.dsum[(int64_t)DS_SIG * cap + j] = ss * sd;
-    b.dsum[(int64_t)DS_S * cap + j] = st * sd;
-    b.dsum[(int64_t)DS_NB * cap + j] = sn0 * sd;
-    b.dsum[(int64_t)DS_NS * cap + j] = sn1 * sd;
-    b.dsum[(int64_t)DS_NQ * cap + j] = sn2 * sd;
-    b.dsum[(int64_t)DS_NNB * cap + j] = (double)nnb;
-  }
+  double sums[5];
+  int nnb;
+  A.template reduce<L>(sums, &nnb);
+  if (lane == 0) write_density<D>(b, prm, j, sums, nnb);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,12 +282,56 @@ __global__ void __launch_bounds__(128) k_eos(BatchDev b, Params prm, EosDev eos,
   wave_count_eos(b.evt, e, c_backup, c_iters, c_noconv);
 }
 
-// ---------------------------------------------------------------------------
+// own record and geometry of particle j for the gradient sums
+template <int D, bool VISC, bool MIXED>
+__device__ __forceinline__ void grad_setup(const BatchDev& b, const Params& prm, const double* __restrict__ Y,
+                                           double t, int64_t j, GradAcc<D, VISC, MIXED>& A) {
+  const int64_t cap = b.cap;
+  const double G3 = metric_G3(prm, t);
+  A.Gk[0] = 0.0;
+  A.Gk[1] = 1.0;
+  A.Gk[2] = 1.0;
+  A.Gk[3] = G3;
+  A.ih = 1.0 / prm.h;
+  A.xa[0] = row(Y, cap, R_X1, j);
+  A.xa[1] = row(Y, cap, R_X2, j);
+  A.xa[2] = D == 3 ? row(Y, cap, R_X3, j) : 0.0;
+  auto recv = [&](int q) -> double {
+    return MIXED ? (double)b.recf[(int64_t)q * cap + j] : b.rec[(int64_t)q * cap + j];
+  };
+  A.aPP = recv(Q_PP);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A.aU[k] = k < D ? recv(Q_U1 + k) : 0.0;
+    A.aV[k] = k < D ? recv(Q_V1 + k) : 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) A.aA[k][i] = (VISC && k < D && i < D) ? recv(Q_A11 + k * 3 + i) : 0.0;
+  }
+  A.init();
+}
+
+template <int D, bool VISC, bool MIXED>
+__device__ __forceinline__ void write_grad(const BatchDev& b, const Params& prm, int64_t j,
+                                           const GradAcc<D, VISC, MIXED>& A) {
+  const int64_t cap = b.cap;
+  const double fsd = sigma_d<D>(prm.h) / prm.h;
+  const double isg = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
+#pragma unroll
+  for (int i = 0; i < D; ++i) b.gsum[(int64_t)(GS_F1 + i) * cap + j] = A.F[i] * fsd;
+#pragma unroll
+  for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+    for (int nu = 0; nu < D; ++nu) b.gsum[(int64_t)(GS_DU11 + kk * 3 + nu) * cap + j] = A.du[kk][nu] * isg;
+  b.gsum[(int64_t)GS_DIVV * cap + j] = A.dv * isg;
+}
+
 template <int D, bool VISC, bool MIXED>
 __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
                                               int64_t nslots) {
   constexpr int L = Team<D>::L;
-  constexpr int NA = D * D;  // viscous components A^{ji}
+  constexpr int ROWS = RowBlock<D>::ROWS;
+  using RT = typename GradAcc<D, VISC, MIXED>::RT;
+  __shared__ int32_t s_lo[Team<D>::PER_BLOCK][ROWS], s_hi[Team<D>::PER_BLOCK][ROWS];
   const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t j = tid / L;
   const int lane = (int)(tid % L);
@@ -323,126 +339,50 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   const int e = b.ev[j];
   if (e < 0) return;
   const EventDev& E = b.evt[e];
-  const double t = E.t + stage * E.dt;
   const int64_t cap = b.cap;
-  const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
-  const double G3 = metric_G3(prm, t);
-  const double Gk[4] = {0.0, 1.0, 1.0, G3};
-  const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
-
-  // own record (A stored as [j][i] with stride 3)
-  auto recv = [&](int q, int64_t k) -> double {
-    return MIXED ? (double)b.recf[(int64_t)q * cap + k] : b.rec[(int64_t)q * cap + k];
-  };
-  double aPP = recv(Q_PP, j), aU[3], aV[3], aA[3][3];
+  const double r2max = (2.0 * prm.h) * (2.0 * prm.h);
+  GradAcc<D, VISC, MIXED> A;
+  grad_setup<D, VISC, MIXED>(b, prm, Y, E.t + stage * E.dt, j, A);
+  const int team = (int)threadIdx.x / L;
+  team_rows<D, L>(b, E, b.keys[j], A.xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+  RowCursor<L, ROWS> cur;
+  cur.start(s_lo[team], s_hi[team], lane);
+  const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
+  const int32_t self = (int32_t)j;
+  for (;;) {
+    int32_t k[PAIR_U];
+    bool v[PAIR_U];
+    take(cur, self, k, v);
+    if (!v[0]) break;
+    double xb[PAIR_U][3], d2[PAIR_U];
+    bool ok[PAIR_U];
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    aU[k] = recv(Q_U1 + k, j);
-    aV[k] = recv(Q_V1 + k, j);
-  }
-  if (VISC) {
-#pragma unroll
-    for (int jj = 0; jj < D; ++jj)
-#pragma unroll
-      for (int ii = 0; ii < D; ++ii) aA[jj][ii] = recv(Q_A11 + jj * 3 + ii, j);
-  }
-
-  double F[3] = {0.0, 0.0, 0.0}, du[3][3], dv = 0.0;
-  Kahan kF[3], kdu[3][3], kdv{0.f, 0.f};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    kF[k] = Kahan{0.f, 0.f};
-#pragma unroll
-    for (int n = 0; n < 3; ++n) {
-      du[k][n] = 0.0;
-      kdu[k][n] = Kahan{0.f, 0.f};
+    for (int u = 0; u < PAIR_U; ++u) {
+      xb[u][0] = row(Y, cap, R_X1, k[u]);
+      xb[u][1] = row(Y, cap, R_X2, k[u]);
+      xb[u][2] = D == 3 ? row(Y, cap, R_X3, k[u]) : 0.0;
+      d2[u] = dist2<D>(A.xa, xb[u]);
+      ok[u] = v[u] && d2[u] < r2max;
     }
-  }
-  int acc = 0;
-  const int team_base = (int)(threadIdx.x & 63) - lane;
-  for_each_row_team<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, team_base, [&](int32_t lo, int32_t hi) {
-    for (int32_t k = first_of<L>(lo, acc, lane); k < hi; k += L) {
-      const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
-      const double d2 = dist2<D>(xa, xb);
-      if (!(d2 < r2max)) continue;
-      if (MIXED) {
-        const float d2f = (float)d2;
-        if (!(d2f > 0.0f)) continue;  // self pair: grad W = 0
-        const float ir = fast_rsqf(d2f);
-        const float f = spline_dwf(d2f * ir * (float)ih) * ir;
-        float dW[3];
 #pragma unroll
-        for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[q]) * f;
-        const float pp = (float)aPP + b.recf[(int64_t)Q_PP * cap + k];
+    for (int u = 0; u < PAIR_U; ++u) {
+      const int32_t m = ok[u] ? k[u] : self;
+      RT bA[3][3], bU[3], bV[3];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-          float val = pp * dW[i];
-          if (VISC) {
-            float vis = 0.f;
+      for (int q = 0; q < 3; ++q) {
+        bU[q] = q < D ? rb[(int64_t)(Q_U1 + q) * cap + m] : RT(0);
+        bV[q] = q < D ? rb[(int64_t)(Q_V1 + q) * cap + m] : RT(0);
 #pragma unroll
-            for (int jj = 0; jj < D; ++jj)
-              vis += ((float)aA[jj][i] + b.recf[(int64_t)(Q_A11 + jj * 3 + i) * cap + k]) * dW[jj];
-            val += (float)Gk[i + 1] * vis;
-          }
-          kF[i].add(val);
-        }
-        float dvv = 0.f;
-#pragma unroll
-        for (int kk = 0; kk < D; ++kk) {
-#pragma unroll
-          for (int nu = 0; nu < D; ++nu)
-            kdu[kk][nu].add((b.recf[(int64_t)(Q_U1 + nu) * cap + k] - (float)aU[nu]) * dW[kk]);
-          dvv += (b.recf[(int64_t)(Q_V1 + kk) * cap + k] - (float)aV[kk]) * dW[kk];
-        }
-        kdv.add(dvv);
-      } else {
-        const double rr = sqrt(d2);
-        if (!(rr > 0.0)) continue;
-        const double f = spline_dw(rr * ih) / rr;
-        double dW[3];
-#pragma unroll
-        for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[q]) * f;
-        const double pp = aPP + b.rec[(int64_t)Q_PP * cap + k];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-          double val = pp * dW[i];
-          if (VISC) {
-            double vis = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < D; ++jj) vis += (aA[jj][i] + b.rec[(int64_t)(Q_A11 + jj * 3 + i) * cap + k]) * dW[jj];
-            val += Gk[i + 1] * vis;
-          }
-          F[i] += val;
-        }
-#pragma unroll
-        for (int kk = 0; kk < D; ++kk) {
-#pragma unroll
-          for (int nu = 0; nu < D; ++nu) du[kk][nu] += (b.rec[(int64_t)(Q_U1 + nu) * cap + k] - aU[nu]) * dW[kk];
-          dv += (b.rec[(int64_t)(Q_V1 + kk) * cap + k] - aV[kk]) * dW[kk];
-        }
+        for (int i = 0; i < 3; ++i)
+          bA[q][i] = (VISC && q < D && i < D) ? rb[(int64_t)(Q_A11 + q * 3 + i) * cap + m] : RT(0);
       }
+      const RT bpp = rb[(int64_t)Q_PP * cap + m];
+      if (ok[u]) A.add(xb[u], d2[u], bpp, bA, bU, bV);
     }
-    acc += hi - lo;
-  });
-  (void)NA;
-#pragma unroll
-  for (int i = 0; i < D; ++i) F[i] = MIXED ? team_sum_k<L>(kF[i]) : team_sum<L>(F[i]);
-#pragma unroll
-  for (int kk = 0; kk < D; ++kk)
-#pragma unroll
-    for (int nu = 0; nu < D; ++nu) du[kk][nu] = MIXED ? team_sum_k<L>(kdu[kk][nu]) : team_sum<L>(du[kk][nu]);
-  dv = MIXED ? team_sum_k<L>(kdv) : team_sum<L>(dv);
-  if (lane == 0) {
-    const double fsd = sigma_d<D>(h) * ih;
-    const double isg = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
-#pragma unroll
-    for (int i = 0; i < D; ++i) b.gsum[(int64_t)(GS_F1 + i) * cap + j] = F[i] * fsd;
-#pragma unroll
-    for (int kk = 0; kk < D; ++kk)
-#pragma unroll
-      for (int nu = 0; nu < D; ++nu) b.gsum[(int64_t)(GS_DU11 + kk * 3 + nu) * cap + j] = du[kk][nu] * isg;
-    b.gsum[(int64_t)GS_DIVV * cap + j] = dv * isg;
+    if (!v[PAIR_U - 1]) break;
   }
+  A.template reduce<L>();
+  if (lane == 0) write_grad<D, VISC, MIXED>(b, prm, j, A);
 }
 
 // Source densities I^mu, I_q at position x and time t: sum over the active
@@ -647,7 +587,12 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
   constexpr int L = Team<D>::L;
   const unsigned gt = nblocks(nslots * L, 256), gp = nblocks(nslots, 128);
   if (mk) (void)hipEventRecord(mk[0], s);
-  hipLaunchKernelGGL((k_density<D, MIXED>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
+  if (prm.density_mode != 0)
+    hipLaunchKernelGGL((k_density<D, MIXED, 0>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
+  else if (prm.ncharge)
+    hipLaunchKernelGGL((k_density<D, MIXED, 4>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
+  else
+    hipLaunchKernelGGL((k_density<D, MIXED, 1>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
   if (mk) (void)hipEventRecord(mk[1], s);
   if (prm.ncharge)
     hipLaunchKernelGGL((k_eos<D, VISC, MIXED, 3>), dim3(gp), dim3(128), 0, s, b, prm, eos, Y, stage, nslots, aux);
