@@ -38,7 +38,10 @@ GROUPS = ["binning", "density_sums", "eos_inversion", "gradient_sums", "eom_upda
 # sources that the stage kernels are compiled from; the measured HBM traffic of
 # a kernel is reported only while these are unchanged since the counters were read
 KERNEL_SOURCES = ["common.h", "sph_device.h", "eos_device.h", "eom_device.h", "stage.hip"]
-TRAFFIC_FILES = {"eos_inversion": "eos_inversion_lumpy2d_40k_traffic.txt"}
+TRAFFIC_FILES = {g: f"{g}_lumpy2d_40k_traffic.txt" for g in GROUPS[1:]}
+# kernel-name prefixes of the groups in the counter output
+GROUP_KERNELS = {"density_sums": "void ccake::k_density<", "eos_inversion": "void ccake::k_eos<",
+                 "gradient_sums": "void ccake::k_grad<", "eom_update": "void ccake::k_eom<"}
 
 
 def kernel_source_digest():
@@ -70,6 +73,52 @@ def measured_traffic(group):
     fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 / float(kv["copy_fetch_factor"])
     write = float(kv["write_kib_per_dispatch"]) * 1024 / float(kv["copy_write_factor"])
     return fetch + write
+
+
+def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, out_dir, command):
+    """Write one traffic file per kernel group from rocprofv3 --pmc output:
+    mean FETCH_SIZE and WRITE_SIZE (KiB) per dispatch of the group's kernel,
+    and the factors that the same counters read per KiB actually moved by a
+    plain copy of copy_mib MiB (read copy_mib, write copy_mib)."""
+    import csv
+    import glob
+
+    def means(d, counter):
+        acc = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter:
+                    acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+    kib = copy_mib * 1024.0
+    cf = [v for k, v in means(copy_fetch_dir, "FETCH_SIZE").items() if "k_copy" in k]
+    cw = [v for k, v in means(copy_write_dir, "WRITE_SIZE").items() if "k_copy" in k]
+    if len(cf) != 1 or len(cw) != 1:
+        raise SystemExit("copy calibration dispatch not found")
+    f_factor, w_factor = cf[0][0] / kib, cw[0][0] / kib
+    fetch, write = means(fetch_dir, "FETCH_SIZE"), means(write_dir, "WRITE_SIZE")
+    digest = kernel_source_digest()
+    for g, prefix in GROUP_KERNELS.items():
+        fk = [(k, v) for k, v in fetch.items() if k.startswith(prefix)]
+        wk = [(k, v) for k, v in write.items() if k.startswith(prefix)]
+        if len(fk) != 1 or len(wk) != 1:
+            raise SystemExit(f"{g}: expected one kernel instance, found {[k for k, _ in fk]}")
+        (kname, (fm, fn)), (_, (wm, wn)) = fk[0], wk[0]
+        path = os.path.join(out_dir, TRAFFIC_FILES[g])
+        with open(path, "w") as fh:
+            fh.write(f"# HBM traffic of {kname.split('(')[0]} on the 40,000-particle 2+1D viscous BSQ lumpy\n"
+                     f"# event (mixed precision), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of the\n"
+                     f"# native driver; KiB per dispatch (mean over {fn} and {wn} dispatches), scaled by what\n"
+                     f"# the counters read per KiB of a {copy_mib} MiB device copy.  Commands:\n")
+            for line in command.strip().splitlines():
+                fh.write(f"#   {line}\n")
+            fh.write(f"kernel: {kname.split('(')[0]}\n")
+            fh.write(f"fetch_kib_per_dispatch: {fm:.1f}\nwrite_kib_per_dispatch: {wm:.1f}\n")
+            fh.write(f"copy_fetch_factor: {f_factor:.4f}\ncopy_write_factor: {w_factor:.4f}\n")
+            fh.write(f"hbm_bytes_per_dispatch: {fm * 1024 / f_factor + wm * 1024 / w_factor:.0f}\n")
+            fh.write(f"source_digest: {digest}\n")
+        print(path)
 
 
 def algorithmic_model(dim, viscous, ncharge, mixed, smoothed=True):
@@ -263,16 +312,17 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes": n}))
 
 
-def write_inputs(path):
-    """The headline workload in the native driver's file format (see
+def write_inputs(path, three_d=False):
+    """The headline workload (or the 1.2 M-particle 3+1D event), mixed
+    precision, in the native driver's file format (see
     paper_2511_22852_amd/csrc/ccake_bench.cpp)."""
     import struct
     import numpy as np
     from paper_2511_22852_amd import binding as B
     from paper_2511_22852_amd import inputs as I
-    w = I.lumpy_2d_workload()
+    w = I.lumpy_3d_workload() if three_d else I.lumpy_2d_workload()
     cols, lo, hi = I.massless_gas_table()
-    cfg = B.config(dim=2, hyperbolic=True, viscous=True, precision=B.MIXED, ncharge=3, h=w.h,
+    cfg = B.config(dim=3 if three_d else 2, hyperbolic=True, viscous=True, precision=B.MIXED, ncharge=3, h=w.h,
                    eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02)
     with open(path, "wb") as f:
         f.write(b"CCAKEBN1")
@@ -301,8 +351,14 @@ def main():
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both",
                     help="which precisions to run (counter-collection passes use one)")
     ap.add_argument("--write-inputs", metavar="PATH",
-                    help="only write the headline workload (mixed precision) for the native driver "
-                         "paper_2511_22852_amd/ccake_bench and exit")
+                    help="only write the headline workload (with --only-3d: the 1.2 M-particle 3+1D "
+                         "event), mixed precision, for the native driver paper_2511_22852_amd/ccake_bench "
+                         "and exit")
+    ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "MIB"),
+                    help="only write profiles/*_traffic.txt from rocprofv3 --pmc output directories of the "
+                         "native driver (FETCH_SIZE, WRITE_SIZE) and of its --copy MIB calibration, and exit")
+    ap.add_argument("--counter-command", default="",
+                    help="with --summarize-counters: the commands that produced the counters (recorded)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (reference kernel for the HBM "
                          "byte counters) and exit")
@@ -311,11 +367,15 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
               "note, not a measured path.", file=sys.stderr)
         sys.exit(2)
+    if args.summarize_counters:
+        fd, wd, cfd, cwd, mib = args.summarize_counters
+        summarize_counters(fd, wd, cfd, cwd, int(mib), os.path.join(ROOT, "profiles"), args.counter_command)
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
     if args.write_inputs:
-        write_inputs(args.write_inputs)
+        write_inputs(args.write_inputs, args.only_3d)
         return
 
     from paper_2511_22852_amd import binding as B

@@ -46,10 +46,13 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
-    # native driver of the C ABI (no Python in the process), linked to the library
+    # native driver of the C ABI (no Python in the process) with the same
+    # objects linked into the executable: the counter profiler collects per
+    # dispatch only for kernels of the executable's own code objects
+    main_obj = os.path.join(BUILD, "ccake_bench.o")
+    _run(["hipcc", *HIPCC_FLAGS, "-c", os.path.join(CSRC, "ccake_bench.cpp"), "-o", main_obj])
     tmp = DRIVER + ".tmp"
-    _run(["hipcc", *HIPCC_FLAGS, "-o", tmp, os.path.join(CSRC, "ccake_bench.cpp"), f"-L{PKG}", "-lccake_hip",
-          "-Wl,-rpath,$ORIGIN"])
+    _run(["hipcc", f"--offload-arch={ARCH}", "-o", tmp, main_obj, *objs, "-lpthread"])
     os.replace(tmp, DRIVER)
     return LIB
 

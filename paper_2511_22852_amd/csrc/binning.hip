@@ -1,7 +1,7 @@
 // Cell binning of a batch of events: per-event bounding box and grid (cell
 // edge >= 2h + skin, the kernel support of "Kernel function" plus the skin
-// that keeps stage-2 pairs inside the block), stable counting sort of the
-// particles by (cell, original id).  This is the uniform-grid neighbour
+// that keeps stage-2 pairs inside the block), counting sort of the particles
+// by cell, then by (x^1, original id) inside each cell.  This is the uniform-grid neighbour
 // binning the paper takes from Cabana's VerletList, rebuilt as
 //   k_bbox   min/max per event: each block reduces 8192 slots, then one atomic
 //            per axis on order-preserving integer images of the coordinates
@@ -9,9 +9,11 @@
 //   k_count  particle -> cell key, atomic count per cell
 //   k_scan   one block per event: exclusive scan of the counts
 //   k_scatter particle -> slot of its cell (arbitrary order within the cell)
-//   k_cellsort one wave per cell: rank by original id, so the order inside a
-//            cell is deterministic; clears the counts for the next binning
-//   k_permute gather of the state, warm starts, ids and keys into cell order
+//   k_cellsort one wave per cell: rank by (x^1, original id), so the order
+//            inside a cell is deterministic and every x-row of cells is
+//            sorted by x^1; clears the counts for the next binning
+//   k_permute gather of the state, warm starts, ids and keys into cell order,
+//            and the binning-time x^1 of every slot
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -217,7 +219,18 @@ __global__ void __launch_bounds__(256) k_scatter(BatchDev b, int64_t nslots) {
 // one wave per cell: the rank of each member is the number of members with a
 // smaller original id (ids are unique within an event)
 constexpr int SORT_CAP = 1024;  // members per cell held in LDS by one wave
+// sort key inside a cell: binning-time x^1 (total order on the bits), then id
+struct CellKey {
+  unsigned long long x;
+  int32_t id;
+  __device__ __forceinline__ bool operator<(const CellKey& o) const { return x < o.x || (x == o.x && id < o.id); }
+};
+__device__ __forceinline__ CellKey cell_key(const BatchDev& b, int32_t p) {
+  return CellKey{ordered_bits(b.Y0[(int64_t)R_X1 * b.cap + p]), b.id[p]};
+}
+
 __global__ void __launch_bounds__(256) k_cellsort(BatchDev b, int dim) {
+  __shared__ unsigned long long s_x[4][SORT_CAP];
   __shared__ int32_t s_id[4][SORT_CAP];
   __shared__ int32_t s_p[4][SORT_CAP];
   const int e = blockIdx.y;
@@ -236,15 +249,17 @@ __global__ void __launch_bounds__(256) k_cellsort(BatchDev b, int dim) {
     if (m <= SORT_CAP) {
       for (int k = lane; k < m; k += 64) {
         const int32_t p = b.perm[s + k];
+        const CellKey key = cell_key(b, p);
         s_p[w][k] = p;
-        s_id[w][k] = b.id[p];
+        s_x[w][k] = key.x;
+        s_id[w][k] = key.id;
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       for (int k = lane; k < m; k += 64) {
-        const int32_t mine = s_id[w][k];
+        const CellKey mine{s_x[w][k], s_id[w][k]};
         int rank = 0;
-        for (int q = 0; q < m; ++q) rank += s_id[w][q] < mine ? 1 : 0;
+        for (int q = 0; q < m; ++q) rank += CellKey{s_x[w][q], s_id[w][q]} < mine ? 1 : 0;
         b.perm[s + rank] = s_p[w][k];
       }
       __builtin_amdgcn_wave_barrier();
@@ -252,9 +267,9 @@ __global__ void __launch_bounds__(256) k_cellsort(BatchDev b, int dim) {
       // oversized cell (degenerate grid): insertion sort by one lane
       for (int32_t i = s + 1; i < s + m; ++i) {
         const int32_t p = b.perm[i];
-        const int32_t pid = b.id[p];
+        const CellKey pk = cell_key(b, p);
         int32_t j = i - 1;
-        while (j >= s && b.id[b.perm[j]] > pid) {
+        while (j >= s && pk < cell_key(b, b.perm[j])) {
           b.perm[j + 1] = b.perm[j];
           --j;
         }
@@ -276,7 +291,10 @@ __global__ void __launch_bounds__(256) k_permute(BatchDev b, int64_t nslots, uin
     if (rowmask & (1u << r)) b.Ys[(int64_t)r * b.cap + j] = b.Y0[(int64_t)r * b.cap + src];
   for (int w = 0; w < NWARM; ++w) b.warms[(int64_t)w * b.cap + j] = b.warm[(int64_t)w * b.cap + src];
   b.ids[j] = b.id[src];
-  if (moved) b.keys[j] = b.key[src];
+  if (moved) {
+    b.keys[j] = b.key[src];
+    b.xbin[j] = b.Y0[(int64_t)R_X1 * b.cap + src];
+  }
 }
 
 // sorted -> home (after an initialisation)

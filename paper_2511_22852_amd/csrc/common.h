@@ -160,6 +160,7 @@ struct BatchDev {
   int32_t* key;      // local cell key (home order)
   int32_t* keys;     // local cell key (sorted order)
   int32_t* perm;     // sorted slot -> home slot
+  double* xbin;      // x^1 of each slot at its event's last binning (sorted order)
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

@@ -19,8 +19,8 @@ struct Handle {
 
 // byte offsets of the arrays of one batch inside its workspace
 struct Layout {
-  size_t Y0, Ys, Y1, th, rec, recf, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, cs, cf, evt, scratch, src,
-      total;
+  size_t Y0, Ys, Y1, th, rec, recf, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, xbin, cs, cf, evt,
+      scratch, src, total;
 };
 
 ccake_status fail(Handle* h, ccake_status code, const char* fmt, ...);

@@ -108,15 +108,13 @@ __device__ __forceinline__ double dist2(const double xa[3], const double xb[3]) 
 }
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
-// block index.  On large grids the hardware index is mapped to a logical one
-// that gives every XCD one contiguous share of the cell-sorted particles, so
-// the neighbourhoods it reads stay in its own L2 (measured: 12% on the FP64
-// 1.2 M-particle 3D event).  Small grids, whose data fit every L2 anyway, keep
-// the plain order (the remap cost them a few per cent).  Bijective.
+// block index.  The hardware index is mapped to a logical one that gives every
+// XCD one contiguous share of the cell-sorted particles, so the neighbourhoods
+// it reads stay in its own L2 instead of every L2 fetching nearly all of them
+// (on the 40k-particle 2D event this cuts the HBM fetch of the pair kernels
+// about fivefold; 12% time on the FP64 1.2 M-particle 3D event).  Bijective.
 constexpr int NUM_XCD = 8;
-constexpr int64_t XCD_REMAP_MIN_BLOCKS = 8192;
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
-  if (nblocks < XCD_REMAP_MIN_BLOCKS) return b;
   const int64_t x = b % NUM_XCD, k = b / NUM_XCD;
   const int64_t q = nblocks / NUM_XCD, r = nblocks % NUM_XCD;
   return x * q + (x < r ? x : r) + k;
@@ -203,11 +201,19 @@ __device__ __forceinline__ void for_each_row(const BatchDev& b, const EventDev& 
   }
 }
 
-// Team version of for_each_row, with the rows kept in LDS.  The L lanes of a
-// team (contiguous lanes of one wave) share the row set-up: row r of the block
-// (r = (dz + S)(2S + 1) + dy + S) is trimmed by lane r mod L and its slot range
-// stored at lo[r], hi[r] (empty rows as lo = hi).  The team then walks the
-// concatenation of its rows with RowCursor below.
+// Team version of for_each_row, with the rows kept in LDS and trimmed in x^1
+// to the particle, not just to cells.  Cells are sorted by x^1 inside (and
+// ordered by x^1 along a row), so the binning-time coordinates xbin of a
+// row's slots increase along it.  A candidate b in row (y, z) can be within
+// the support now only if |xbin_b - x_a| <= rx (rx from the row's gap to x_a
+// with reach = support + skin: b moved at most half the skin since
+// binning), so the row is cut to the slots whose xbin lies in
+// [x_a - rx, x_a + rx]; only its first and last cells need a search (binary,
+// all searches of a lane interleaved, so they cost one round of dependent
+// loads per halving).  Row r of the block (r = (dz + S)(2S + 1) + dy + S) is
+// set up by lane r mod L; its slot range is stored at lo[r], hi[r] (empty
+// rows as lo = hi).  The team then walks the concatenation of its rows with
+// RowCursor below.
 template <int D>
 struct RowBlock {
   static constexpr int W = 2 * SUBCELLS + 1;
@@ -229,31 +235,84 @@ __device__ __forceinline__ void team_rows(const BatchDev& b, const EventDev& E, 
   const double R = reach * (1.0 + 1e-9);
   const double R2 = R * R;
   const int32_t* cs = b.cell_start + E.c_base;
+  // per row of this lane: first cell [s0, e0), last cell [s1, e1), x^1 interval
+  int32_t s0[PER], e0[PER], s1[PER], e1[PER];
+  double xl[PER], xh[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int r = lane + q * L;
+    s0[q] = e0[q] = s1[q] = e1[q] = 0;
+    xl[q] = xh[q] = 0.0;
     if (r >= ROWS) continue;
-    int32_t rlo = 0, rhi = 0;
     const int dz = D == 3 ? r / W - SUBCELLS : 0, dy = r % W - SUBCELLS;
     const int z = iz + dz, y = iy + dy;
-    if (z >= 0 && z < nz && y >= 0 && y < ny) {
-      const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
-      const double gy = interval_gap(xa[1], E.lo[1] + y * e, e);
-      const double r2 = R2 - gy * gy - gz * gz;
-      if (r2 >= 0.0) {
-        const double rx = sqrt(r2) * (1.0 + 1e-9);
-        int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
-        x0 = max(x0, max(ix - SUBCELLS, 0));
-        x1 = min(x1, min(ix + SUBCELLS, nx - 1));
-        if (x0 <= x1) {
-          const int c = (z * ny + y) * nx;
-          rlo = cs[c + x0];
-          rhi = cs[c + x1 + 1];
+    if (z < 0 || z >= nz || y < 0 || y >= ny) continue;
+    const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
+    const double gy = interval_gap(xa[1], E.lo[1] + y * e, e);
+    const double r2 = R2 - gy * gy - gz * gz;
+    if (!(r2 >= 0.0)) continue;
+    const double rx = sqrt(r2) * (1.0 + 1e-9);
+    int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
+    x0 = max(x0, max(ix - SUBCELLS, 0));
+    x1 = min(x1, min(ix + SUBCELLS, nx - 1));
+    if (x0 > x1) continue;
+    const int c = (z * ny + y) * nx;
+    s0[q] = cs[c + x0];
+    e0[q] = cs[c + x0 + 1];
+    s1[q] = cs[c + x1];
+    e1[q] = cs[c + x1 + 1];
+    xl[q] = xa[0] - rx;
+    xh[q] = xa[0] + rx;
+  }
+  // lower bound of xl in the first cell, upper bound of xh in the last cell
+  int32_t f0[PER], n0[PER], f1[PER], n1[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    f0[q] = s0[q];
+    n0[q] = e0[q] - s0[q];
+    f1[q] = s1[q];
+    n1[q] = e1[q] - s1[q];
+  }
+  for (;;) {
+    bool more = false;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) more = more || n0[q] > 0 || n1[q] > 0;
+    if (!more) break;
+    double v0[PER], v1[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {  // probes of finished searches read a valid slot and are ignored
+      v0[q] = b.xbin[n0[q] > 0 ? f0[q] + (n0[q] >> 1) : 0];
+      v1[q] = b.xbin[n1[q] > 0 ? f1[q] + (n1[q] >> 1) : 0];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      if (n0[q] > 0) {
+        const int32_t half = n0[q] >> 1;
+        if (v0[q] < xl[q]) {
+          f0[q] += half + 1;
+          n0[q] -= half + 1;
+        } else {
+          n0[q] = half;
+        }
+      }
+      if (n1[q] > 0) {
+        const int32_t half = n1[q] >> 1;
+        if (v1[q] <= xh[q]) {
+          f1[q] += half + 1;
+          n1[q] -= half + 1;
+        } else {
+          n1[q] = half;
         }
       }
     }
-    lo[r] = rlo;
-    hi[r] = rhi;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int r = lane + q * L;
+    if (r < ROWS) {
+      lo[r] = f0[q];
+      hi[r] = f1[q];
+    }
   }
   // the rows are read back by other lanes of the same wave
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
