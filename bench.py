@@ -37,7 +37,7 @@ GROUPS = ["binning", "density_sums", "eos_inversion", "gradient_sums", "eom_upda
 
 # sources that the stage kernels are compiled from; the measured HBM traffic of
 # a kernel is reported only while these are unchanged since the counters were read
-KERNEL_SOURCES = ["common.h", "sph_device.h", "eos_device.h", "eom_device.h", "stage.hip"]
+KERNEL_SOURCES = ["common.h", "sph_device.h", "pair_device.h", "eos_device.h", "eom_device.h", "stage.hip"]
 TRAFFIC_FILES = {g: f"{g}_lumpy2d_40k_traffic.txt" for g in GROUPS[1:]}
 # kernel-name prefixes of the groups in the counter output
 GROUP_KERNELS = {"density_sums": "void ccake::k_density<", "eos_inversion": "void ccake::k_eos<",

@@ -3,8 +3,9 @@
 // that keeps stage-2 pairs inside the block), counting sort of the particles
 // by cell, then by (x^1, original id) inside each cell.  This is the uniform-grid neighbour
 // binning the paper takes from Cabana's VerletList, rebuilt as
-//   k_bbox   min/max per event: each block reduces 8192 slots, then one atomic
-//            per axis on order-preserving integer images of the coordinates
+//   k_bbox   min/max per event: a few blocks per event reduce its slots, then
+//            one atomic per axis and block on order-preserving integer images
+//            of the coordinates
 //   k_grid   one thread per event: grid origin, cells per axis, reset of the box
 //   k_count  particle -> cell key, atomic count per cell
 //   k_scan   one block per event: exclusive scan of the counts
@@ -16,42 +17,51 @@
 //            and the binning-time x^1 of every slot
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 #include "sph_device.h"
 
 namespace ccake {
 
-// slots per k_bbox block: few blocks, so few atomics on the same addresses
-constexpr int BBOX_PER_THREAD = 32;
+// k_bbox: blocks (x, e) reduce slices of `per` x 256 slots of event e (an
+// event's slots are contiguous), BBOX_BATCH per thread at a time with the
+// loads of a batch issued together; one atomic per axis and block on the
+// event's box, so an event sees at most gridDim.x atomics per address
+constexpr int BBOX_BATCH = 8;
 
-__global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslots) {
+__global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int per) {
   __shared__ double s_lo[4][3], s_hi[4][3];
-  __shared__ int s_e[4];
+  const int e = blockIdx.y;
+  const EventDev& E = b.evt[e];
+  if (!E.active || !E.rebin) return;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x * per;
+  if (first >= E.n) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t base = (int64_t)blockIdx.x * blockDim.x * BBOX_PER_THREAD;
-  // the block's event: that of its first slot (slots of an event are contiguous)
-  int main = base < nslots ? b.ev[base] : -1;
-  if (main >= 0 && !b.evt[main].rebin) main = -1;
+  const int64_t n = E.n, p0 = E.p_base;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int q = 0; q < BBOX_PER_THREAD; ++q) {
-    const int64_t i = base + (int64_t)q * blockDim.x + threadIdx.x;
-    if (i >= nslots) break;
-    int e = b.ev[i];
-    if (e < 0 || !b.evt[e].rebin) continue;  // empty slot, or keeps its cells this step
-    for (int k = 0; k < dim; ++k) {
-      const double x = row(b.Y0, b.cap, R_X1 + k, i);
-      if (!isfinite(x)) continue;
-      if (e == main) {
-        lo[k] = fmin(lo[k], x);
-        hi[k] = fmax(hi[k], x);
-      } else {  // another event inside this block's slots (batches only)
-        atomicMin(&b.evt[e].bb_min[k], ordered_bits(x));
-        atomicMax(&b.evt[e].bb_max[k], ordered_bits(x));
-      }
+  for (int q0 = 0; q0 < per; q0 += BBOX_BATCH) {
+    double x[BBOX_BATCH][3];
+    bool v[BBOX_BATCH];
+#pragma unroll
+    for (int u = 0; u < BBOX_BATCH; ++u) {
+      const int64_t i = first + (int64_t)(q0 + u) * blockDim.x + threadIdx.x;
+      v[u] = q0 + u < per && i < n;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) x[u][k] = (v[u] && k < dim) ? row(b.Y0, b.cap, R_X1 + k, p0 + i) : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < BBOX_BATCH; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (v[u] && k < dim && isfinite(x[u][k])) {
+          lo[k] = fmin(lo[k], x[u][k]);
+          hi[k] = fmax(hi[k], x[u][k]);
+        }
   }
-  for (int k = 0; k < dim; ++k) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       lo[k] = fmin(lo[k], __shfl_xor(lo[k], off, 64));
@@ -59,14 +69,13 @@ __global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslot
     }
   }
   if (lane == 0) {
-    s_e[w] = main;
     for (int k = 0; k < 3; ++k) {
       s_lo[w][k] = lo[k];
       s_hi[w][k] = hi[k];
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && main >= 0) {
+  if (threadIdx.x == 0) {
     const int nw = (int)(blockDim.x >> 6);
     for (int k = 0; k < dim; ++k) {
       double l = s_lo[0][k], h = s_hi[0][k];
@@ -74,8 +83,8 @@ __global__ void __launch_bounds__(256) k_bbox(BatchDev b, int dim, int64_t nslot
         l = fmin(l, s_lo[a][k]);
         h = fmax(h, s_hi[a][k]);
       }
-      if (isfinite(l)) atomicMin(&b.evt[main].bb_min[k], ordered_bits(l));
-      if (isfinite(h)) atomicMax(&b.evt[main].bb_max[k], ordered_bits(h));
+      if (isfinite(l)) atomicMin(&b.evt[e].bb_min[k], ordered_bits(l));
+      if (isfinite(h)) atomicMax(&b.evt[e].bb_max[k], ordered_bits(h));
     }
   }
 }
@@ -168,37 +177,71 @@ __global__ void __launch_bounds__(256) k_count(BatchDev b, int dim, int64_t nslo
   if (e >= 0 && head == lane) atomicAdd(&b.cell_fill[cell], len);
 }
 
-// exclusive scan of the cell counts of one event (one 1024-thread block per event)
+// exclusive scan of the cell counts of one event (one 1024-thread block per
+// event), over tiles of SCAN_TILE cells: each tile is loaded into LDS with
+// coalesced loads, every thread scans SCAN_PER consecutive cells, and the
+// per-thread totals are scanned across the block (waves by shuffles, then
+// the wave totals)
+constexpr int SCAN_T = 1024, SCAN_PER = 8, SCAN_TILE = SCAN_T * SCAN_PER;
+
 __global__ void __launch_bounds__(1024) k_scan(BatchDev b, int dim) {
   const int e = blockIdx.x;
   const EventDev& E = b.evt[e];
   if (!E.active || !E.rebin) return;
   int64_t ncell = 1;
   for (int k = 0; k < dim; ++k) ncell *= E.nc[k];
-  __shared__ int32_t part[1024];
-  const int T = blockDim.x;
-  const int64_t chunk = (ncell + T - 1) / T;
-  const int64_t c0 = threadIdx.x * chunk, c1 = min(ncell, c0 + chunk);
+  __shared__ int32_t s_c[SCAN_TILE];
+  __shared__ int32_t s_w[SCAN_T / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   int32_t* cf = b.cell_fill + E.c_base;
   int32_t* cs = b.cell_start + E.c_base;
-  int32_t sum = 0;
-  for (int64_t c = c0; c < c1; ++c) sum += cf[c];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {
-    const int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+  int32_t run = (int32_t)E.p_base;  // slot of the first cell of the tile
+  for (int64_t t0 = 0; t0 < ncell; t0 += SCAN_TILE) {
+    const int n = (int)min((int64_t)SCAN_TILE, ncell - t0);
+    int32_t v[SCAN_PER];
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+      const int c = q * SCAN_T + t;
+      v[q] = c < n ? cf[t0 + c] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) s_c[q * SCAN_T + t] = v[q];
     __syncthreads();
-    part[threadIdx.x] += v;
+    int32_t mine[SCAN_PER], sum = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+      mine[q] = s_c[t * SCAN_PER + q];
+      sum += mine[q];
+    }
+    // inclusive scan of the thread sums within the wave
+    int32_t inc = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_w[w] = inc;
     __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int a = 0; a < SCAN_T / 64; ++a) {
+      const int32_t x = s_w[a];
+      before += a < w ? x : 0;
+      total += x;
+    }
+    int32_t r = run + before + inc - sum;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+      const int64_t c = t0 + (int64_t)t * SCAN_PER + q;
+      if (c < t0 + n) {
+        cs[c] = r;
+        cf[c] = r;  // becomes the scatter cursor
+      }
+      r += mine[q];
+    }
+    run += total;
+    __syncthreads();  // s_c and s_w are reused by the next tile
   }
-  int32_t run = (int32_t)E.p_base + (threadIdx.x > 0 ? part[threadIdx.x - 1] : 0);
-  for (int64_t c = c0; c < c1; ++c) {
-    const int32_t cnt = cf[c];
-    cs[c] = run;
-    cf[c] = run;  // becomes the scatter cursor
-    run += cnt;
-  }
-  if (threadIdx.x == T - 1) cs[ncell] = (int32_t)(E.p_base + E.n);
+  if (threadIdx.x == 0) cs[ncell] = (int32_t)(E.p_base + E.n);
 }
 
 __global__ void __launch_bounds__(256) k_scatter(BatchDev b, int64_t nslots) {
@@ -347,11 +390,14 @@ hipError_t launch_bin_only(const BatchDev& b, int e, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, uint32_t rowmask,
-                      hipStream_t s, const hipEvent_t* marks) {
+hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, int64_t max_event_n,
+                      uint32_t rowmask, hipStream_t s, const hipEvent_t* marks) {
   if (nslots <= 0 || nevents <= 0) return hipSuccess;
   if (marks) (void)hipEventRecord(marks[0], s);
-  hipLaunchKernelGGL(k_bbox, dim3(blocks_of(nslots, 256 * BBOX_PER_THREAD)), dim3(256), 0, s, b, prm.dim, nslots);
+  // about 16 blocks per event (at most 64 batches of slots per thread)
+  const int64_t mx = std::max<int64_t>(1, std::min(max_event_n, nslots));
+  const int per = (int)std::min<int64_t>(std::max<int64_t>((mx + 256 * 16 - 1) / (256 * 16), BBOX_BATCH), 64);
+  hipLaunchKernelGGL(k_bbox, dim3(blocks_of(mx, 256 * per), nevents), dim3(256), 0, s, b, prm.dim, per);
   hipLaunchKernelGGL(k_grid, dim3(blocks_of(nevents, 64)), dim3(64), 0, s, b, prm, prm.dim);
   hipLaunchKernelGGL(k_count, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, prm.dim, nslots);
   hipLaunchKernelGGL(k_scan, dim3(nevents), dim3(1024), 0, s, b, prm.dim);

@@ -7,8 +7,9 @@
 namespace ccake {
 
 // marks (optional): 2 events recorded before and after the binning kernels
-hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, uint32_t rowmask,
-                      hipStream_t s, const hipEvent_t* marks = nullptr);
+// max_event_n bounds the particles of any event that is binned
+hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t nslots, int64_t max_event_n,
+                      uint32_t rowmask, hipStream_t s, const hipEvent_t* marks = nullptr);
 // which = 0: full Heun step (two stages); which = 1: pass 1 (+ pass 2 in rate mode when fout != null)
 // marks (optional, which = 0): 5 events around pass 1 / pass 2 of both stages
 hipError_t launch_passes(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, int which,

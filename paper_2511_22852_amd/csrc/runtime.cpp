@@ -410,7 +410,7 @@ extern "C" ccake_status ccake_init_particles(ccake_sim* s, double t0, const doub
   HIPCHK(s, hipMemcpy(s->b.Y1, up.data(), up.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(s, hipMemcpy(s->b.rec, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(s, launch_upload(s->b, 0, n, s->b.Y1, NROW, s->stream));
-  HIPCHK(s, launch_bin(s->b, s->prm, 1, n, 0x1FFFFu, s->stream));
+  HIPCHK(s, launch_bin(s->b, s->prm, 1, n, n, 0x1FFFFu, s->stream));
   HIPCHK(s, launch_init(s->b, s->prm, s->eos, dens_kind, s->b.rec, n, s->stream));
   HIPCHK(s, launch_commit(s->b, n, 0x1FFFFu, s->stream));
   st = fetch_event(s);
@@ -459,7 +459,7 @@ static const int PROF_MARKS = 12;  // 2 around the binning, 5 around each stage'
 static ccake_status enqueue_step(ccake_sim* s, const hipEvent_t* marks, bool rebin) {
   BatchDev b = s->b;
   if (rebin) {
-    HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream, marks));
+    HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, s->n, live_rows(s->prm), s->stream, marks));
   } else {
     if (marks) {
       HIPCHK(s, hipEventRecord(marks[0], s->stream));
@@ -654,7 +654,7 @@ static ccake_status evaluate(ccake_sim* s, bool rates) {
   if (!s->initialised) return fail(s, CCAKE_E_STATE, "not initialised");
   double* aux = (double*)(s->base + s->L.aux);
   HIPCHK(s, hipMemsetAsync(aux, 0, sizeof(double) * NAUXROW * s->n, s->stream));
-  HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream));
+  HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, s->n, live_rows(s->prm), s->stream));
   HIPCHK(s, launch_passes(s->b, s->prm, s->eos, s->n, 1, rates ? s->b.Y1 : nullptr, aux, s->stream));
   // the home arrays keep their order while the cells now index the sorted copy
   s->need_bin = true;
@@ -712,7 +712,7 @@ extern "C" ccake_status ccake_debug_pairs(ccake_sim* s, int64_t cap, int32_t* a,
   if (!npairs || cap < 0 || (cap > 0 && (!a || !b))) return fail(s, CCAKE_E_ARG, "ccake_debug_pairs: bad arguments");
   if (!s->initialised) return fail(s, CCAKE_E_STATE, "not initialised");
   int64_t* counter = (int64_t*)(s->base + s->L.scratch);
-  HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, live_rows(s->prm), s->stream));
+  HIPCHK(s, launch_bin(s->b, s->prm, 1, s->n, s->n, live_rows(s->prm), s->stream));
   s->need_bin = true;
   HIPCHK(s, hipMemsetAsync(counter, 0, sizeof(int64_t), s->stream));
   HIPCHK(s, launch_pairs(s->b, s->prm, 0, s->n, counter, cap, a, b, s->stream));

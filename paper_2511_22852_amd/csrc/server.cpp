@@ -186,7 +186,7 @@ static ccake_status admit_and_init(ccake_server* s, std::vector<std::pair<int, P
     // order), k_init restricted to it
     const int64_t nslots = s->palloc.high_water();
     if ((st = srv_hip(s, launch_bin_only(s->b, e, s->stream), "bin only"))) return st;
-    if ((st = srv_hip(s, launch_bin(s->b, s->prm, s->max_events, nslots, 0x1FFFFu, s->stream), "bin"))) return st;
+    if ((st = srv_hip(s, launch_bin(s->b, s->prm, s->max_events, nslots, n, 0x1FFFFu, s->stream), "bin"))) return st;
     if ((st = srv_hip(s, launch_init(s->b, s->prm, s->eos, p.dens_kind, s->b.rec, nslots, s->stream, e), "init")))
       return st;
     if ((st = srv_hip(s, launch_commit(s->b, nslots, 0x1FFFFu, s->stream), "commit"))) return st;
@@ -295,17 +295,18 @@ static void worker_loop(ccake_server* s) {
     for (auto& fp : fresh)
       if (s->slots[fp.first].steps_total <= 0) finish_event(s, fp.first, CCAKE_OK);
     // one batched Heun step over every resident event
-    int64_t resident_particles = 0;
+    int64_t resident_particles = 0, largest = 0;
     bool any = false;
     for (auto& r : s->slots)
       if (r.used) {
         any = true;
         resident_particles += r.n;
+        largest = std::max<int64_t>(largest, r.n);
       }
     if (!any) continue;
     const int64_t nslots = s->palloc.high_water();
     hipError_t he = launch_schedule(s->b, s->cfg.skin, s->prm.hyperbolic && s->prm.dim == 3, s->stream);
-    if (he == hipSuccess) he = launch_bin(s->b, s->prm, s->max_events, nslots, live_rows(s->prm), s->stream);
+    if (he == hipSuccess) he = launch_bin(s->b, s->prm, s->max_events, nslots, largest, live_rows(s->prm), s->stream);
     if (he == hipSuccess) he = launch_passes(s->b, s->prm, s->eos, nslots, 0, nullptr, nullptr, s->stream);
     if (he == hipSuccess) he = launch_advance(s->b, s->stream);
     s->steps += 1;
