@@ -28,7 +28,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6      # vector FP64: 256 CU x 128 flop/clk x 2.4 GHz
-FP32_PEAK_TFLOPS = 157.3     # vector FP32, published (packed) figure
+FP32_PEAK_TFLOPS = 157.3     # vector FP32, published figure: needs packed (two-wide) FP32 instructions
+# The build disables packed FP32, so the vector ALU peak of these kernels is
+# one wave64 instruction per clock per CU (4 SIMDs x 16 lanes), i.e. 2 flop x
+# 64 lanes x 256 CU x 2.4 GHz for FP32 FMA, the same as FP64.
+VALU_PEAK_TFLOPS = 78.6
+VALU_ISSUE_PER_S = 256 * 2.4e9   # wave64 vector instructions per second, whole chip
 
 METRIC = "SPH particle-steps/s (FP64 vs FP32-Kahan) + p50/p99 event latency, 1 GPU"
 
@@ -53,11 +58,9 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(group):
-    """HBM bytes per launch of the group's kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each divided by what the
-    counter reads per byte of a plain device copy), or None when there is none
-    or the kernel sources changed since."""
+def counter_summary(group):
+    """The committed counter summary of the group's kernel (key: value), or
+    None when there is none or the kernel sources changed since."""
     name = TRAFFIC_FILES.get(group)
     path = os.path.join(ROOT, "profiles", name) if name else None
     if not path or not os.path.exists(path):
@@ -70,16 +73,29 @@ def measured_traffic(group):
                 kv[k.strip()] = v.strip()
     if kv.get("source_digest") != kernel_source_digest():
         return None
+    return kv
+
+
+def measured_traffic(group):
+    """HBM bytes per launch of the group's kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each divided by what the
+    counter reads per byte of a plain device copy), or None."""
+    kv = counter_summary(group)
+    if kv is None:
+        return None
     fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 / float(kv["copy_fetch_factor"])
     write = float(kv["write_kib_per_dispatch"]) * 1024 / float(kv["copy_write_factor"])
     return fetch + write
 
 
-def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, out_dir, command):
+def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, out_dir, command,
+                       sq_dir=None):
     """Write one traffic file per kernel group from rocprofv3 --pmc output:
     mean FETCH_SIZE and WRITE_SIZE (KiB) per dispatch of the group's kernel,
     and the factors that the same counters read per KiB actually moved by a
-    plain copy of copy_mib MiB (read copy_mib, write copy_mib)."""
+    plain copy of copy_mib MiB (read copy_mib, write copy_mib).  With sq_dir
+    (a run with SQ_INSTS_VALU and SQ_WAVES), also the vector-ALU instructions
+    (per wave, summed over waves) per dispatch."""
     import csv
     import glob
 
@@ -98,6 +114,7 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
         raise SystemExit("copy calibration dispatch not found")
     f_factor, w_factor = cf[0][0] / kib, cw[0][0] / kib
     fetch, write = means(fetch_dir, "FETCH_SIZE"), means(write_dir, "WRITE_SIZE")
+    valu = means(sq_dir, "SQ_INSTS_VALU") if sq_dir else {}
     digest = kernel_source_digest()
     for g, prefix in GROUP_KERNELS.items():
         fk = [(k, v) for k, v in fetch.items() if k.startswith(prefix)]
@@ -117,6 +134,9 @@ def summarize_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, cop
             fh.write(f"fetch_kib_per_dispatch: {fm:.1f}\nwrite_kib_per_dispatch: {wm:.1f}\n")
             fh.write(f"copy_fetch_factor: {f_factor:.4f}\ncopy_write_factor: {w_factor:.4f}\n")
             fh.write(f"hbm_bytes_per_dispatch: {fm * 1024 / f_factor + wm * 1024 / w_factor:.0f}\n")
+            vk = [v for k, v in valu.items() if k.startswith(prefix)]
+            if len(vk) == 1:
+                fh.write(f"valu_wave_instructions_per_dispatch: {vk[0][0]:.0f}\n")
             fh.write(f"source_digest: {digest}\n")
         print(path)
 
@@ -138,13 +158,16 @@ def algorithmic_model(dim, viscous, ncharge, mixed, smoothed=True):
     nth = 6 + (5 if viscous else 0)
     ngs = dim + dim * dim + 1
     dens_in = dim + ((1 + ncharge) if smoothed else 0)
+    # compensated (Kahan) additions of the FP32 form: 3 more flops per term
+    kd = 3 * (1 + ((1 + ncharge) if smoothed else 0)) if mixed else 0
+    kg = 3 * (dim + dim * dim + 1) if mixed else 0
     return {
         "density_sums": dict(bytes=8 * dens_in + 4 + 8 * 6,
-                             pair_flops=5 + 1 + 1 + 7 + 1 + (2 * (1 + ncharge) if smoothed else 0)),
+                             pair_flops=5 + 1 + 1 + 7 + 1 + (2 * (1 + ncharge) if smoothed else 0) + kd),
         "eos_inversion": dict(bytes=8 * 5 + 8 * (state - dim) + 8 * 8 * 2 + 8 * nth + recb * rec, pair_flops=0),
         "gradient_sums": dict(bytes=8 * dim + 4 + recb * rec + 8 + 8 * ngs,
                               pair_flops=5 + 1 + 1 + 5 + 1 + dim + 1 + 2 * dim + 4 * dim * dim + 3 * dim
-                              + ((4 * dim * dim + dim) if viscous else 0)),
+                              + ((4 * dim * dim + dim) if viscous else 0) + kg),
         "eom_update": dict(bytes=8 * ngs + 8 * nth + 8 * state * 3, pair_flops=0),
     }
 
@@ -354,9 +377,10 @@ def main():
                     help="only write the headline workload (with --only-3d: the 1.2 M-particle 3+1D "
                          "event), mixed precision, for the native driver paper_2511_22852_amd/ccake_bench "
                          "and exit")
-    ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "MIB"),
-                    help="only write profiles/*_traffic.txt from rocprofv3 --pmc output directories of the "
-                         "native driver (FETCH_SIZE, WRITE_SIZE) and of its --copy MIB calibration, and exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="FETCH WRITE COPY_FETCH COPY_WRITE MIB [SQ]: only write profiles/*_traffic.txt from "
+                         "rocprofv3 --pmc output directories of the native driver (FETCH_SIZE, WRITE_SIZE), of "
+                         "its --copy MIB calibration and optionally of an SQ_INSTS_VALU run, and exit")
     ap.add_argument("--counter-command", default="",
                     help="with --summarize-counters: the commands that produced the counters (recorded)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -368,8 +392,11 @@ def main():
               "note, not a measured path.", file=sys.stderr)
         sys.exit(2)
     if args.summarize_counters:
-        fd, wd, cfd, cwd, mib = args.summarize_counters
-        summarize_counters(fd, wd, cfd, cwd, int(mib), os.path.join(ROOT, "profiles"), args.counter_command)
+        if len(args.summarize_counters) not in (5, 6):
+            ap.error("--summarize-counters takes FETCH WRITE COPY_FETCH COPY_WRITE MIB [SQ]")
+        fd, wd, cfd, cwd, mib = args.summarize_counters[:5]
+        sq = args.summarize_counters[5] if len(args.summarize_counters) == 6 else None
+        summarize_counters(fd, wd, cfd, cwd, int(mib), os.path.join(ROOT, "profiles"), args.counter_command, sq)
         return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
@@ -410,17 +437,21 @@ def main():
     nbytes = w.n * model[names[k]]["bytes"]
     flops = w.n * head["nnb"] * model[names[k]]["pair_flops"]
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
-    t_alu = flops / (FP32_PEAK_TFLOPS * 1e12)
+    t_alu = flops / (VALU_PEAK_TFLOPS * 1e12)
     if t_hbm >= t_alu:
         roof = dict(bound="hbm", achieved=nbytes / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
     else:
-        roof = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s")
+        roof = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(names[k])
     roof["kernel"] = names[k]
     roof["avg_launch_us"] = avg_s * 1e6
     roof["algorithmic_bytes_per_launch"] = nbytes
     roof["algorithmic_flops_per_launch"] = flops
+    # issued vector-ALU instructions (counters) against the issue rate
+    cs = counter_summary(names[k])
+    if cs and "valu_wave_instructions_per_dispatch" in cs:
+        roof["valu_issue_frac"] = float(cs["valu_wave_instructions_per_dispatch"]) / (avg_s * VALU_ISSUE_PER_S)
 
     out = {
         "metric": METRIC,
