@@ -96,6 +96,22 @@ class EosC(ctypes.Structure):
         ("lo", ctypes.c_double * 4), ("hi", ctypes.c_double * 4),
         ("cols", ctypes.POINTER(ctypes.c_double)),
         ("A0", ctypes.c_double), ("muq0", ctypes.c_double * 3), ("cq", ctypes.c_double * 3),
+        ("inv", ctypes.c_void_p),
+    ]
+
+
+NINV = 9
+(I_T, I_MUB, I_MUS, I_MUQ, I_P, I_E, I_CS2, I_KAP, I_TAB) = range(NINV)
+
+
+class InvC(ctypes.Structure):
+    """Offline inverted table: s nodes 10^d (1 + 9 m / P) inside decades
+    d0 <= d < d1 plus 10^d1; x_q = n_q / s on uniform grids (ncharge 3)."""
+    _fields_ = [
+        ("ncharge", ctypes.c_int32), ("d0", ctypes.c_int32), ("d1", ctypes.c_int32),
+        ("per_decade", ctypes.c_int32), ("nx", ctypes.c_int32 * 3), ("pad", ctypes.c_int32),
+        ("xlo", ctypes.c_double * 3), ("xhi", ctypes.c_double * 3),
+        ("val", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -134,7 +150,13 @@ def lib():
         L.orc_totals.restype = None
         L.orc_totals.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(EosC), ctypes.c_double,
                                  ctypes.c_int64, dp, dp]
-        assert L.orc_nvar() == NVAR and L.orc_naux() == NAUX
+        L.orc_inv_ns.restype = ctypes.c_int64
+        L.orc_inv_ns.argtypes = [ctypes.POINTER(InvC)]
+        L.orc_inv_build.restype = ctypes.c_int
+        L.orc_inv_build.argtypes = [ctypes.POINTER(EosC), ctypes.POINTER(InvC)]
+        L.orc_inv_eval.restype = None
+        L.orc_inv_eval.argtypes = [ctypes.POINTER(EosC), ctypes.c_int, ctypes.c_int64, dp, dp, ip]
+        assert L.orc_nvar() == NVAR and L.orc_naux() == NAUX and L.orc_ninv() == NINV
         _lib = L
     return _lib
 
@@ -215,6 +237,42 @@ def eos_table(cols: np.ndarray, lo_fm, hi_fm, tol=1e-13, max_iter=60) -> Eos:
         e.hi[k] = hi_fm[k]
     e.cols = _dp(cols)
     return Eos(e, cols)
+
+
+def eos_inverted(forward: Eos, ncharge: int, d0: int, d1: int, per_decade: int, nx=(2, 2, 2),
+                 xlo=(0.0, 0.0, 0.0), xhi=(0.0, 0.0, 0.0)) -> Eos:
+    """The forward EoS with an offline inverted table ("EoS inverter",
+    offline option) built by the online inverter at every node; stages then
+    interpolate it, and invert online only off its grid."""
+    v = InvC()
+    v.ncharge, v.d0, v.d1, v.per_decade = ncharge, d0, d1, per_decade
+    for q in range(3):
+        v.nx[q] = int(nx[q]) if ncharge else 1
+        v.xlo[q], v.xhi[q] = float(xlo[q]), float(xhi[q])
+    ns = lib().orc_inv_ns(ctypes.byref(v))
+    shape = (ns, v.nx[0], v.nx[1], v.nx[2], NINV)
+    val = np.empty(shape)
+    v.val = _dp(val)
+    bad = lib().orc_inv_build(ctypes.byref(forward.c), ctypes.byref(v))
+    if bad:
+        raise RuntimeError(f"offline table: {bad} node inversions did not converge")
+    e = EosC.from_buffer_copy(forward.c)
+    e.inv = ctypes.cast(ctypes.pointer(v), ctypes.c_void_p)
+    out = Eos(e, (forward.keep, val, v))
+    out.table = val
+    out.grid = v
+    return out
+
+
+def inv_eval(eos: Eos, x4: np.ndarray, fallback: bool = False):
+    """Offline lookups at points (s, nB, nS, nQ): rows T, muB, muS, muQ, p, e,
+    cs2, kappa, in_table, and whether each point was on the grid."""
+    x4 = _f64(x4)
+    n = x4.shape[1]
+    out = np.empty((NINV, n))
+    inside = np.empty(n, np.int32)
+    lib().orc_inv_eval(ctypes.byref(eos.c), int(fallback), n, _dp(x4), _dp(out), _ip(inside))
+    return out, inside.astype(bool)
 
 
 def kernel_w(dim, h, r):

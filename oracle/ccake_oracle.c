@@ -26,6 +26,8 @@
  *   minimal Israel-Stewart ............. eq. min_bul_rel, eq. min_she_rel
  *   first-order DNMR-type couplings .... eq. dnmr (coefficients supplied by caller)
  *   online EoS inverter + backup ....... "EoS inverter", backup-EoS chain
+ *   offline inverted table ............. "EoS inverter" (offline option; grid
+ *                                        evenly spaced inside log decades of s)
  *   modified conformal EoS ............. Appendix "Modified EoS to permit lower eps_min"
  *
  * Readings where the paper is silent or garbled are restated at the point
@@ -106,6 +108,7 @@ typedef struct {
   double lo[4], hi[4];   /* table axes (T, muB, muS, muQ), fm^-1 */
   const double *cols;    /* [7][nT][nB][nS][nQ] dimensionless columns */
   double A0, muq0[3], cq[3]; /* modified conformal parameters (T0 = 1 fm^-1) */
+  const struct orc_inv *inv; /* offline inverted table, or NULL (online inversion) */
 } orc_eos;
 
 /* table columns: p/T^4, s/T^3, nB/T^3, nS/T^3, nQ/T^3, c_s^2, (dp/de)_n */
@@ -652,6 +655,197 @@ int orc_eos_invert(const orc_eos *e, int mode, int ncharge, int64_t n, const dou
   return bad;
 }
 
+/* ========================================================================
+ * Offline inverter ("EoS inverter", offline option): the thermodynamics are
+ * converted once, by the online inverter, onto a fixed grid in the
+ * hydrodynamic variables, and a stage only interpolates.  The paper fixes
+ * the idea and the s grid (evenly spaced inside logarithmic decades, e.g.
+ * s = 0.01, 0.02, ..., 0.1, 0.2, ..., 1, 2, ..., 10); the rest is read as
+ * follows:
+ *  - s nodes: 10^d (1 + 9 m / P), m = 0..P-1, for decades d0 <= d < d1, then
+ *    10^d1 (so the spacing is uniform inside a decade and continuous at its
+ *    upper end);
+ *  - charge coordinates: the ratios x_q = n_q / s (which can have either
+ *    sign) on uniform grids [x_lo, x_hi] with nx nodes each;
+ *  - each node stores T, mu_B, mu_S, mu_Q, p, e, c_s^2, kappa and whether the
+ *    online inverter answered from the table (1) or the backup (0);
+ *  - between nodes every stored quantity is multilinear in (s, x_B, x_S,
+ *    x_Q), i.e. linear in s inside the decade segment; the point counts as a
+ *    table point when every corner node with a nonzero weight does;
+ *  - a point outside the grid is inverted online.
+ * ======================================================================== */
+enum { I_T, I_MUB, I_MUS, I_MUQ, I_P, I_E, I_CS2, I_KAP, I_TAB, NINV };
+
+typedef struct orc_inv {
+  int32_t ncharge;      /* 0: table in s alone (mu = 0); 3: (s, x_B, x_S, x_Q) */
+  int32_t d0, d1;       /* s from 10^d0 to 10^d1 fm^-3 */
+  int32_t per_decade;   /* P: nodes per decade */
+  int32_t nx[3];        /* nodes of x_q (ncharge 3; >= 2 each) */
+  int32_t pad;
+  double xlo[3], xhi[3];
+  double *val;          /* [ns][nx_B][nx_S][nx_Q][NINV] */
+} orc_inv;
+
+/* 10^d by repeated multiplication (d small) */
+static double pow10i(int d)
+{
+  double p = 1.0;
+  for (int k = 0; k < (d < 0 ? -d : d); ++k) p *= 10.0;
+  return d >= 0 ? p : 1.0 / p;
+}
+
+int64_t orc_inv_ns(const orc_inv *v) { return (int64_t)(v->d1 - v->d0) * v->per_decade + 1; }
+
+static double inv_s_node(const orc_inv *v, int64_t g)
+{
+  if (g >= (int64_t)(v->d1 - v->d0) * v->per_decade) return pow10i(v->d1);
+  int d = v->d0 + (int)(g / v->per_decade), m = (int)(g % v->per_decade);
+  return pow10i(d) * (1.0 + 9.0 * m / v->per_decade);
+}
+
+static double inv_x_node(const orc_inv *v, int q, int k)
+{
+  return v->xlo[q] + (v->xhi[q] - v->xlo[q]) * k / (v->nx[q] - 1);
+}
+
+static int64_t inv_charge_nodes(const orc_inv *v)
+{
+  return v->ncharge ? (int64_t)v->nx[0] * v->nx[1] * v->nx[2] : 1;
+}
+
+/* Fills v->val by inverting every node online with the forward EoS e. */
+int orc_inv_build(const orc_eos *e, orc_inv *v)
+{
+  const int64_t ns = orc_inv_ns(v), nc = inv_charge_nodes(v);
+  int bad = 0;
+#pragma omp parallel for reduction(+:bad) schedule(static)
+  for (int64_t i = 0; i < ns * nc; ++i) {
+    const int64_t g = i / nc;
+    int64_t r = i % nc;
+    double in[4] = {inv_s_node(v, g), 0.0, 0.0, 0.0};
+    if (v->ncharge) {
+      int k[3];
+      k[2] = (int)(r % v->nx[2]);
+      r /= v->nx[2];
+      k[1] = (int)(r % v->nx[1]);
+      k[0] = (int)(r / v->nx[1]);
+      for (int q = 0; q < 3; ++q) in[1 + q] = inv_x_node(v, q, k[q]) * in[0];
+    }
+    thermo th;
+    invert(e, 0, v->ncharge, in, &th);
+    double *o = v->val + i * NINV;
+    o[I_T] = th.T;
+    for (int q = 0; q < 3; ++q) o[I_MUB + q] = th.mu[q];
+    o[I_P] = th.p;
+    o[I_E] = th.e;
+    o[I_CS2] = th.cs2;
+    o[I_KAP] = th.kappa;
+    o[I_TAB] = th.in_table ? 1.0 : 0.0;
+    if (!th.ok) bad++;
+  }
+  return bad;
+}
+
+/* Interpolated thermodynamics at in = (s, nB, nS, nQ); 0 when outside the grid. */
+static int inv_lookup(const orc_inv *v, const double in[4], thermo *th)
+{
+  const double s = in[0];
+  const int64_t ns = orc_inv_ns(v);
+  if (!(s >= inv_s_node(v, 0) && s <= inv_s_node(v, ns - 1))) return 0;
+  /* decade, then the segment inside it */
+  int d = v->d0;
+  while (d + 1 < v->d1 && s >= pow10i(d + 1)) ++d;
+  int m = (int)floor((s / pow10i(d) - 1.0) * v->per_decade / 9.0);
+  if (m < 0) m = 0;
+  if (m > v->per_decade - 1) m = v->per_decade - 1;
+  const int64_t g = (int64_t)(d - v->d0) * v->per_decade + m;
+  const double s0 = inv_s_node(v, g), s1 = inv_s_node(v, g + 1);
+  double f[4] = {(s - s0) / (s1 - s0), 0.0, 0.0, 0.0};
+  int64_t k[4] = {g, 0, 0, 0};
+  if (v->ncharge) {
+    for (int q = 0; q < 3; ++q) {
+      const double x = in[1 + q] / s;
+      const double u = (x - v->xlo[q]) / (v->xhi[q] - v->xlo[q]) * (v->nx[q] - 1);
+      if (!(u >= 0.0 && u <= v->nx[q] - 1)) return 0;
+      int64_t kk = (int64_t)floor(u);
+      if (kk > v->nx[q] - 2) kk = v->nx[q] - 2;
+      k[1 + q] = kk;
+      f[1 + q] = u - kk;
+    }
+  }
+  const int nd = v->ncharge ? 4 : 1;
+  double acc[NINV] = {0.0};
+  int all_table = 1;
+  for (int c = 0; c < (1 << nd); ++c) {
+    double wgt = 1.0;
+    int64_t idx = 0;
+    for (int a = 0; a < nd; ++a) {
+      const int bit = (c >> (nd - 1 - a)) & 1;
+      wgt *= bit ? f[a] : 1.0 - f[a];
+      const int64_t dim_n = a == 0 ? ns : v->nx[a - 1];
+      idx = idx * dim_n + k[a] + bit;
+    }
+    const double *o = v->val + idx * NINV;
+    for (int q = 0; q < NINV; ++q) acc[q] += wgt * o[q];
+    if (wgt > 0.0 && !(o[I_TAB] > 0.5)) all_table = 0;
+  }
+  th->T = acc[I_T];
+  for (int q = 0; q < 3; ++q) {
+    th->mu[q] = v->ncharge ? acc[I_MUB + q] : 0.0;
+    th->n[q] = v->ncharge ? in[1 + q] : 0.0;
+  }
+  th->p = acc[I_P];
+  th->e = acc[I_E];
+  th->s = s;
+  th->cs2 = acc[I_CS2];
+  th->kappa = acc[I_KAP];
+  th->in_table = all_table;
+  th->iters = 0;
+  th->ok = 1;
+  return 1;
+}
+
+/* (s, n) -> thermodynamics for a stage: the offline table when the EoS
+ * carries one and the point lies on its grid, the online inverter otherwise */
+static void thermo_of_sn(const orc_eos *e, int ncharge, const double in[4], thermo *th)
+{
+  if (e->inv && inv_lookup(e->inv, in, th)) return;
+  invert(e, 0, ncharge, in, th);
+}
+
+/* Offline lookups of n points in = [4][n] (s, nB, nS, nQ): out = [NINV][n]
+ * (T, muB, muS, muQ, p, e, cs2, kappa, in_table); inside[i] = 1 when the
+ * point was on the grid.  Points off the grid are inverted online when
+ * fallback is set, else left as NaN. */
+void orc_inv_eval(const orc_eos *e, int fallback, int64_t n, const double *in, double *out, int32_t *inside)
+{
+  const int ncharge = e->inv ? e->inv->ncharge : 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double v[4] = {in[i], in[n + i], in[2 * n + i], in[3 * n + i]};
+    thermo th;
+    int on = e->inv && inv_lookup(e->inv, v, &th);
+    inside[i] = on;
+    if (!on) {
+      if (fallback) {
+        invert(e, 0, ncharge, v, &th);
+      } else {
+        for (int q = 0; q < NINV; ++q) out[q * n + i] = NAN;
+        continue;
+      }
+    }
+    out[I_T * n + i] = th.T;
+    for (int q = 0; q < 3; ++q) out[(I_MUB + q) * n + i] = th.mu[q];
+    out[I_P * n + i] = th.p;
+    out[I_E * n + i] = th.e;
+    out[I_CS2 * n + i] = th.cs2;
+    out[I_KAP * n + i] = th.kappa;
+    out[I_TAB * n + i] = th.in_table;
+  }
+}
+
+int orc_ninv(void) { return NINV; }
+
 /* thermodynamic columns at given (T, mu): p, e, s, nB, nS, nQ, cs2, kappa */
 void orc_eos_eval(const orc_eos *e, int use_table, int64_t n, const double *x, double *out)
 {
@@ -930,7 +1124,7 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
         for (int k = 0; k < 3; ++k) q->n[k] = k < prm->ncharge ? y[(V_NB + k) * n + a] * sigma : 0.0;
       }
       double in[4] = {q->s, q->n[0], q->n[1], q->n[2]};
-      invert(eos, 0, prm->ncharge, in, &q->th);
+      thermo_of_sn(eos, prm->ncharge, in, &q->th);
       if (!q->th.ok) bad++;
       double w = q->th.e + q->th.p;
       q->eta = prm->eta_over_s * q->s;
