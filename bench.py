@@ -369,6 +369,7 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=200, help="Heun steps per served event")
     ap.add_argument("--steps-3d", type=int, default=10,
                     help="timed steps of each 3+1D configuration (0 = skip them)")
+    ap.add_argument("--no-offline", action="store_true", help="skip the offline-inverter run of the event")
     ap.add_argument("--only-3d", action="store_true",
                     help="only time the 1.2 M-particle 3+1D event in mixed precision (profiling runs)")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both",
@@ -479,6 +480,28 @@ def main():
         "eos_mean_newton_iterations_last_step": head["newton_iters"] / (2 * w.n),
         "roofline": roof,
     }
+    if not args.no_offline:
+        # the offline inverter (the paper's GPU path) on the same event: the
+        # (s, n) inversions of the stages interpolate a table on a grid in s
+        # (evenly spaced inside decades) and n_q / s
+        grid = dict(decade_lo=-2, decade_hi=3, per_decade=36, nx=(11, 7, 9), x_lo=(0.0, -0.03, -0.02),
+                    x_hi=(0.1, 0.03, 0.06))
+        eos_off = B.Eos.table(cols, lo, hi)
+        t0 = time.perf_counter()
+        eos_off.build_inverted(3, **grid)
+        build_s = time.perf_counter() - t0
+        r = run_gpu(B, I, w, eos_off, B.MIXED, args.steps, args.warmup)
+        out["offline_eos_mixed"] = {
+            "value": w.n * args.steps / r["elapsed"], "ms_per_step": r["elapsed"] / args.steps * 1e3,
+            "eos_inversion_ms_per_step": r["ms"][2] / args.steps,
+            "online_eos_inversion_ms_per_step": head["ms"][2] / args.steps,
+            "table": f"s: 10^-2..10^3 fm^-3, {grid['per_decade']} per decade; n/s (B, S, Q): {grid['nx']} nodes",
+            "build_seconds": build_s,
+            "eos_mean_newton_iterations_last_step": r["newton_iters"] / (2 * w.n),
+        }
+        print(f"[bench] offline EoS: {out['offline_eos_mixed']['ms_per_step']:.4f} ms/step", file=sys.stderr,
+              flush=True)
+        eos_off.close()
     if args.steps_3d > 0:
         w2 = I.lumpy_3d_workload()
         other = {}

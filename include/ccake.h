@@ -151,6 +151,43 @@ ccake_status ccake_eos_destroy(ccake_eos* eos);
 ccake_status ccake_eos_invert(ccake_eos* eos, int32_t mode, int32_t ncharge, int64_t n, const double* in,
                               double* out, int32_t* in_table, void* stream);
 
+/* Offline inverter ("EoS inverter", offline option): the thermodynamics are
+ * converted once onto a fixed grid in the hydrodynamic variables, and the
+ * stages then interpolate instead of root-finding.  The s nodes are evenly
+ * spaced inside logarithmic decades, 10^d (1 + 9 m / per_decade) for
+ * decade_lo <= d < decade_hi and m = 0 .. per_decade - 1, then
+ * 10^decade_hi (fm^-3); with ncharge = 3 the ratios x_q = n_q / s (B, S, Q)
+ * take nx[q] >= 2 uniform values in [x_lo[q], x_hi[q]].  At most 2^28 nodes. */
+typedef struct ccake_inv_grid {
+  int32_t ncharge;              /* 0 (s only, mu = 0) or 3 */
+  int32_t decade_lo, decade_hi;
+  int32_t per_decade;
+  int32_t nx[3];
+  int32_t pad;
+  double x_lo[3], x_hi[3];
+} ccake_inv_grid;
+
+/* Builds the offline table of eos on the device: every node is inverted
+ * once by the online inverter (cold start) and T, mu_B, mu_S, mu_Q, p, e,
+ * c_s^2, (dp/de)_n and the table/backup origin are stored (replacing any
+ * previous table; the device memory belongs to eos).  Simulations and servers
+ * created afterwards with eos interpolate it multilinearly in (s, x_B, x_S,
+ * x_Q) for the (s, n) inversions of their stages, invert online off the grid,
+ * and must have the table's ncharge.  A point is reported in the table when
+ * every corner node with a weight above 1e-9 is.  ccake_eos_invert stays online.
+ * Synchronises the stream.  Errors: CCAKE_E_ARG for a bad grid,
+ * CCAKE_E_CAPACITY above 2^28 nodes, CCAKE_E_EOS_NOCONV when a node does not
+ * converge (no table is attached then).                                      */
+ccake_status ccake_eos_build_inverted(ccake_eos* eos, const ccake_inv_grid* grid, void* stream);
+
+/* Lookups in the offline table at n points in = [4][n] (s, nB, nS, nQ),
+ * device pointers: out [9][n] = T, muB, muS, muQ, p, e, c_s^2, (dp/de)_n,
+ * in_table (0/1); inside[n] = 1 for points on the grid.  Points off the grid
+ * are inverted online when fallback != 0, else set to NaN.  Synchronises.
+ * CCAKE_E_STATE when eos has no offline table.                              */
+ccake_status ccake_eos_offline_eval(ccake_eos* eos, int32_t fallback, int64_t n, const double* in, double* out,
+                                    int32_t* inside, void* stream);
+
 /* --------------------------------------------------------- simulation ---- */
 
 /* Device bytes a simulation of n particles needs; the caller allocates them

@@ -671,7 +671,9 @@ int orc_eos_invert(const orc_eos *e, int mode, int ncharge, int64_t n, const dou
  *    online inverter answered from the table (1) or the backup (0);
  *  - between nodes every stored quantity is multilinear in (s, x_B, x_S,
  *    x_Q), i.e. linear in s inside the decade segment; the point counts as a
- *    table point when every corner node with a nonzero weight does;
+ *    table point when every corner node with a weight above 1e-9 does (a
+ *    point on a node face is decided by the nodes of that face, whatever
+ *    the last bits of its coordinates);
  *  - a point outside the grid is inverted online.
  * ======================================================================== */
 enum { I_T, I_MUB, I_MUS, I_MUQ, I_P, I_E, I_CS2, I_KAP, I_TAB, NINV };
@@ -787,7 +789,7 @@ static int inv_lookup(const orc_inv *v, const double in[4], thermo *th)
     }
     const double *o = v->val + idx * NINV;
     for (int q = 0; q < NINV; ++q) acc[q] += wgt * o[q];
-    if (wgt > 0.0 && !(o[I_TAB] > 0.5)) all_table = 0;
+    if (wgt > 1e-9 && !(o[I_TAB] > 0.5)) all_table = 0;
   }
   th->T = acc[I_T];
   for (int q = 0; q < 3; ++q) {

@@ -32,7 +32,8 @@ NAUX = 21
 
 EXPORTS = [
     "ccake_eos_create_conformal", "ccake_eos_create_gas", "ccake_eos_create_table",
-    "ccake_eos_destroy", "ccake_eos_invert", "ccake_workspace_bytes", "ccake_create",
+    "ccake_eos_destroy", "ccake_eos_invert", "ccake_eos_build_inverted", "ccake_eos_offline_eval",
+    "ccake_workspace_bytes", "ccake_create",
     "ccake_init_particles", "ccake_set_state", "ccake_get_state", "ccake_time", "ccake_step",
     "ccake_check", "ccake_set_sources", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
     "ccake_destroy", "ccake_server_create", "ccake_server_submit", "ccake_server_poll",
@@ -57,6 +58,19 @@ class Config(ctypes.Structure):
         ("c_PiPi", ctypes.c_double), ("c_Pipi", ctypes.c_double), ("c_pipi", ctypes.c_double),
         ("c_piPi", ctypes.c_double), ("skin", ctypes.c_double),
     ]
+
+
+class InvGrid(ctypes.Structure):
+    """Grid of the offline inverted EoS table (ccake_inv_grid)."""
+    _fields_ = [
+        ("ncharge", ctypes.c_int32), ("decade_lo", ctypes.c_int32), ("decade_hi", ctypes.c_int32),
+        ("per_decade", ctypes.c_int32), ("nx", ctypes.c_int32 * 3), ("pad", ctypes.c_int32),
+        ("x_lo", ctypes.c_double * 3), ("x_hi", ctypes.c_double * 3),
+    ]
+
+
+# rows of ccake_eos_offline_eval
+OFFLINE_ROWS = ("T", "muB", "muS", "muQ", "p", "e", "cs2", "kappa", "in_table")
 
 
 class Source(ctypes.Structure):
@@ -111,6 +125,8 @@ def lib():
             "ccake_eos_create_table": [ctypes.POINTER(vp), ip, dp, dp, dp, i32, dbl],
             "ccake_eos_destroy": [vp],
             "ccake_eos_invert": [vp, i32, i32, i64, vp, vp, vp, vp],
+            "ccake_eos_build_inverted": [vp, ctypes.POINTER(InvGrid), vp],
+            "ccake_eos_offline_eval": [vp, i32, i64, vp, vp, vp, vp],
             "ccake_workspace_bytes": [ctypes.POINTER(Config), i64, ctypes.POINTER(ctypes.c_size_t)],
             "ccake_create": [ctypes.POINTER(vp), ctypes.POINTER(Config), vp, i64, vp, ctypes.c_size_t, vp],
             "ccake_init_particles": [vp, dbl, vp, vp, i32, vp, i32],
@@ -216,6 +232,34 @@ class Eos:
                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(it.data_ptr()),
                                       ctypes.c_void_p(stream.cuda_stream)), self.h)
         return out.cpu().numpy(), it.cpu().numpy()
+
+    def build_inverted(self, ncharge, decade_lo, decade_hi, per_decade, nx=(2, 2, 2), x_lo=(0.0, 0.0, 0.0),
+                       x_hi=(0.0, 0.0, 0.0), device="cuda:0"):
+        """Attach the offline inverted table (ccake_eos_build_inverted):
+        simulations created afterwards with this EoS interpolate it."""
+        import torch
+        g = InvGrid()
+        g.ncharge, g.decade_lo, g.decade_hi, g.per_decade = ncharge, decade_lo, decade_hi, per_decade
+        for q in range(3):
+            g.nx[q], g.x_lo[q], g.x_hi[q] = int(nx[q]), float(x_lo[q]), float(x_hi[q])
+        stream = torch.cuda.current_stream(device)
+        _check(lib().ccake_eos_build_inverted(self.h, ctypes.byref(g), ctypes.c_void_p(stream.cuda_stream)),
+               self.h)
+        return self
+
+    def offline_eval(self, x4, fallback=False, device="cuda:0"):
+        """Offline lookups at (s, nB, nS, nQ) [4, n]: rows OFFLINE_ROWS [9, n]
+        and whether each point was on the grid."""
+        import torch
+        x = torch.as_tensor(_f64(x4), device=device).contiguous()
+        n = x.shape[1]
+        out = torch.empty((9, n), dtype=torch.float64, device=device)
+        inside = torch.empty(n, dtype=torch.int32, device=device)
+        stream = torch.cuda.current_stream(device)
+        _check(lib().ccake_eos_offline_eval(self.h, int(fallback), n, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(inside.data_ptr()),
+                                            ctypes.c_void_p(stream.cuda_stream)), self.h)
+        return out.cpu().numpy(), inside.cpu().numpy().astype(bool)
 
     def close(self):
         if self.h:

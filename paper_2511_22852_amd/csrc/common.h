@@ -53,6 +53,18 @@ enum EosKind { EOS_CONFORMAL = 0, EOS_TABLE = 1, EOS_GAS = 2 };
 // table node: 8 doubles, the four Newton columns first (32-byte aligned)
 enum TabCol { TC_S, TC_NB, TC_NS, TC_NQ, TC_P, TC_CS2, TC_KAP, TC_PAD, TC_STRIDE };
 
+// Offline inverted table ("EoS inverter", offline option): thermodynamics
+// at nodes s = 10^d (1 + 9 m / P) (decades d0 <= d < d1, then 10^d1) times
+// x_q = n_q / s on uniform grids; val == nullptr: no table.
+enum InvCol { IV_T, IV_MUB, IV_MUS, IV_MUQ, IV_P, IV_E, IV_CS2, IV_KAP, IV_TAB, IV_STRIDE };
+struct InvDev {
+  const double* val;  // [ns][nx_B][nx_S][nx_Q][IV_STRIDE]
+  int32_t ncharge, d0, d1, P;
+  int32_t nx[3], pad;
+  int64_t ns;
+  double xlo[3], xhi[3];
+};
+
 struct EosDev {
   int32_t kind;
   int32_t n[4];
@@ -61,6 +73,7 @@ struct EosDev {
   double fstar;
   double tol;
   const double* tab;  // node-major [nT][nB][nS][nQ][8]
+  InvDev inv;         // offline table of the (s, n) inversions of the stages
 };
 
 // one external source, widths folded into 1/(2 w^2) and the normalisation of

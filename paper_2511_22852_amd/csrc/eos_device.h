@@ -454,4 +454,101 @@ __device__ inline void eos_invert(const EosDev& e, int mode, const double in[4],
 }
 
 
+// ---------------------------------------------------------------------------
+// Offline inverter ("EoS inverter", offline option).  The node values are the
+// online inversions of the node coordinates (built once by k_inv_build); a
+// lookup interpolates every stored quantity multilinearly in (s, x_B, x_S,
+// x_Q), x_q = n_q / s, linear in s inside a decade segment.  The point counts
+// as a table point when every corner node with a weight above 1e-9 came from
+// the table (so a point on a node face is decided by that face alone, whatever
+// the rounding of its coordinates).  Returns false (th untouched) off the grid.
+
+// 10^d by repeated multiplication (small d)
+__device__ __forceinline__ double pow10_int(int d) {
+  double p = 1.0;
+  const int a = d < 0 ? -d : d;
+  for (int k = 0; k < a; ++k) p *= 10.0;
+  return d >= 0 ? p : 1.0 / p;
+}
+
+__host__ __device__ inline double inv_s_node(const InvDev& v, int64_t g) {
+#pragma clang fp contract(off)
+  const int64_t last = (int64_t)(v.d1 - v.d0) * v.P;
+  int d = v.d1, m = 0;
+  if (g < last) {
+    d = v.d0 + (int)(g / v.P);
+    m = (int)(g % v.P);
+  }
+  double p = 1.0;
+  const int a = d < 0 ? -d : d;
+  for (int k = 0; k < a; ++k) p *= 10.0;
+  p = d >= 0 ? p : 1.0 / p;
+  return g < last ? p * (1.0 + 9.0 * m / v.P) : p;
+}
+
+template <int NQ>
+__device__ inline bool inv_lookup(const InvDev& v, const double in[4], Thermo& th) {
+#pragma clang fp contract(off)
+  const double s = in[0];
+  if (!(s >= inv_s_node(v, 0) && s <= inv_s_node(v, v.ns - 1))) return false;
+  int d = v.d0;
+  while (d + 1 < v.d1 && s >= pow10_int(d + 1)) ++d;
+  int m = (int)floor((s / pow10_int(d) - 1.0) * v.P / 9.0);
+  m = m < 0 ? 0 : (m > v.P - 1 ? v.P - 1 : m);
+  const int64_t g = (int64_t)(d - v.d0) * v.P + m;
+  const double s0 = inv_s_node(v, g), s1 = inv_s_node(v, g + 1);
+  constexpr int ND = NQ > 0 ? 4 : 1;
+  double f[4] = {(s - s0) / (s1 - s0), 0.0, 0.0, 0.0};
+  int64_t k[4] = {g, 0, 0, 0};
+  int64_t ext[4] = {v.ns, 1, 1, 1};
+  if (NQ > 0) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double x = in[1 + q] / s;
+      const double u = (x - v.xlo[q]) / (v.xhi[q] - v.xlo[q]) * (v.nx[q] - 1);
+      if (!(u >= 0.0 && u <= v.nx[q] - 1)) return false;
+      int64_t kk = (int64_t)floor(u);
+      kk = kk > v.nx[q] - 2 ? v.nx[q] - 2 : kk;
+      k[1 + q] = kk;
+      f[1 + q] = u - kk;
+      ext[1 + q] = v.nx[q];
+    }
+  }
+  double acc[IV_STRIDE];
+#pragma unroll
+  for (int c = 0; c < IV_STRIDE; ++c) acc[c] = 0.0;
+  bool all_table = true;
+#pragma unroll
+  for (int c = 0; c < (1 << ND); ++c) {
+    double w = 1.0;
+    int64_t idx = 0;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      const int bit = (c >> (ND - 1 - a)) & 1;
+      w *= bit ? f[a] : 1.0 - f[a];
+      idx = idx * ext[a] + k[a] + bit;
+    }
+    const double* o = v.val + idx * IV_STRIDE;
+#pragma unroll
+    for (int q = 0; q < IV_STRIDE; ++q) acc[q] += w * o[q];
+    if (w > 1e-9 && !(o[IV_TAB] > 0.5)) all_table = false;
+  }
+  th.T = acc[IV_T];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    th.mu[q] = NQ > 0 ? acc[IV_MUB + q] : 0.0;
+    th.n[q] = NQ > 0 ? in[1 + q] : 0.0;
+  }
+  th.p = acc[IV_P];
+  th.e = acc[IV_E];
+  th.s = s;
+  th.cs2 = acc[IV_CS2];
+  th.kappa = acc[IV_KAP];
+  th.in_table = all_table ? 1 : 0;
+  th.iters = 0;
+  th.evals = 0;
+  th.ok = 1;
+  return true;
+}
+
 }  // namespace ccake

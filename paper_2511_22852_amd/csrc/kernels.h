@@ -26,6 +26,10 @@ hipError_t launch_pairs(const BatchDev& b, const Params& prm, int e, int64_t n, 
 hipError_t launch_unsort(const BatchDev& b, int e, int64_t n, uint32_t rowmask, double* out, hipStream_t s);
 hipError_t launch_upload(const BatchDev& b, int e, int64_t n, const double* in, int nrows, hipStream_t s);
 hipError_t launch_totals(const BatchDev& b, const Params& prm, int nevents, double* out, hipStream_t s);
+hipError_t launch_inv_build(const EosDev& eos, const InvDev& v, double* val, int64_t nodes, uint32_t* bad,
+                            hipStream_t s);
+hipError_t launch_inv_eval(const EosDev& eos, int fallback, int64_t n, const double* in, double* out,
+                           int32_t* inside, hipStream_t s);
 hipError_t launch_eos_invert(const EosDev& eos, int mode, int nq, int64_t n, const double* in, double* out,
                              int32_t* in_table, uint32_t* bad, hipStream_t s);
 

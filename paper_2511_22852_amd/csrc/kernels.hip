@@ -186,8 +186,94 @@ __global__ void __launch_bounds__(128) k_eos_invert(EosDev eos, int mode, int64_
   if (!th.ok && bad) atomicAdd(bad, 1u);
 }
 
+// Offline table: one thread per node inverts the node's (s, n) online (cold
+// start) with the forward EoS and stores the thermodynamics.
+template <int NQ>
+__global__ void __launch_bounds__(128) k_inv_build(EosDev eos, InvDev v, double* val, int64_t nodes,
+                                                   uint32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nodes) return;
+  const int64_t nc = NQ > 0 ? (int64_t)v.nx[0] * v.nx[1] * v.nx[2] : 1;
+  const int64_t g = i / nc;
+  int64_t r = i % nc;
+  double in[4] = {inv_s_node(v, g), 0.0, 0.0, 0.0};
+  if (NQ > 0) {
+    int k[3];
+    k[2] = (int)(r % v.nx[2]);
+    r /= v.nx[2];
+    k[1] = (int)(r % v.nx[1]);
+    k[0] = (int)(r / v.nx[1]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double x = v.xlo[q] + (v.xhi[q] - v.xlo[q]) * k[q] / (v.nx[q] - 1);
+      in[1 + q] = x * in[0];
+    }
+  }
+  eos.inv.val = nullptr;  // the forward EoS inverts the nodes
+  Thermo th;
+  eos_invert<NQ>(eos, 0, in, nullptr, th);
+  double* o = val + i * IV_STRIDE;
+  o[IV_T] = th.T;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) o[IV_MUB + q] = th.mu[q];
+  o[IV_P] = th.p;
+  o[IV_E] = th.e;
+  o[IV_CS2] = th.cs2;
+  o[IV_KAP] = th.kappa;
+  o[IV_TAB] = th.in_table ? 1.0 : 0.0;
+  if (!th.ok) atomicAdd(bad, 1u);
+}
+
+// Offline lookups of n points (s, nB, nS, nQ) = in [4][n]: out [9][n] = T,
+// muB, muS, muQ, p, e, cs2, kappa, in_table; inside[i] = 1 on the grid.  Off
+// the grid: online inversion when fallback is set, else NaN.
+template <int NQ>
+__global__ void __launch_bounds__(128) k_inv_eval(EosDev eos, int fallback, int64_t n, const double* in,
+                                                  double* out, int32_t* inside) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v[4] = {in[i], in[n + i], in[2 * n + i], in[3 * n + i]};
+  Thermo th;
+  const bool on = eos.inv.val && inv_lookup<NQ>(eos.inv, v, th);
+  inside[i] = on ? 1 : 0;
+  if (!on) {
+    if (!fallback) {
+      for (int q = 0; q < IV_STRIDE; ++q) out[q * n + i] = NAN;
+      return;
+    }
+    eos_invert<NQ>(eos, 0, v, nullptr, th);
+  }
+  out[IV_T * n + i] = th.T;
+  for (int q = 0; q < 3; ++q) out[(IV_MUB + q) * n + i] = th.mu[q];
+  out[IV_P * n + i] = th.p;
+  out[IV_E * n + i] = th.e;
+  out[IV_CS2 * n + i] = th.cs2;
+  out[IV_KAP * n + i] = th.kappa;
+  out[IV_TAB * n + i] = th.in_table;
+}
+
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_inv_build(const EosDev& eos, const InvDev& v, double* val, int64_t nodes, uint32_t* bad,
+                            hipStream_t s) {
+  if (nodes <= 0) return hipSuccess;
+  if (v.ncharge)
+    hipLaunchKernelGGL(k_inv_build<3>, dim3(blocks_for(nodes, 128)), dim3(128), 0, s, eos, v, val, nodes, bad);
+  else
+    hipLaunchKernelGGL(k_inv_build<0>, dim3(blocks_for(nodes, 128)), dim3(128), 0, s, eos, v, val, nodes, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_eval(const EosDev& eos, int fallback, int64_t n, const double* in, double* out,
+                           int32_t* inside, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (eos.inv.ncharge)
+    hipLaunchKernelGGL(k_inv_eval<3>, dim3(blocks_for(n, 128)), dim3(128), 0, s, eos, fallback, n, in, out, inside);
+  else
+    hipLaunchKernelGGL(k_inv_eval<0>, dim3(blocks_for(n, 128)), dim3(128), 0, s, eos, fallback, n, in, out, inside);
+  return hipGetLastError();
+}
 
 hipError_t launch_advance(const BatchDev& b, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(blocks_for(b.max_events, 64)), dim3(64), 0, s, b);

@@ -248,9 +248,70 @@ extern "C" ccake_status ccake_eos_create_table(ccake_eos** out, const int32_t n[
   return CCAKE_OK;
 }
 
+extern "C" ccake_status ccake_eos_build_inverted(ccake_eos* eos, const ccake_inv_grid* g, void* stream) {
+  if (!eos || !g) return CCAKE_E_ARG;
+  if ((g->ncharge != 0 && g->ncharge != 3) || g->decade_lo >= g->decade_hi || g->decade_lo < -30 ||
+      g->decade_hi > 30 || g->per_decade < 1 || g->per_decade > 100000)
+    return fail(eos, CCAKE_E_ARG, "ccake_eos_build_inverted: bad s grid");
+  InvDev v;
+  memset(&v, 0, sizeof v);
+  v.ncharge = g->ncharge;
+  v.d0 = g->decade_lo;
+  v.d1 = g->decade_hi;
+  v.P = g->per_decade;
+  v.ns = (int64_t)(v.d1 - v.d0) * v.P + 1;
+  int64_t nodes = v.ns;
+  for (int q = 0; q < 3; ++q) {
+    if (g->ncharge) {
+      if (g->nx[q] < 2 || g->nx[q] > 100000 || !std::isfinite(g->x_lo[q]) || !std::isfinite(g->x_hi[q]) ||
+          !(g->x_hi[q] > g->x_lo[q]))
+        return fail(eos, CCAKE_E_ARG, "ccake_eos_build_inverted: bad n/s grid of charge %d", q);
+      v.nx[q] = g->nx[q];
+      v.xlo[q] = g->x_lo[q];
+      v.xhi[q] = g->x_hi[q];
+      nodes *= g->nx[q];
+    } else {
+      v.nx[q] = 1;
+    }
+  }
+  if (nodes > ((int64_t)1 << 28)) return fail(eos, CCAKE_E_CAPACITY, "ccake_eos_build_inverted: %lld nodes", (long long)nodes);
+  hipStream_t s = (hipStream_t)stream;
+  double* val = nullptr;
+  if (hipMalloc((void**)&val, (size_t)nodes * IV_STRIDE * sizeof(double)) != hipSuccess)
+    return fail(eos, CCAKE_E_NOMEM, "ccake_eos_build_inverted: %lld nodes", (long long)nodes);
+  EosDev fwd = eos->dev;
+  fwd.inv.val = nullptr;
+  hipError_t he = hipMemsetAsync(eos->d_bad, 0, sizeof(uint32_t), s);
+  if (he == hipSuccess) he = launch_inv_build(fwd, v, val, nodes, eos->d_bad, s);
+  uint32_t bad = 0;
+  if (he == hipSuccess) he = hipMemcpyAsync(&bad, eos->d_bad, sizeof bad, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess || bad) {
+    (void)hipFree(val);
+    if (he != hipSuccess) return fail(eos, CCAKE_E_HIP, "ccake_eos_build_inverted: %s", hipGetErrorString(he));
+    return fail(eos, CCAKE_E_EOS_NOCONV, "ccake_eos_build_inverted: %u node inversions did not converge", bad);
+  }
+  if (eos->d_inv) (void)hipFree(eos->d_inv);
+  eos->d_inv = val;
+  v.val = val;
+  eos->dev.inv = v;
+  return CCAKE_OK;
+}
+
+extern "C" ccake_status ccake_eos_offline_eval(ccake_eos* eos, int32_t fallback, int64_t n, const double* in,
+                                               double* out, int32_t* inside, void* stream) {
+  if (!eos || n < 0 || (n > 0 && (!in || !out || !inside))) return CCAKE_E_ARG;
+  if (!eos->dev.inv.val) return fail(eos, CCAKE_E_STATE, "ccake_eos_offline_eval: no inverted table");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(eos, launch_inv_eval(eos->dev, fallback ? 1 : 0, n, in, out, inside, s));
+  HIPCHK(eos, hipStreamSynchronize(s));
+  return CCAKE_OK;
+}
+
 extern "C" ccake_status ccake_eos_destroy(ccake_eos* eos) {
   if (!eos) return CCAKE_OK;
   if (eos->d_tab) (void)hipFree(eos->d_tab);
+  if (eos->d_inv) (void)hipFree(eos->d_inv);
   if (eos->d_bad) (void)hipFree(eos->d_bad);
   delete eos;
   return CCAKE_OK;
@@ -288,6 +349,7 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
   if (!validate_config(cfg, &why)) return CCAKE_E_ARG;
   if (((uintptr_t)workspace & 255) != 0) return CCAKE_E_ARG;
   if (eos->dev.kind == EOS_CONFORMAL && cfg->ncharge != 0) return CCAKE_E_ARG;
+  if (eos->dev.inv.val && eos->dev.inv.ncharge != cfg->ncharge) return CCAKE_E_ARG;
   const int64_t ccap = cell_capacity(*cfg, n);
   Layout L = make_layout(n, ccap, 1);
   if (bytes < L.total) return CCAKE_E_CAPACITY;

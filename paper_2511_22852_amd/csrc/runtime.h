@@ -36,6 +36,7 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
 struct ccake_eos : ccake::Handle {
   ccake::EosDev dev;
   double* d_tab = nullptr;
+  double* d_inv = nullptr;  // offline inverted table (dev.inv.val)
   uint32_t* d_bad = nullptr;
 };
 

@@ -330,6 +330,7 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
   if (!out || !eos || !validate_config(cfg, &why) || max_particles <= 0 || max_events <= 0 || !(dt > 0.0))
     return CCAKE_E_ARG;
   if (eos->dev.kind == EOS_CONFORMAL && cfg->ncharge != 0) return CCAKE_E_ARG;
+  if (eos->dev.inv.val && eos->dev.inv.ncharge != cfg->ncharge) return CCAKE_E_ARG;
   if (2.0 * dt * (cfg->dim == 3 && cfg->coords == CCAKE_HYPERBOLIC ? 2.0 : 1.0) > cfg->skin) return CCAKE_E_ARG;
   ccake_server* s = new ccake_server();
   s->magic = HANDLE_SERVER;

@@ -160,14 +160,18 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
       for (int q = 0; q < 3; ++q) dens[1 + q] = row(Y, cap, R_NB + q, j) * sigma;
   }
 
-  // EoS inversion (s, n) -> (T, mu), warm-started from the particle's last roots
-  double warm[NWARM], wnew[NWARM];
-#pragma unroll
-  for (int w = 0; w < NWARM; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
+  // EoS inversion (s, n) -> (T, mu): the offline table when the EoS carries
+  // one and (s, n) is on its grid, else online, warm-started from the
+  // particle's last roots
   Thermo th;
-  eos_invert<NQ>(eos, 0, dens, warm, th, wnew);
+  if (!(eos.inv.val && inv_lookup<NQ>(eos.inv, dens, th))) {
+    double warm[NWARM], wnew[NWARM];
 #pragma unroll
-  for (int w = 0; w < NWARM; ++w) b.warms[(int64_t)w * cap + j] = wnew[w];
+    for (int w = 0; w < NWARM; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
+    eos_invert<NQ>(eos, 0, dens, warm, th, wnew);
+#pragma unroll
+    for (int w = 0; w < NWARM; ++w) b.warms[(int64_t)w * cap + j] = wnew[w];
+  }
   c_noconv = th.ok ? 0u : 1u;
   c_backup = (!th.in_table && eos.kind == EOS_TABLE) ? 1u : 0u;
   c_iters = (uint32_t)th.iters;

@@ -1,0 +1,156 @@
+"""GPU parity of the offline inverted EoS table ("EoS inverter", offline
+option): lookups and stages of the HIP library (through the C ABI) against
+the oracle, each side building its own table from the same grid description
+with its own online inverter.
+
+Bars: on-grid decisions and in-table flags bit-exact; FP64 values within a
+relative 1e-12 (chemical potentials on the scale of T); rates within 1e-12
+per state row; trajectories within 1e-9.
+"""
+import numpy as np
+import pytest
+
+from cases import make, perturb, rel_inf, table
+from paper_2511_22852_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GRID = dict(decade_lo=-1, decade_hi=3, per_decade=36, nx=(9, 5, 5), x_lo=(-0.1, -0.05, -0.05),
+            x_hi=(0.1, 0.05, 0.05))
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2511_22852_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    return oracle_mod
+
+
+def tables(O, B, ncharge=3, grid=GRID):
+    cols, lo, hi = table("small")
+    oe, ge = O.eos_table(cols, lo, hi), B.Eos.table(cols, lo, hi)
+    oinv = O.eos_inverted(oe, ncharge, grid["decade_lo"], grid["decade_hi"], grid["per_decade"],
+                          nx=grid["nx"], xlo=grid["x_lo"], xhi=grid["x_hi"])
+    ge.build_inverted(ncharge, grid["decade_lo"], grid["decade_hi"], grid["per_decade"], nx=grid["nx"],
+                      x_lo=grid["x_lo"], x_hi=grid["x_hi"])
+    return oe, oinv, ge
+
+
+def check_rows(O, g, o, sel):
+    T = np.abs(o[O.I_T, sel]).max()
+    for r in (O.I_T, O.I_P, O.I_E, O.I_CS2, O.I_KAP):
+        assert rel_inf(g[r, sel], o[r, sel]) <= 1e-12, (r, rel_inf(g[r, sel], o[r, sel]))
+    for r in (O.I_MUB, O.I_MUS, O.I_MUQ):
+        assert np.abs(g[r, sel] - o[r, sel]).max() <= 1e-12 * T, r
+
+
+def test_lookup_parity(B, O):
+    oe, oinv, ge = tables(O, B)
+    rng = np.random.default_rng(11)
+    m = 20000
+    s = 10.0 ** rng.uniform(-1.3, 3.2, m)           # some points below and above the s grid
+    x = np.stack([rng.uniform(-0.12, 0.12, m), rng.uniform(-0.06, 0.06, m), rng.uniform(-0.06, 0.06, m)])
+    pts = np.vstack([s, x * s])
+    # exact node coordinates too (every corner weight but one is zero there)
+    P = GRID["per_decade"]
+    nodes = np.array([10.0 ** (-1 + g // P) * (1 + 9 * (g % P) / P) for g in range(4 * P)] + [1000.0])
+    pts = np.hstack([pts, np.vstack([nodes, np.zeros((3, nodes.size))])])
+    o, o_in = O.inv_eval(oinv, pts)
+    g, g_in = ge.offline_eval(pts)
+    assert np.array_equal(g_in, o_in)
+    assert 0.5 < o_in.mean() < 0.95
+    assert np.isnan(g[:, ~g_in]).all()
+    check_rows(O, g, o, o_in)
+    assert np.array_equal(g[O.I_TAB, o_in], o[O.I_TAB, o_in])
+    assert 0 < o[O.I_TAB, o_in].mean() < 1                # table and backup corners both present
+    # off the grid: the online inversion on both sides
+    g2, _ = ge.offline_eval(pts, fallback=True)
+    o2, _ = O.inv_eval(oinv, pts, fallback=True)
+    check_rows(O, g2, o2, ~o_in)
+
+
+def test_charge_free_table(B, O):
+    grid = dict(GRID, nx=(1, 1, 1))
+    oe, oinv, ge = tables(O, B, ncharge=0, grid=grid)
+    s = 10.0 ** np.linspace(-0.9, 2.9, 777)
+    pts = np.vstack([s, np.zeros((3, s.size))])
+    o, o_in = O.inv_eval(oinv, pts)
+    g, g_in = ge.offline_eval(pts)
+    assert o_in.all() and g_in.all()
+    check_rows(O, g, o, o_in)
+    assert np.array_equal(g[O.I_TAB], o[O.I_TAB])
+
+
+def lumpy_case(O, B):
+    w = I.lumpy_2d_workload(n_side=40, seed=1, n_hot=10, radius=1.0, rhoB=0.05, rhoQ=0.02)
+    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", h=w.h)
+    grid = dict(GRID, decade_lo=-1, decade_hi=3, nx=(13, 5, 9), x_lo=(-0.02, -0.03, -0.02),
+                x_hi=(0.1, 0.03, 0.06))
+    oinv = O.eos_inverted(oe, 3, grid["decade_lo"], grid["decade_hi"], grid["per_decade"], nx=grid["nx"],
+                          xlo=grid["x_lo"], xhi=grid["x_hi"])
+    ge.build_inverted(3, grid["decade_lo"], grid["decade_hi"], grid["per_decade"], nx=grid["nx"],
+                      x_lo=grid["x_lo"], x_hi=grid["x_hi"])
+    y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    return w, prm, oe, oinv, cfg, ge, y
+
+
+def test_rate_parity_offline(B, O):
+    w, prm, oe, oinv, cfg, ge, y = lumpy_case(O, B)
+    y = perturb(O, y, 2, True, seed=4)
+    f_o, aux_o, bad = O.rhs(prm, oinv, w.t0, y)
+    assert bad == 0
+    dens = aux_o[[O.A_S, O.A_NB, O.A_NS, O.A_NQ]]
+    _, inside = O.inv_eval(oinv, dens)
+    assert inside.mean() > 0.95                       # the stage really interpolates
+    sim = B.Sim(cfg, ge, w.n)
+    sim.set_state(w.t0, y)
+    f_g, aux_g = sim.rhs()
+    for r in range(O.NVAR):
+        if np.abs(f_o[r]).max() == 0.0:
+            assert np.abs(f_g[r]).max() == 0.0, r
+        else:
+            assert rel_inf(f_g[r], f_o[r]) <= 1e-12, (r, rel_inf(f_g[r], f_o[r]))
+    for a in (O.A_T, O.A_P, O.A_E, O.A_CS2):
+        assert rel_inf(aux_g[a], aux_o[a]) <= 1e-12, a
+    assert np.array_equal(aux_g[O.A_INTABLE], aux_o[O.A_INTABLE])
+    # no Newton iteration for the particles on the grid
+    assert np.all(aux_g[B.AUX_NEWTON, inside] == 0)
+
+
+def test_trajectory_offline(B, O):
+    w, prm, oe, oinv, cfg, ge, y = lumpy_case(O, B)
+    n = 40
+    _, yo, _ = O.evolve(prm, oinv, w.t0, w.dt, n, y)
+    sim = B.Sim(cfg, ge, w.n)
+    sim.set_state(w.t0, y)
+    sim.step(w.dt, n)
+    sim.check()
+    yg = sim.get_state()
+    for r in (O.V_X1, O.V_U1, O.V_U2, O.V_S, O.V_B, O.V_P11, O.V_P12, O.V_P33):
+        assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))
+
+
+def test_offline_rejections(B, O):
+    cols, lo, hi = table("small")
+    ge = B.Eos.table(cols, lo, hi)
+    with pytest.raises(B.CcakeError) as e:
+        ge.offline_eval(np.ones((4, 3)))
+    assert e.value.status == B.E_STATE
+    for bad in (dict(per_decade=0), dict(decade_hi=-1), dict(nx=(1, 5, 5))):
+        grid = dict(GRID, **bad)
+        with pytest.raises(B.CcakeError) as e:
+            ge.build_inverted(3, grid["decade_lo"], grid["decade_hi"], grid["per_decade"], nx=grid["nx"],
+                              x_lo=grid["x_lo"], x_hi=grid["x_hi"])
+        assert e.value.status == B.E_ARG
+    ge.build_inverted(3, **GRID)
+    cfg = B.config(dim=2, ncharge=0, h=0.3)
+    with pytest.raises(B.CcakeError) as e:
+        B.Sim(cfg, ge, 100)
+    assert e.value.status == B.E_ARG
