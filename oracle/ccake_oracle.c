@@ -54,7 +54,8 @@ enum {
 /* ---- auxiliary outputs of one right-hand-side evaluation ---- */
 enum {
   A_SIGSTAR, A_S, A_NB, A_NS, A_NQ, A_T, A_MUB, A_MUS, A_MUQ, A_P, A_E,
-  A_CS2, A_INTABLE, A_GAMMA, A_THETA, A_NNB, A_F1, A_F2, A_F3, NAUX
+  A_CS2, A_INTABLE, A_GAMMA, A_THETA, A_NNB, A_F1, A_F2, A_F3,
+  A_KN_SHEAR, A_REINV_SHEAR, A_KN_BULK, A_REINV_BULK, NAUX
 };
 
 typedef struct {
@@ -942,6 +943,7 @@ typedef struct {
 typedef struct {
   double R[4];
   double dS, dB, dN[3], dP[4][4], theta, pisig;
+  double sigsig;   /* sigma^{mu nu} sigma_{mu nu} */
 } pout;
 
 static void eom_eval(const pctx *c, const double a[4], pout *o)
@@ -979,9 +981,13 @@ static void eom_eval(const pctx *c, const double a[4], pout *o)
       sig[mu][nu] = 0.5 * (m->ginv[mu] * nab[mu][nu] + m->ginv[nu] * nab[nu][mu])
                   - 0.5 * (u[mu] * Du[nu] + u[nu] * Du[mu]) - Delta * theta / 3.0;
     }
-  double pisig = 0.0;
+  double pisig = 0.0, sigsig = 0.0;
   for (int mu = 0; mu < 4; ++mu)
-    for (int nu = 0; nu < 4; ++nu) pisig += c->pi[mu][nu] * m->g[mu] * m->g[nu] * sig[mu][nu];
+    for (int nu = 0; nu < 4; ++nu) {
+      pisig += c->pi[mu][nu] * m->g[mu] * m->g[nu] * sig[mu][nu];
+      sigsig += sig[mu][nu] * m->g[mu] * m->g[nu] * sig[mu][nu];
+    }
+  o->sigsig = sigsig;
   double DPi = 0.0;
   if (c->viscous) DPi = -(c->Pi + c->zeta * theta) / c->tauPi - c->cPiPi * c->Pi * theta + c->cPipi * pisig;
   double uI = 0.0;
@@ -1275,6 +1281,18 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
         aux[A_THETA * nout + oi] = o.theta;
         aux[A_NNB * nout + oi] = qa->nnb;
         for (int i = 1; i <= 3; ++i) aux[(A_F1 + i - 1) * nout + oi] = F[i];
+        /* Knudsen and inverse Reynolds numbers ("Particlization", eq.
+         * knudsen-reynolds): Kn_pi = tau_pi sqrt(sigma:sigma), Re^-1_pi =
+         * sqrt(pi:pi)/p, Kn_Pi = tau_Pi theta, Re^-1_Pi = |Pi|/p; zero for
+         * ideal runs */
+        double pipi = 0.0;
+        for (int mu = 0; mu < 4; ++mu)
+          for (int nu = 0; nu < 4; ++nu) pipi += qa->pi[mu][nu] * m.g[mu] * m.g[nu] * qa->pi[mu][nu];
+        const int vis = prm->viscous;
+        aux[A_KN_SHEAR * nout + oi] = vis ? qa->taupi * sqrt(fabs(o.sigsig)) : 0.0;
+        aux[A_REINV_SHEAR * nout + oi] = vis ? sqrt(fabs(pipi)) / qa->th.p : 0.0;
+        aux[A_KN_BULK * nout + oi] = vis ? qa->tauPi * o.theta : 0.0;
+        aux[A_REINV_BULK * nout + oi] = vis ? fabs(qa->Pi) / qa->th.p : 0.0;
       }
     }
     free(buf);
