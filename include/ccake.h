@@ -68,12 +68,16 @@ enum {
 
 /* per-particle diagnostics of one right-hand-side evaluation (ccake_rhs, ccake_read);
  * NEWTON is the number of Newton iterations of the particle's EoS inversion and
- * EOS_EVALS the number of residual evaluations (step halvings included) */
+ * EOS_EVALS the number of residual evaluations (step halvings included).  The
+ * Knudsen and inverse Reynolds numbers ("Particlization", eq. knudsen-reynolds)
+ * are KN_SHEAR = tau_pi sqrt(sigma:sigma), REINV_SHEAR = sqrt(pi:pi)/p,
+ * KN_BULK = tau_Pi theta, REINV_BULK = |Pi|/p, zero for ideal runs. */
 enum {
   CCAKE_AUX_SIGSTAR = 0, CCAKE_AUX_S, CCAKE_AUX_NB, CCAKE_AUX_NS, CCAKE_AUX_NQ, CCAKE_AUX_T,
   CCAKE_AUX_MUB, CCAKE_AUX_MUS, CCAKE_AUX_MUQ, CCAKE_AUX_P, CCAKE_AUX_E, CCAKE_AUX_CS2,
   CCAKE_AUX_INTABLE, CCAKE_AUX_GAMMA, CCAKE_AUX_THETA, CCAKE_AUX_NNB, CCAKE_AUX_F1,
-  CCAKE_AUX_F2, CCAKE_AUX_F3, CCAKE_AUX_NEWTON, CCAKE_AUX_EOS_EVALS, CCAKE_NAUX
+  CCAKE_AUX_F2, CCAKE_AUX_F3, CCAKE_AUX_NEWTON, CCAKE_AUX_EOS_EVALS, CCAKE_AUX_KN_SHEAR,
+  CCAKE_AUX_REINV_SHEAR, CCAKE_AUX_KN_BULK, CCAKE_AUX_REINV_BULK, CCAKE_NAUX
 };
 
 typedef struct ccake_eos ccake_eos;

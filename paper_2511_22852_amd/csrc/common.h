@@ -22,7 +22,8 @@ enum Row {
 // auxiliary per-particle outputs of a right-hand-side evaluation (debug/parity)
 enum Aux {
   X_SIGSTAR, X_S, X_NB, X_NS, X_NQ, X_T, X_MUB, X_MUS, X_MUQ, X_P, X_E,
-  X_CS2, X_INTABLE, X_GAMMA, X_THETA, X_NNB, X_F1, X_F2, X_F3, X_NEWTON, X_EOS_EVALS, NAUXROW
+  X_CS2, X_INTABLE, X_GAMMA, X_THETA, X_NNB, X_F1, X_F2, X_F3, X_NEWTON, X_EOS_EVALS,
+  X_KN_SHEAR, X_REINV_SHEAR, X_KN_BULK, X_REINV_BULK, NAUXROW
 };
 
 // per-particle thermodynamic record written by pass 1, read (own particle) by pass 2

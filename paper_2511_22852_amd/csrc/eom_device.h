@@ -55,6 +55,7 @@ struct EomIn {
 struct EomOut {
   double a[4];        // du^i/dx0
   double dS, dB, theta;
+  double sigsig;      // sigma^{mu nu} sigma_{mu nu} (viscous runs; 0 otherwise)
   double dN[3];       // dN_q/dx0
   double dP[4][4];    // d(pi^{ij}/sigma)/dx0
 };
@@ -222,7 +223,17 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
   const double heat = uI - (in.mu[0] * in.Iq[0] + in.mu[1] * in.Iq[1] + in.mu[2] * in.Iq[2]);
 #pragma unroll
   for (int q = 0; q < 3; ++q) out.dN[q] = in.Iq[q] * igs;
+  out.sigsig = 0.0;
   if (VISC) {
+    double ss = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const double v = at(sg[m][n], a);
+        ss += v * g[m] * g[n] * v;
+      }
+    out.sigsig = ss;
     const double ps = at(pisig, a), th = out.theta;
     out.dS = (-Pi * th + ps + heat) / (gam * in.sigma * in.T);
     out.dB = (at(DPi, a) + Pi * th) * igs;

@@ -548,6 +548,25 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
       aux[X_THETA * n + ii] = o.theta;
 #pragma unroll
       for (int k = 1; k <= 3; ++k) aux[(X_F1 + k - 1) * n + ii] = in.F[k];
+      // Knudsen and inverse Reynolds numbers ("Particlization", eq. knudsen-reynolds)
+      double kns = 0.0, res = 0.0, knb = 0.0, reb = 0.0;
+      if (VISC) {
+        const double p = T_[(int64_t)T_P * cap + j];
+        const double gm[4] = {1.0, -1.0, -1.0, -Gk[3]};
+        double pipi = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) pipi += in.pi[m][k] * gm[m] * gm[k] * in.pi[m][k];
+        kns = in.taupi * sqrt(fabs(o.sigsig));
+        res = sqrt(fabs(pipi)) / p;
+        knb = in.tauPi * o.theta;
+        reb = fabs(in.Pi) / p;
+      }
+      aux[X_KN_SHEAR * n + ii] = kns;
+      aux[X_REINV_SHEAR * n + ii] = res;
+      aux[X_KN_BULK * n + ii] = knb;
+      aux[X_REINV_BULK * n + ii] = reb;
     }
     return;
   }

@@ -141,6 +141,13 @@ def test_rate_parity_fp64(B, O, name):
         assert np.abs(aux_g[a] - aux_o[a]).max() <= 1e-12 * np.abs(aux_o[O.A_T]).max(), a
     assert np.array_equal(aux_g[O.A_INTABLE], aux_o[O.A_INTABLE])
     assert np.array_equal(aux_g[O.A_NNB], aux_o[O.A_NNB])
+    # Knudsen and inverse Reynolds numbers
+    for ga, oa in ((B.AUX_KN_SHEAR, O.A_KN_SHEAR), (B.AUX_REINV_SHEAR, O.A_REINV_SHEAR),
+                   (B.AUX_KN_BULK, O.A_KN_BULK), (B.AUX_REINV_BULK, O.A_REINV_BULK)):
+        if np.abs(aux_o[oa]).max() == 0.0:
+            assert np.abs(aux_g[ga]).max() == 0.0, ga
+        else:
+            assert rel_inf(aux_g[ga], aux_o[oa]) <= 1e-12, (ga, rel_inf(aux_g[ga], aux_o[oa]))
 
 
 @pytest.mark.parametrize("name", ["gubser2d_ideal", "lumpy2d_visc_table_inside", "lumpy3d_visc_table"])
