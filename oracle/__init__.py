@@ -25,12 +25,13 @@ LIB = os.path.join(HERE, "libccake_oracle.so")
 HBARC = 0.1973269804
 
 NVAR = 17
-NAUX = 23
+NAUX = 31
 (V_X1, V_X2, V_X3, V_U1, V_U2, V_U3, V_S, V_NB, V_NS, V_NQ, V_B,
  V_P11, V_P12, V_P13, V_P22, V_P23, V_P33) = range(NVAR)
 (A_SIGSTAR, A_S, A_NB, A_NS, A_NQ, A_T, A_MUB, A_MUS, A_MUQ, A_P, A_E,
  A_CS2, A_INTABLE, A_GAMMA, A_THETA, A_NNB, A_F1, A_F2, A_F3,
- A_KN_SHEAR, A_REINV_SHEAR, A_KN_BULK, A_REINV_BULK) = range(NAUX)
+ A_KN_SHEAR, A_REINV_SHEAR, A_KN_BULK, A_REINV_BULK,
+ A_DE0, A_DE1, A_DE2, A_DE3, A_DSIG0, A_DSIG1, A_DSIG2, A_DSIG3) = range(NAUX)
 
 EOS_CONFORMAL, EOS_TABLE, EOS_GAS, EOS_MODCONF = 0, 1, 2, 3
 

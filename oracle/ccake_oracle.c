@@ -55,7 +55,8 @@ enum {
 enum {
   A_SIGSTAR, A_S, A_NB, A_NS, A_NQ, A_T, A_MUB, A_MUS, A_MUQ, A_P, A_E,
   A_CS2, A_INTABLE, A_GAMMA, A_THETA, A_NNB, A_F1, A_F2, A_F3,
-  A_KN_SHEAR, A_REINV_SHEAR, A_KN_BULK, A_REINV_BULK, NAUX
+  A_KN_SHEAR, A_REINV_SHEAR, A_KN_BULK, A_REINV_BULK,
+  A_DE0, A_DE1, A_DE2, A_DE3, A_DSIG0, A_DSIG1, A_DSIG2, A_DSIG3, NAUX
 };
 
 typedef struct {
@@ -1176,7 +1177,7 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
       const int64_t a = targets ? targets[oi] : oi;
       const pass1_t *qa = &P1[a];
       int64_t cnt = neighbours(prm, &g, y, n, a, &buf, &cap);
-      double F[4] = {0, 0, 0, 0}, dudx[4][4], divv = 0.0;
+      double F[4] = {0, 0, 0, 0}, dudx[4][4], divv = 0.0, de[4] = {0, 0, 0, 0};
       memset(dudx, 0, sizeof dudx);
       for (int64_t j = 0; j < cnt; ++j) {
         int64_t b = buf[j];
@@ -1194,6 +1195,7 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
         for (int k = 1; k <= D; ++k) {
           for (int nu = 1; nu <= D; ++nu) dudx[k][nu] += (qb->u[nu] - qa->u[nu]) * dW[k];
           divv += (qb->v[k] - qa->v[k]) * dW[k];
+          de[k] += (qb->th.e - qa->th.e) * dW[k];
         }
       }
       pctx c;
@@ -1293,6 +1295,35 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
         aux[A_REINV_SHEAR * nout + oi] = vis ? sqrt(fabs(pipi)) / qa->th.p : 0.0;
         aux[A_KN_BULK * nout + oi] = vis ? qa->tauPi * o.theta : 0.0;
         aux[A_REINV_BULK * nout + oi] = vis ? fabs(qa->Pi) / qa->th.p : 0.0;
+        /* Freeze-out surface element ("Freeze-out hypersurface construction"):
+         * spatial d_i e in the n = 1 difference form, d_0 e from the energy
+         * equation D e = -(e + p + Pi) theta + pi:sigma + u.I with
+         * D = gamma d_0 + u^i d_i; normal n_mu = -d_mu e / sqrt(|d e . d e|),
+         * |d sigma| = m / (sigma |u^mu n_mu|) with m = 1, d sigma_mu =
+         * |d sigma| n_mu (all zero where the normal is undefined) */
+        double dmu[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 1; k <= D; ++k) dmu[k] = de[k] / qa->sigstar;
+        double uI = 0.0;
+        for (int mu = 0; mu < 4; ++mu) uI += m.g[mu] * c.u[mu] * c.I[mu];
+        const double De = -(qa->th.e + qa->th.p + (prm->viscous ? qa->Pi : 0.0)) * o.theta
+                        + (prm->viscous ? o.pisig : 0.0) + uI;
+        double adv = 0.0;
+        for (int k = 1; k <= D; ++k) adv += c.u[k] * dmu[k];
+        dmu[0] = (De - adv) / c.u[0];
+        double nn = 0.0;
+        for (int mu = 0; mu < 4; ++mu) nn += m.ginv[mu] * dmu[mu] * dmu[mu];
+        const double norm = sqrt(fabs(nn));
+        double nl[4] = {0.0, 0.0, 0.0, 0.0}, un = 0.0;
+        if (norm > 0.0)
+          for (int mu = 0; mu < 4; ++mu) {
+            nl[mu] = -dmu[mu] / norm;
+            un += c.u[mu] * nl[mu];
+          }
+        const double dsig = (norm > 0.0 && fabs(un) > 0.0) ? 1.0 / (c.sigma * fabs(un)) : 0.0;
+        for (int mu = 0; mu < 4; ++mu) {
+          aux[(A_DE0 + mu) * nout + oi] = dmu[mu];
+          aux[(A_DSIG0 + mu) * nout + oi] = dsig * nl[mu];
+        }
       }
     }
     free(buf);

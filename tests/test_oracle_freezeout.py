@@ -1,0 +1,107 @@
+"""Pins of the oracle's freeze-out surface elements ("Freeze-out hypersurface
+construction"): d_mu e (spatial part by SPH, time part from the energy
+equation), the outward normal n_mu = -d_mu e / sqrt(|d e . d e|) and
+d sigma_mu = n_mu / (sigma |u^mu n_mu|) (m = 1).
+
+* Bjorken flow (fluid at rest in Milne coordinates, uniform lattice): no
+  spatial gradient, d_tau e = -(e + p + Pi)/tau + pi:sigma with the closed
+  form pi:sigma = (pi^xx + pi^yy)/(3 tau) - (2 tau / 3) pi^{eta eta}, so
+  n_mu = (1, 0, 0, 0) and d sigma_mu = (1/sigma, 0, 0, 0);
+* a static Cartesian blob: d_0 e = 0 exactly, and by mirror symmetry the
+  gradient of a particle on the x axis has no y component (beyond the
+  rounding of the lattice) and points inwards; its normal is spacelike and
+  orthogonal to u, so d sigma = 0;
+* everywhere: |u^mu d sigma_mu| sigma = 1 and g^{mu nu} d sigma_mu d sigma_nu
+  = +-|d sigma|^2 with n a unit vector.
+"""
+import numpy as np
+
+from paper_2511_22852_amd import inputs as I
+
+
+def lattice_event(O, hyperbolic, viscous, t0, dens_fn, side=31, dx=0.1, h=0.15):
+    xi = I.lattice((side, side), dx, -0.5 * dx * (side - 1))
+    n = xi.shape[1]
+    prm = O.params(dim=2, hyperbolic=hyperbolic, viscous=viscous, ncharge=0, h=h, eta_over_s=0.1 if viscous else 0.0,
+                   use_cells=1)
+    eos = O.eos_conformal(11.0)
+    dens = np.zeros((4, n))
+    dens[0] = dens_fn(xi)
+    y = O.init(prm, eos, t0, xi, np.zeros_like(xi), 1, dens)
+    return xi, prm, eos, y
+
+
+def test_bjorken_surface_element(oracle_mod):
+    O = oracle_mod
+    tau = 1.4
+    xi, prm, eos, y = lattice_event(O, True, True, tau, lambda x: np.full(x.shape[1], 40.0))
+    c = int(np.argmin(np.hypot(xi[0], xi[1])))
+    yB, p11, p22, p33 = -0.01, 0.02, 0.03, -0.015
+    y[O.V_B], y[O.V_P11], y[O.V_P22], y[O.V_P33] = yB, p11, p22, p33
+    _, aux, bad = O.rhs(prm, eos, tau, y)
+    assert bad == 0
+    a = lambda r: aux[r, c]
+    sig = a(O.A_SIGSTAR) / tau
+    e, p = a(O.A_E), a(O.A_P)
+    Pi = sig * yB
+    pixx, piyy, pihh = sig * p11, sig * p22, sig * p33
+    pisig = (pixx + piyy) / (3 * tau) - (2 * tau / 3) * pihh
+    de0 = -(e + p + Pi) / tau + pisig
+    assert abs(a(O.A_DE0) / de0 - 1) < 1e-12
+    # (the lattice's densities agree to rounding, so the spatial gradient is round-off)
+    for r in (O.A_DE1, O.A_DE2, O.A_DE3):
+        assert abs(a(r)) < 1e-12 * abs(de0)
+    assert abs(a(O.A_DSIG0) * sig - 1) < 1e-12
+    for r in (O.A_DSIG1, O.A_DSIG2, O.A_DSIG3):
+        assert abs(a(r)) < 1e-12 * a(O.A_DSIG0)
+
+
+def test_static_blob_on_axis(oracle_mod):
+    O = oracle_mod
+    blob = lambda x: 5.0 + 40.0 * np.exp(-(x[0] ** 2 + x[1] ** 2) / (2 * 0.6 ** 2))
+    xi, prm, eos, y = lattice_event(O, False, False, 0.0, blob)
+    _, aux, bad = O.rhs(prm, eos, 0.0, y)
+    assert bad == 0
+    assert np.all(aux[O.A_DE0] == 0.0)
+    on_axis = (np.abs(xi[1]) < 1e-12) & (xi[0] > 0.25) & (xi[0] < 1.2)
+    assert on_axis.sum() >= 5
+    assert np.all(aux[O.A_DE1, on_axis] < 0.0)
+    # mirror symmetry up to the rounding of the lattice coordinates
+    assert np.all(np.abs(aux[O.A_DE2, on_axis]) < 1e-10 * np.abs(aux[O.A_DE1, on_axis]))
+    for r in (O.A_DSIG0, O.A_DSIG1, O.A_DSIG2, O.A_DSIG3):
+        assert np.all(aux[r] == 0.0)
+
+
+def test_normalisation_everywhere(oracle_mod):
+    """Flowing, expanding, viscous lumpy event: |u.dsigma| sigma = 1 and
+    |dsigma.dsigma| = |dsigma|^2 for every particle with a surface element."""
+    O = oracle_mod
+    w = I.lumpy_2d_workload(n_side=24, spacing=0.1, h=0.25, seed=5, n_hot=6, radius=0.8, width=0.5)
+    prm = O.params(dim=2, hyperbolic=True, viscous=True, ncharge=0, h=w.h, eta_over_s=0.1, use_cells=1)
+    eos = O.eos_conformal(11.0)
+    rng = np.random.default_rng(2)
+    u = 0.3 * rng.standard_normal(w.xi.shape)
+    y = O.init(prm, eos, w.t0, w.xi, u, 1, w.dens / 10.0)
+    _, aux, bad = O.rhs(prm, eos, w.t0, y)
+    assert bad == 0
+    tau = w.t0
+    gam = aux[O.A_GAMMA]
+    uu = np.stack([gam, y[O.V_U1], y[O.V_U2], np.zeros_like(gam)])
+    ds = aux[[O.A_DSIG0, O.A_DSIG1, O.A_DSIG2, O.A_DSIG3]]
+    have = np.any(ds != 0.0, axis=0)
+    assert have.mean() > 0.9
+    sig = aux[O.A_SIGSTAR] / (gam * tau)
+    udots = np.einsum("mi,mi->i", uu, ds)
+    assert np.allclose(np.abs(udots[have]) * sig[have], 1.0, rtol=1e-12, atol=0)
+    ginv = np.array([1.0, -1.0, -1.0, -1.0 / tau ** 2])
+    dsds = np.einsum("m,mi,mi->i", ginv, ds, ds)
+    # |d sigma|^2 = (|u.d sigma|)^2 / (u.n)^2 ... with n unit: dsigma = |dsigma| n
+    mag = 1.0 / (sig * np.abs(np.einsum("mi,mi->i", uu, ds / np.sqrt(np.abs(dsds)))))
+    assert np.allclose(np.sqrt(np.abs(dsds[have])), mag[have], rtol=1e-10)
+    # n = -d e / |d e|: d sigma . d e = -|d sigma| (d e . d e) / sqrt(|d e . d e|)
+    de = aux[[O.A_DE0, O.A_DE1, O.A_DE2, O.A_DE3]]
+    dsde = np.einsum("m,mi,mi->i", ginv, ds, de)
+    dede = np.einsum("m,mi,mi->i", ginv, de, de)
+    want = -np.sqrt(np.abs(dsds)) * dede / np.sqrt(np.abs(dede))
+    assert np.allclose(dsde[have], want[have], rtol=1e-10, atol=0)
+    assert (dede[have] > 0).any() and (dede[have] < 0).any()   # timelike and spacelike normals
