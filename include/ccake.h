@@ -71,13 +71,21 @@ enum {
  * EOS_EVALS the number of residual evaluations (step halvings included).  The
  * Knudsen and inverse Reynolds numbers ("Particlization", eq. knudsen-reynolds)
  * are KN_SHEAR = tau_pi sqrt(sigma:sigma), REINV_SHEAR = sqrt(pi:pi)/p,
- * KN_BULK = tau_Pi theta, REINV_BULK = |Pi|/p, zero for ideal runs. */
+ * KN_BULK = tau_Pi theta, REINV_BULK = |Pi|/p, zero for ideal runs.  The
+ * freeze-out surface element ("Freeze-out hypersurface construction") is
+ * DE0..DE3 = d_mu e (spatial part in the n = 1 SPH difference form, d_0 e from
+ * the energy equation D e = -(e + p + Pi) theta + pi:sigma + u.I) and
+ * DSIG0..DSIG3 = d sigma_mu = n_mu / (sigma |u^mu n_mu|) with the outward
+ * normal n_mu = -d_mu e / sqrt(|d e . d e|); zero where the normal is
+ * undefined or orthogonal to u.  Lower indices; index 3 is eta or z. */
 enum {
   CCAKE_AUX_SIGSTAR = 0, CCAKE_AUX_S, CCAKE_AUX_NB, CCAKE_AUX_NS, CCAKE_AUX_NQ, CCAKE_AUX_T,
   CCAKE_AUX_MUB, CCAKE_AUX_MUS, CCAKE_AUX_MUQ, CCAKE_AUX_P, CCAKE_AUX_E, CCAKE_AUX_CS2,
   CCAKE_AUX_INTABLE, CCAKE_AUX_GAMMA, CCAKE_AUX_THETA, CCAKE_AUX_NNB, CCAKE_AUX_F1,
   CCAKE_AUX_F2, CCAKE_AUX_F3, CCAKE_AUX_NEWTON, CCAKE_AUX_EOS_EVALS, CCAKE_AUX_KN_SHEAR,
-  CCAKE_AUX_REINV_SHEAR, CCAKE_AUX_KN_BULK, CCAKE_AUX_REINV_BULK, CCAKE_NAUX
+  CCAKE_AUX_REINV_SHEAR, CCAKE_AUX_KN_BULK, CCAKE_AUX_REINV_BULK, CCAKE_AUX_DE0, CCAKE_AUX_DE1,
+  CCAKE_AUX_DE2, CCAKE_AUX_DE3, CCAKE_AUX_DSIG0, CCAKE_AUX_DSIG1, CCAKE_AUX_DSIG2, CCAKE_AUX_DSIG3,
+  CCAKE_NAUX
 };
 
 typedef struct ccake_eos ccake_eos;

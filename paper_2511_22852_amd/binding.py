@@ -23,12 +23,13 @@ FP64, MIXED = 0, 1
 DENS_SMOOTHED, DENS_SPECIFIC = 0, 1
 INIT_S, INIT_E = 0, 1
 NROW = 17
-NAUX = 25
+NAUX = 33
 (ROW_X1, ROW_X2, ROW_X3, ROW_U1, ROW_U2, ROW_U3, ROW_S, ROW_NB, ROW_NS, ROW_NQ, ROW_B,
  ROW_P11, ROW_P12, ROW_P13, ROW_P22, ROW_P23, ROW_P33) = range(NROW)
 (AUX_SIGSTAR, AUX_S, AUX_NB, AUX_NS, AUX_NQ, AUX_T, AUX_MUB, AUX_MUS, AUX_MUQ, AUX_P, AUX_E,
  AUX_CS2, AUX_INTABLE, AUX_GAMMA, AUX_THETA, AUX_NNB, AUX_F1, AUX_F2, AUX_F3, AUX_NEWTON,
- AUX_EOS_EVALS, AUX_KN_SHEAR, AUX_REINV_SHEAR, AUX_KN_BULK, AUX_REINV_BULK) = range(NAUX)
+ AUX_EOS_EVALS, AUX_KN_SHEAR, AUX_REINV_SHEAR, AUX_KN_BULK, AUX_REINV_BULK, AUX_DE0, AUX_DE1, AUX_DE2,
+ AUX_DE3, AUX_DSIG0, AUX_DSIG1, AUX_DSIG2, AUX_DSIG3) = range(NAUX)
 
 EXPORTS = [
     "ccake_eos_create_conformal", "ccake_eos_create_gas", "ccake_eos_create_table",

@@ -23,7 +23,8 @@ enum Row {
 enum Aux {
   X_SIGSTAR, X_S, X_NB, X_NS, X_NQ, X_T, X_MUB, X_MUS, X_MUQ, X_P, X_E,
   X_CS2, X_INTABLE, X_GAMMA, X_THETA, X_NNB, X_F1, X_F2, X_F3, X_NEWTON, X_EOS_EVALS,
-  X_KN_SHEAR, X_REINV_SHEAR, X_KN_BULK, X_REINV_BULK, NAUXROW
+  X_KN_SHEAR, X_REINV_SHEAR, X_KN_BULK, X_REINV_BULK, X_DE0, X_DE1, X_DE2, X_DE3, X_DSIG0, X_DSIG1,
+  X_DSIG2, X_DSIG3, NAUXROW
 };
 
 // per-particle thermodynamic record written by pass 1, read (own particle) by pass 2
@@ -47,7 +48,7 @@ enum DSum { DS_SIG, DS_S, DS_NB, DS_NS, DS_NQ, DS_NNB, NDSUM };
 
 // gradient sums of a particle: force F_i, d_k u^j (row-major k*3+j, divided by sigma*), div v
 enum GSum { GS_F1, GS_F2, GS_F3, GS_DU11, GS_DU12, GS_DU13, GS_DU21, GS_DU22, GS_DU23, GS_DU31, GS_DU32,
-            GS_DU33, GS_DIVV, NGSUM };
+            GS_DU33, GS_DIVV, GS_DE1, GS_DE2, GS_DE3, NGSUM };
 
 enum EosKind { EOS_CONFORMAL = 0, EOS_TABLE = 1, EOS_GAS = 2 };
 

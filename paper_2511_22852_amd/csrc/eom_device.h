@@ -56,6 +56,7 @@ struct EomOut {
   double a[4];        // du^i/dx0
   double dS, dB, theta;
   double sigsig;      // sigma^{mu nu} sigma_{mu nu} (viscous runs; 0 otherwise)
+  double pisig;       // pi^{mu nu} sigma_{mu nu} (viscous runs; 0 otherwise)
   double dN[3];       // dN_q/dx0
   double dP[4][4];    // d(pi^{ij}/sigma)/dx0
 };
@@ -224,6 +225,7 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
 #pragma unroll
   for (int q = 0; q < 3; ++q) out.dN[q] = in.Iq[q] * igs;
   out.sigsig = 0.0;
+  out.pisig = 0.0;
   if (VISC) {
     double ss = 0.0;
 #pragma unroll
@@ -235,6 +237,7 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
       }
     out.sigsig = ss;
     const double ps = at(pisig, a), th = out.theta;
+    out.pisig = ps;
     out.dS = (-Pi * th + ps + heat) / (gam * in.sigma * in.T);
     out.dB = (at(DPi, a) + Pi * th) * igs;
 #pragma unroll

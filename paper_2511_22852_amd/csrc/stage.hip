@@ -389,6 +389,41 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   if (lane == 0) write_grad<D, VISC, MIXED>(b, prm, j, A);
 }
 
+// Spatial gradient of the energy density for the freeze-out surface
+// ("Freeze-out hypersurface construction"), n = 1 difference form like
+// d_k u^j: d_i e_a = (1/sigma*_a) sum_b (e_b - e_a) d_i W_ab.  One thread per
+// particle; runs only for diagnostic evaluations.
+template <int D>
+__global__ void __launch_bounds__(128) k_fo_grad(BatchDev b, Params prm, const double* __restrict__ Y,
+                                                 int64_t nslots) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nslots) return;
+  const int e = b.ev[j];
+  if (e < 0) return;
+  const EventDev& E = b.evt[e];
+  const int64_t cap = b.cap;
+  const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
+  const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
+  const double* Ev = b.th + (int64_t)T_E * cap;
+  const double ea = Ev[j];
+  double de[3] = {0.0, 0.0, 0.0};
+  for_each_row<D>(b, E, b.keys[j], xa, prm.cell_edge, [&](int32_t lo, int32_t hi) {
+    for (int32_t k = lo; k < hi; ++k) {
+      const double xb[3] = {row(Y, cap, R_X1, k), row(Y, cap, R_X2, k), D == 3 ? row(Y, cap, R_X3, k) : 0.0};
+      const double d2 = dist2<D>(xa, xb);
+      if (!(d2 < r2max)) continue;
+      const double r = sqrt(d2);
+      if (!(r > 0.0)) continue;
+      const double f = spline_dw(r * ih) / r * (Ev[k] - ea);
+#pragma unroll
+      for (int q = 0; q < D; ++q) de[q] += f * (xa[q] - xb[q]);
+    }
+  });
+  const double isg = sigma_d<D>(h) / h / b.th[(int64_t)T_SIGSTAR * cap + j];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) b.gsum[(int64_t)(GS_DE1 + q) * cap + j] = q < D ? de[q] * isg : 0.0;
+}
+
 // Source densities I^mu, I_q at position x and time t: sum over the active
 // sources of the rates times the normalised Gaussian around the moving
 // centre, divided by sqrt(-g) (eq. conservation_source with the smeared
@@ -567,6 +602,43 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
       aux[X_REINV_SHEAR * n + ii] = res;
       aux[X_KN_BULK * n + ii] = knb;
       aux[X_REINV_BULK * n + ii] = reb;
+      // freeze-out surface element ("Freeze-out hypersurface construction"):
+      // d_0 e from D e = -(e + p + Pi) theta + pi:sigma + u.I, D = gamma d_0 + u^i d_i;
+      // n_mu = -d_mu e / sqrt(|d e . d e|), d sigma_mu = n_mu / (sigma |u.n|)
+      {
+        const double ee = T_[(int64_t)T_E * cap + j], pp = T_[(int64_t)T_P * cap + j];
+        const double gm[4] = {1.0, -1.0, -1.0, -Gk[3]};
+        const double giv[4] = {1.0, -1.0, -1.0, -1.0 / Gk[3]};
+        double dmu[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < D; ++q) dmu[1 + q] = b.gsum[(int64_t)(GS_DE1 + q) * cap + j];
+        double uI = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) uI += gm[m] * in.u[m] * in.I[m];
+        const double De = -(ee + pp + in.Pi) * o.theta + o.pisig + uI;
+        double adv = 0.0;
+#pragma unroll
+        for (int k = 1; k <= D; ++k) adv += in.u[k] * dmu[k];
+        dmu[0] = (De - adv) / in.u[0];
+        double nn = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) nn += giv[m] * dmu[m] * dmu[m];
+        const double norm = sqrt(fabs(nn));
+        double nl[4] = {0.0, 0.0, 0.0, 0.0}, un = 0.0;
+        if (norm > 0.0) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            nl[m] = -dmu[m] / norm;
+            un += in.u[m] * nl[m];
+          }
+        }
+        const double dsig = (norm > 0.0 && fabs(un) > 0.0) ? 1.0 / (in.sigma * fabs(un)) : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          aux[(X_DE0 + m) * n + ii] = dmu[m];
+          aux[(X_DSIG0 + m) * n + ii] = dsig * nl[m];
+        }
+      }
     }
     return;
   }
@@ -624,6 +696,7 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
   if (mk) (void)hipEventRecord(mk[2], s);
   if (!rates) return;
   hipLaunchKernelGGL((k_grad<D, VISC, MIXED>), dim3(gt), dim3(256), 0, s, b, prm, Y, stage, nslots);
+  if (aux) hipLaunchKernelGGL((k_fo_grad<D>), dim3(gp), dim3(128), 0, s, b, prm, Y, nslots);
   if (mk) (void)hipEventRecord(mk[3], s);
   hipLaunchKernelGGL((k_eom<D, VISC>), dim3(gp), dim3(128), 0, s, b, prm, Y, stage, mode, nslots, fout, aux);
   if (mk) (void)hipEventRecord(mk[4], s);

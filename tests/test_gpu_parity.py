@@ -148,6 +148,14 @@ def test_rate_parity_fp64(B, O, name):
             assert np.abs(aux_g[ga]).max() == 0.0, ga
         else:
             assert rel_inf(aux_g[ga], aux_o[oa]) <= 1e-12, (ga, rel_inf(aux_g[ga], aux_o[oa]))
+    # freeze-out surface elements: each 4-vector on the scale of its largest
+    # component; d sigma divides by u.n, which cancels for normals nearly
+    # orthogonal to u (condition number of that division: |u| |n| / |u.n|)
+    for g0, o0, tol in ((B.AUX_DE0, O.A_DE0, 1e-12), (B.AUX_DSIG0, O.A_DSIG0, 1e-10)):
+        og = aux_o[o0:o0 + 4]
+        gg = aux_g[g0:g0 + 4]
+        scale = np.abs(og).max(axis=0)
+        assert np.all(np.abs(gg - og) <= tol * scale + 1e-300), (g0, np.max(np.abs(gg - og) / (scale + 1e-300)))
 
 
 @pytest.mark.parametrize("name", ["gubser2d_ideal", "lumpy2d_visc_table_inside", "lumpy3d_visc_table"])
