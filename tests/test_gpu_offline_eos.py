@@ -154,3 +154,25 @@ def test_offline_rejections(B, O):
     with pytest.raises(B.CcakeError) as e:
         B.Sim(cfg, ge, 100)
     assert e.value.status == B.E_ARG
+
+
+def test_rate_parity_offline_3d(B, O):
+    w = I.lumpy_3d_workload(nxy=20, dxy=0.1, neta=12, deta=0.125, h=0.3, seed=3, n_hot=6, radius=0.6)
+    prm, oe, cfg, ge = make(O, B, dim=3, viscous=True, ncharge=3, eos="table", h=w.h)
+    grid = dict(decade_lo=-1, decade_hi=3, per_decade=36, nx=(13, 5, 9), x_lo=(-0.02, -0.03, -0.02),
+                x_hi=(0.1, 0.03, 0.06))
+    oinv = O.eos_inverted(oe, 3, grid["decade_lo"], grid["decade_hi"], grid["per_decade"], nx=grid["nx"],
+                          xlo=grid["x_lo"], xhi=grid["x_hi"])
+    ge.build_inverted(3, **grid)
+    y = perturb(O, O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens), 3, True, seed=6)
+    f_o, aux_o, bad = O.rhs(prm, oinv, w.t0, y)
+    assert bad == 0
+    _, inside = O.inv_eval(oinv, aux_o[[O.A_S, O.A_NB, O.A_NS, O.A_NQ]])
+    assert inside.mean() > 0.9
+    sim = B.Sim(cfg, ge, w.n)
+    sim.set_state(w.t0, y)
+    f_g, aux_g = sim.rhs()
+    for r in range(O.NVAR):
+        if np.abs(f_o[r]).max() > 0.0:
+            assert rel_inf(f_g[r], f_o[r]) <= 1e-12, (r, rel_inf(f_g[r], f_o[r]))
+    assert np.array_equal(aux_g[O.A_INTABLE], aux_o[O.A_INTABLE])

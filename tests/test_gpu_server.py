@@ -49,9 +49,18 @@ def alone(B, cfg, eos, w, nsteps):
     return y
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_alone_equals_in_mix(B, eos, precision):
+@pytest.fixture(scope="module")
+def eos_offline(B):
+    """The same EoS with the offline inverted table attached."""
+    cols, lo, hi = I.massless_gas_table(nT=24, nmu=12)
+    e = B.Eos.table(cols, lo, hi)
+    return e.build_inverted(3, -2, 3, 18, nx=(11, 7, 9), x_lo=(0.0, -0.03, -0.02), x_hi=(0.1, 0.03, 0.06))
+
+
+@pytest.mark.parametrize("precision,inverter", [(0, "online"), (1, "online"), (1, "offline")])
+def test_alone_equals_in_mix(B, eos, eos_offline, precision, inverter):
     cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=0.24, precision=precision, **TR)
+    eos = eos_offline if inverter == "offline" else eos
     evs = events(8)
     steps = [10 + 3 * i for i in range(len(evs))]
     ref = [alone(B, cfg, eos, w, s) for w, s in zip(evs, steps)]
