@@ -24,10 +24,14 @@ SRC = os.path.join(HERE, "ccake_oracle.c")
 LIB = os.path.join(HERE, "libccake_oracle.so")
 HBARC = 0.1973269804
 
-NVAR = 17
+NVAR = 26
 NAUX = 31
 (V_X1, V_X2, V_X3, V_U1, V_U2, V_U3, V_S, V_NB, V_NS, V_NQ, V_B,
- V_P11, V_P12, V_P13, V_P22, V_P23, V_P33) = range(NVAR)
+ V_P11, V_P12, V_P13, V_P22, V_P23, V_P33,
+ V_JB1, V_JB2, V_JB3, V_JS1, V_JS2, V_JS3, V_JQ1, V_JQ2, V_JQ3) = range(NVAR)
+# kappa_{qq'}/T^2 of the paper's full BSQ diffusion matrix ("BSQ diffusion and
+# the beam energy scan"), rows and columns (B, S, Q)
+KAPPA_T2_BSQ = ((0.0482, -0.0482, 0.0), (-0.0482, 0.1447, 0.0147), (0.0, 0.0147, 0.0880))
 (A_SIGSTAR, A_S, A_NB, A_NS, A_NQ, A_T, A_MUB, A_MUS, A_MUQ, A_P, A_E,
  A_CS2, A_INTABLE, A_GAMMA, A_THETA, A_NNB, A_F1, A_F2, A_F3,
  A_KN_SHEAR, A_REINV_SHEAR, A_KN_BULK, A_REINV_BULK,
@@ -61,6 +65,9 @@ class Params(ctypes.Structure):
         ("c_piPi", ctypes.c_double),
         ("nsrc", ctypes.c_int32), ("pad1", ctypes.c_int32),
         ("src", ctypes.c_void_p),
+        ("diffusion", ctypes.c_int32), ("pad2", ctypes.c_int32),
+        ("kappa_T2", ctypes.c_double * 9), ("tauJ_coeff", ctypes.c_double),
+        ("c_JJ", ctypes.c_double),
     ]
 
 
@@ -178,8 +185,14 @@ def _f64(a):
 def params(dim=2, hyperbolic=True, viscous=False, ncharge=0, h=0.3, eta_over_s=0.0,
            zeta_peak=0.0, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, taupi_coeff=5.0,
            tauPi_ratio=1.0, c_PiPi=1.0, c_Pipi=0.0, c_pipi=4.0 / 3.0, c_piPi=0.0,
-           use_cells=None, nthreads=0, density_mode=0, source_specs=None) -> Params:
+           use_cells=None, nthreads=0, density_mode=0, source_specs=None, diffusion=False,
+           kappa_T2=KAPPA_T2_BSQ, tauJ_coeff=0.2, c_JJ=0.0) -> Params:
     p = Params()
+    p.diffusion = int(bool(diffusion))
+    kT = np.asarray(kappa_T2, dtype=np.float64).reshape(3, 3)
+    for i in range(9):
+        p.kappa_T2[i] = float(kT.flat[i])
+    p.tauJ_coeff, p.c_JJ = tauJ_coeff, c_JJ
     if source_specs:
         arr = sources(source_specs)
         p.nsrc = len(source_specs)

@@ -46,10 +46,13 @@
 #include <omp.h>
 #endif
 
-/* ---- state layout: 17 rows of n doubles, original particle order ---- */
+/* ---- state layout: 26 rows of n doubles, original particle order ----
+ * The last nine are the charge diffusion currents J^k_q / sigma (q = B, S, Q;
+ * k = 1..3 contravariant spatial), zero unless diffusion is on. */
 enum {
   V_X1, V_X2, V_X3, V_U1, V_U2, V_U3, V_S, V_NB, V_NS, V_NQ, V_B,
-  V_P11, V_P12, V_P13, V_P22, V_P23, V_P33, NVAR
+  V_P11, V_P12, V_P13, V_P22, V_P23, V_P33,
+  V_JB1, V_JB2, V_JB3, V_JS1, V_JS2, V_JS3, V_JQ1, V_JQ2, V_JQ3, NVAR
 };
 /* ---- auxiliary outputs of one right-hand-side evaluation ---- */
 enum {
@@ -80,6 +83,12 @@ typedef struct {
   int32_t nsrc;        /* external sources (eq. conservation_source), 0 = isolated */
   int32_t pad1;
   const struct orc_source *src;
+  /* BSQ charge diffusion ("BSQ diffusion", eq. min_dif_rel); needs ncharge 3 */
+  int32_t diffusion;   /* 0 off, 1 on */
+  int32_t pad2;
+  double kappa_T2[9];  /* kappa_{qq'} / T^2, row-major q*3+q' (constant matrix) */
+  double tauJ_coeff;   /* tau_{qq'} = tauJ_coeff delta_{qq'} / T */
+  double c_JJ;         /* coefficient of -tau_J J^mu theta (reading; 0 by default) */
 } orc_params;
 
 /* One external source of energy-momentum and charge (eq. conservation_source;
@@ -926,6 +935,31 @@ static void geom_at(int hyperbolic, double t, geom *m)
  * and I_q to the charges (eq. charge_conservation), dN_q/dx0 = I_q/(gamma sigma).
  * In Dp the source heats at fixed n: Dp gains (dp/de)_n u.I; the charge
  * source's (dp/dn_q)_e I_q is taken as zero (reading; exact for p = eps/3).
+ *
+ * BSQ diffusion ("BSQ diffusion", eq. min_dif_rel, eq. charge_conservation,
+ * eq. genform with R^S_a = -mu_a/T of eq. dsdnrewr).  State V^k_q = J^k_q/sigma.
+ * Readings:
+ *   - sign: in the mostly-minus metric J^mu relaxes towards
+ *     +kappa_{qq'} nabla^mu alpha_{q'} (alpha = mu/T), the sign of eq. dnmr
+ *     that moves charge down its chemical-potential gradient;
+ *   - nabla^i alpha = g^{ii} d_i alpha: the u^i D alpha part of the
+ *     projection is dropped (for these equations of state alpha is a
+ *     function of n/s, whose comoving derivative is itself first order);
+ *   - the theta term of eq. min_dif_rel (coefficient 1/(2 beta), beta not
+ *     given) enters as -c_JJ tau_J J theta with a caller-supplied c_JJ;
+ *   - the pressure does not respond to diffusion ((dp/dn_q)_e = 0, as for
+ *     the sources), so the momentum solve is unchanged (R^i_b = 0).
+ * Relaxation, with Delta^mu_nu D J^nu = DJ^mu + u^mu J^nu Du_nu and
+ * DJ^i = gamma dJ^i/dx0 + u^l Gam^i_lk J^k, D sigma = -sigma theta:
+ *     gamma sigma dV^i/dx0 = (kappa_{qq'} g^{ii} d_i alpha_{q'} - J^i)/tau_J
+ *         + (1 - c_JJ) J^i theta - u^i J^nu Du_nu - u^l Gam^i_lk J^k.
+ * Charges: integrating eq. charge_conservation over the particle's
+ * coordinate volume 1/sigma* (which moves with v) gives
+ *     d/dx0 [N_q + sqrt(-g) J^0_q / sigma*] = [sqrt(-g) I_q - d_i(sqrt(-g) F^i_q)] / sigma*,
+ * F^i = J^i - v^i J^0, J^0 = G_k u^k J^k / gamma (u_mu J^mu = 0); the flux
+ * divergence takes the n = -1 form, so the charge moved between two
+ * particles is equal and opposite and sum_a (N + sqrt(-g) J^0/sigma*) is
+ * conserved.  Entropy: gamma sigma T dS/dx0 gains -mu_q gamma sigma dN_q/dx0.
  * ======================================================================== */
 typedef struct {
   int D, viscous;
@@ -939,12 +973,20 @@ typedef struct {
   double P[4][4];    /* pi^{ij} / sigma (spatial) */
   double cPiPi, cPipi, cpipi, cpiPi;
   double I[4], Iq[3], mu[3]; /* source densities I^mu, I_q; chemical potentials */
+  int diffusion;
+  double J[3][4];     /* J^mu_q (J^0 from orthogonality) */
+  double V[3][4];     /* J^k_q / sigma (state) */
+  double dalpha[3][4];/* d_k alpha_q, n = 1 form */
+  double divF[3];     /* sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad W  (~ d_i F^i / sigma*) */
+  double kapJ[3][3];  /* diffusion matrix kappa_{qq'} */
+  double tauJ, cJJ;
 } pctx;
 
 typedef struct {
   double R[4];
   double dS, dB, dN[3], dP[4][4], theta, pisig;
   double sigsig;   /* sigma^{mu nu} sigma_{mu nu} */
+  double dV[3][4]; /* d(J^k_q/sigma)/dx0 */
 } pout;
 
 static void eom_eval(const pctx *c, const double a[4], pout *o)
@@ -1014,6 +1056,31 @@ static void eom_eval(const pctx *c, const double a[4], pout *o)
   o->dS = ((c->viscous ? -c->Pi * theta + pisig : 0.0) + heat) / (gam * c->sigma * c->T);
   o->dB = c->viscous ? (DPi + c->Pi * theta) / (gam * c->sigma) : 0.0;
   for (int q = 0; q < 3; ++q) o->dN[q] = c->Iq[q] / (gam * c->sigma);
+  memset(o->dV, 0, sizeof o->dV);
+  if (c->diffusion) {
+    for (int q = 0; q < 3; ++q) {
+      double JDu = 0.0;
+      for (int nu = 0; nu < 4; ++nu) JDu += c->J[q][nu] * Dl[nu];
+      for (int i = 1; i <= c->D; ++i) {
+        double target = 0.0;
+        for (int r = 0; r < 3; ++r) target += c->kapJ[q][r] * m->ginv[i] * c->dalpha[r][i];
+        double val = (target - c->J[q][i]) / c->tauJ + (1.0 - c->cJJ) * c->J[q][i] * theta - u[i] * JDu;
+        for (int l = 0; l < 4; ++l)
+          for (int k = 0; k < 4; ++k) val -= u[l] * m->Gam[i][l][k] * c->J[q][k];
+        o->dV[q][i] = val / (gam * c->sigma);
+      }
+      /* d/dx0 of sqrt(-g) J^0 / sigma* = J^0/(gamma sigma) = (G_k u^k V^k)/gamma^2 */
+      double X = 0.0, dX = 0.0;
+      for (int k = 1; k < 4; ++k) {
+        X += m->G[k] * u[k] * c->V[q][k];
+        dX += (m->Gdot[k] * u[k] + m->G[k] * a[k]) * c->V[q][k] + m->G[k] * u[k] * o->dV[q][k];
+      }
+      double dY = dX / (gam * gam) - 2.0 * X * dgam / (gam * gam * gam);
+      double ddiff = -dY - m->sqrtg * c->divF[q];
+      o->dN[q] += ddiff;
+      o->dS -= c->mu[q] * ddiff / c->T;
+    }
+  }
   double dwPs = (pisig + Dp + DPi + uI) / (c->sigma * gam);
   for (int i = 0; i < 4; ++i) o->R[i] = 0.0;
   for (int i = 1; i <= c->D; ++i) {
@@ -1042,6 +1109,9 @@ typedef struct {
   double eta, zeta, taupi, tauPi;
   double ppi_over_s2;       /* (p + Pi)/sigma*^2 */
   double A_over_s2[4][4];   /* (pi^{ji} - v^j pi^{0i})/sigma*^2, [j][i] */
+  double J[3][4];           /* diffusion currents J^mu_q */
+  double alpha[3];          /* mu_q / T */
+  double F_over_s2[3][4];   /* (J^k_q - v^k J^0_q)/sigma*^2 */
   int nnb;
 } pass1_t;
 
@@ -1164,6 +1234,21 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
       q->ppi_over_s2 = (q->th.p + q->Pi) / s2;
       for (int j = 0; j < 4; ++j)
         for (int i = 0; i < 4; ++i) q->A_over_s2[j][i] = (q->pi[j][i] - q->v[j] * q->pi[0][i]) / s2;
+      memset(q->J, 0, sizeof q->J);
+      memset(q->F_over_s2, 0, sizeof q->F_over_s2);
+      for (int c = 0; c < 3; ++c) q->alpha[c] = 0.0;
+      if (prm->diffusion) {
+        for (int c = 0; c < 3; ++c) {
+          double J0 = 0.0;
+          for (int k = 1; k <= D; ++k) {
+            q->J[c][k] = sigma * y[(V_JB1 + 3 * c + k - 1) * n + a];
+            J0 += m.G[k] * q->u[k] * q->J[c][k];
+          }
+          q->J[c][0] = J0 / q->gam;
+          for (int k = 1; k <= D; ++k) q->F_over_s2[c][k] = (q->J[c][k] - q->v[k] * q->J[c][0]) / s2;
+          q->alpha[c] = q->th.mu[c] / q->th.T;
+        }
+      }
     }
     free(buf);
   }
@@ -1178,7 +1263,9 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
       const pass1_t *qa = &P1[a];
       int64_t cnt = neighbours(prm, &g, y, n, a, &buf, &cap);
       double F[4] = {0, 0, 0, 0}, dudx[4][4], divv = 0.0, de[4] = {0, 0, 0, 0};
+      double dal[3][4], divF[3] = {0, 0, 0};
       memset(dudx, 0, sizeof dudx);
+      memset(dal, 0, sizeof dal);
       for (int64_t j = 0; j < cnt; ++j) {
         int64_t b = buf[j];
         const pass1_t *qb = &P1[b];
@@ -1197,6 +1284,12 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
           divv += (qb->v[k] - qa->v[k]) * dW[k];
           de[k] += (qb->th.e - qa->th.e) * dW[k];
         }
+        if (prm->diffusion)
+          for (int c = 0; c < 3; ++c)
+            for (int k = 1; k <= D; ++k) {
+              dal[c][k] += (qb->alpha[c] - qa->alpha[c]) * dW[k];
+              divF[c] += (qa->F_over_s2[c][k] + qb->F_over_s2[c][k]) * dW[k];
+            }
       }
       pctx c;
       memset(&c, 0, sizeof c);
@@ -1236,6 +1329,20 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
         c.mu[q] = q < prm->ncharge ? qa->th.mu[q] : 0.0;
         if (q >= prm->ncharge) c.Iq[q] = 0.0;
       }
+      c.diffusion = prm->diffusion;
+      if (prm->diffusion) {
+        memcpy(c.J, qa->J, sizeof c.J);
+        for (int q = 0; q < 3; ++q) {
+          for (int k = 1; k <= D; ++k) {
+            c.V[q][k] = y[(V_JB1 + 3 * q + k - 1) * n + a];
+            c.dalpha[q][k] = dal[q][k] / qa->sigstar;
+          }
+          c.divF[q] = divF[q];
+          for (int r = 0; r < 3; ++r) c.kapJ[q][r] = prm->kappa_T2[3 * q + r] * qa->th.T * qa->th.T;
+        }
+        c.tauJ = prm->tauJ_coeff / qa->th.T;
+        c.cJJ = prm->c_JJ;
+      }
 
       double zero[4] = {0, 0, 0, 0}, M[4][4], rhs[4], acc_u[4] = {0, 0, 0, 0};
       pout o0, oj;
@@ -1269,6 +1376,9 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
         dydt[V_P23 * nout + oi] = o.dP[2][3];
         dydt[V_P33 * nout + oi] = o.dP[3][3];
       }
+      if (prm->diffusion)
+        for (int q = 0; q < 3; ++q)
+          for (int k = 1; k <= D; ++k) dydt[(V_JB1 + 3 * q + k - 1) * nout + oi] = o.dV[q][k];
       if (aux) {
         aux[A_SIGSTAR * nout + oi] = qa->sigstar;
         aux[A_S * nout + oi] = qa->s;
@@ -1412,7 +1522,8 @@ int orc_init(const orc_params *prm, const orc_eos *eos, double t0, int64_t n,
   return bad;
 }
 
-/* Per-event totals: S, NB, NS, NQ, E, M1, M2, M3 where
+/* Per-event totals: S, NB, NS, NQ, E, M1, M2, M3 (charges as conserved with
+ * diffusion, N_q + sqrt(-g) J^0_q / sigma*) where
  *   E   = sum_a sqrt(-g) T^{00}_a / sigma*_a,
  *   M_i = sum_a sqrt(-g) G_i T^{0i}_a / sigma*_a.
  * In Cartesian coordinates E and M_i are the conserved energy and momentum. */
@@ -1427,11 +1538,20 @@ void orc_totals(const orc_params *prm, const orc_eos *eos, double t, int64_t n, 
   for (int k = 0; k < 8; ++k) out[k] = 0.0;
   for (int64_t a = 0; a < n; ++a) {
     out[0] += y[V_S * n + a];
-    for (int k = 0; k < 3; ++k) out[1 + k] += y[(V_NB + k) * n + a];
     double u[4] = {0, 0, 0, 0};
     for (int k = 1; k <= prm->dim; ++k) u[k] = y[(V_U1 + k - 1) * n + a];
     double gam = gamma_of(&m, u);
     u[0] = gam;
+    /* charge of a particle: N_q, plus sqrt(-g) J^0_q / sigma* with diffusion */
+    for (int q = 0; q < 3; ++q) {
+      double Nq = y[(V_NB + q) * n + a];
+      if (prm->diffusion) {
+        double X = 0.0;
+        for (int k = 1; k <= prm->dim; ++k) X += m.G[k] * u[k] * y[(V_JB1 + 3 * q + k - 1) * n + a];
+        Nq += X / (gam * gam);
+      }
+      out[1 + q] += Nq;
+    }
     double sigstar = aux[A_SIGSTAR * n + a];
     double sigma = sigstar / (gam * m.sqrtg);
     double p = aux[A_P * n + a], w = aux[A_E * n + a] + p;
