@@ -20,7 +20,7 @@
  *     mem = CCAKE_DEVICE: device pointers valid on the library's device; the
  *     copy is enqueued on the handle's stream and the pointer must stay valid
  *     until the stream reaches it.
- *   - The state layout (17 rows, CCAKE_ROW_*) is the exchange format of
+ *   - The state layout (26 rows, CCAKE_ROW_*) is the exchange format of
  *     ccake_set_state / ccake_get_state (checkpoint / restore).
  *   - Handles are not thread-safe; one simulation per stream.
  */
@@ -58,11 +58,15 @@ enum { CCAKE_DENS_SMOOTHED = 0, CCAKE_DENS_SPECIFIC = 1 };
 /* dens_kind of ccake_init_particles */
 enum { CCAKE_INIT_S = 0, CCAKE_INIT_E = 1 };
 
-/* rows of the state exchange format */
+/* rows of the state exchange format: x^k, u^k, S = s/sigma, N_q = n_q/sigma,
+ * B = Pi/sigma, P^{ij} = pi^{ij}/sigma, and J^k_q/sigma (the charge diffusion
+ * currents, contravariant spatial components; zero without diffusion) */
 enum {
   CCAKE_ROW_X1 = 0, CCAKE_ROW_X2, CCAKE_ROW_X3, CCAKE_ROW_U1, CCAKE_ROW_U2, CCAKE_ROW_U3,
   CCAKE_ROW_S, CCAKE_ROW_NB, CCAKE_ROW_NS, CCAKE_ROW_NQ, CCAKE_ROW_B,
   CCAKE_ROW_P11, CCAKE_ROW_P12, CCAKE_ROW_P13, CCAKE_ROW_P22, CCAKE_ROW_P23, CCAKE_ROW_P33,
+  CCAKE_ROW_JB1, CCAKE_ROW_JB2, CCAKE_ROW_JB3, CCAKE_ROW_JS1, CCAKE_ROW_JS2, CCAKE_ROW_JS3,
+  CCAKE_ROW_JQ1, CCAKE_ROW_JQ2, CCAKE_ROW_JQ3,
   CCAKE_NROW
 };
 
@@ -107,7 +111,15 @@ typedef struct ccake_server ccake_server;
  *   tauPi_ratio    tau_Pi = tauPi_ratio * tau_pi
  *   c_PiPi,c_Pipi  first-order DNMR-type bulk couplings / tau_Pi (minimal IS: 1, 0)
  *   c_pipi,c_piPi  first-order DNMR-type shear couplings / tau_pi (minimal IS: 4/3, 0)
- *   skin           cell edge = 2h + skin; must exceed 2 dt max(1, 1/x0)          */
+ *   skin           cell edge = 2h + skin; must exceed 2 dt max(1, 1/x0)
+ *   diffusion      0 off; 1 BSQ charge diffusion ("BSQ diffusion", eq. min_dif_rel,
+ *                  needs ncharge 3): J^mu_q relaxes towards +kappa_{qq'} nabla^mu
+ *                  alpha_{q'} (alpha = mu/T, nabla^i alpha = g^{ii} d_i alpha) over
+ *                  tau_J; the charges move by the n = -1 SPH divergence of
+ *                  J - v J^0 and the entropy by -mu_q/T per unit charge moved
+ *   kappa_T2       kappa_{qq'}/T^2, row-major (B, S, Q), constant
+ *   tauJ_coeff     tau_J = tauJ_coeff / T (the paper's example: 0.2)
+ *   c_JJ           coefficient of the -c_JJ tau_J J^mu theta term (0 by default) */
 typedef struct ccake_config {
   int32_t dim, coords, viscous, precision, ncharge, density_mode;
   double h;
@@ -116,6 +128,9 @@ typedef struct ccake_config {
   double taupi_coeff, tauPi_ratio;
   double c_PiPi, c_Pipi, c_pipi, c_piPi;
   double skin;
+  int32_t diffusion, pad0;
+  double kappa_T2[9];
+  double tauJ_coeff, c_JJ;
 } ccake_config;
 
 /* Per-event counters of the last evaluation (ccake_totals). */

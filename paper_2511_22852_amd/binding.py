@@ -22,10 +22,13 @@ CARTESIAN, HYPERBOLIC = 0, 1
 FP64, MIXED = 0, 1
 DENS_SMOOTHED, DENS_SPECIFIC = 0, 1
 INIT_S, INIT_E = 0, 1
-NROW = 17
+NROW = 26
 NAUX = 33
 (ROW_X1, ROW_X2, ROW_X3, ROW_U1, ROW_U2, ROW_U3, ROW_S, ROW_NB, ROW_NS, ROW_NQ, ROW_B,
- ROW_P11, ROW_P12, ROW_P13, ROW_P22, ROW_P23, ROW_P33) = range(NROW)
+ ROW_P11, ROW_P12, ROW_P13, ROW_P22, ROW_P23, ROW_P33,
+ ROW_JB1, ROW_JB2, ROW_JB3, ROW_JS1, ROW_JS2, ROW_JS3, ROW_JQ1, ROW_JQ2, ROW_JQ3) = range(NROW)
+# kappa_{qq'}/T^2 of the paper's full BSQ diffusion matrix (rows and columns B, S, Q)
+KAPPA_T2_BSQ = ((0.0482, -0.0482, 0.0), (-0.0482, 0.1447, 0.0147), (0.0, 0.0147, 0.0880))
 (AUX_SIGSTAR, AUX_S, AUX_NB, AUX_NS, AUX_NQ, AUX_T, AUX_MUB, AUX_MUS, AUX_MUQ, AUX_P, AUX_E,
  AUX_CS2, AUX_INTABLE, AUX_GAMMA, AUX_THETA, AUX_NNB, AUX_F1, AUX_F2, AUX_F3, AUX_NEWTON,
  AUX_EOS_EVALS, AUX_KN_SHEAR, AUX_REINV_SHEAR, AUX_KN_BULK, AUX_REINV_BULK, AUX_DE0, AUX_DE1, AUX_DE2,
@@ -58,6 +61,8 @@ class Config(ctypes.Structure):
         ("taupi_coeff", ctypes.c_double), ("tauPi_ratio", ctypes.c_double),
         ("c_PiPi", ctypes.c_double), ("c_Pipi", ctypes.c_double), ("c_pipi", ctypes.c_double),
         ("c_piPi", ctypes.c_double), ("skin", ctypes.c_double),
+        ("diffusion", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("kappa_T2", ctypes.c_double * 9), ("tauJ_coeff", ctypes.c_double), ("c_JJ", ctypes.c_double),
     ]
 
 
@@ -179,8 +184,15 @@ def _ptr(a):
 
 def config(dim=2, hyperbolic=True, viscous=False, precision=FP64, ncharge=0, density_mode=DENS_SMOOTHED,
            h=0.3, eta_over_s=0.0, zeta_peak=0.0, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, taupi_coeff=5.0,
-           tauPi_ratio=1.0, c_PiPi=1.0, c_Pipi=0.0, c_pipi=4.0 / 3.0, c_piPi=0.0, skin=None) -> Config:
+           tauPi_ratio=1.0, c_PiPi=1.0, c_Pipi=0.0, c_pipi=4.0 / 3.0, c_piPi=0.0, skin=None,
+           diffusion=False, kappa_T2=KAPPA_T2_BSQ, tauJ_coeff=0.2, c_JJ=0.0) -> Config:
     c = Config()
+    c.diffusion = int(bool(diffusion))
+    kT = [float(v) for row in kappa_T2 for v in row]
+    assert len(kT) == 9
+    for i in range(9):
+        c.kappa_T2[i] = kT[i]
+    c.tauJ_coeff, c.c_JJ = tauJ_coeff, c_JJ
     c.dim, c.coords, c.viscous = dim, HYPERBOLIC if hyperbolic else CARTESIAN, int(viscous)
     c.precision, c.ncharge, c.density_mode = int(precision), ncharge, density_mode
     c.h, c.eta_over_s = h, eta_over_s

@@ -1,10 +1,11 @@
 // Shared device/host definitions of the CCAKE SPH library (gfx950).
 //
 // Layout conventions
-//   * particle state: 17 rows of FP64, row-major [row][capacity], particles of
+//   * particle state: 26 rows of FP64, row-major [row][capacity], particles of
 //     one event contiguous and, after binning, sorted by (cell, id);
 //   * rows: x^1..x^3, u^1..u^3, S = s/sigma, N_B, N_S, N_Q (= n_q/sigma),
-//     B = Pi/sigma, P^{ij} = pi^{ij}/sigma for ij = 11,12,13,22,23,33
+//     B = Pi/sigma, P^{ij} = pi^{ij}/sigma for ij = 11,12,13,22,23,33,
+//     V^k_q = J^k_q/sigma (charge diffusion currents, q = B,S,Q, k = 1..3)
 //     (the dynamical variables of the paper's SPH equations of motion);
 //   * the index 3 is eta (hyperbolic) or z (Cartesian); in 2+1D it is a
 //     symmetry direction (u^3 = 0, no particle coordinate).
@@ -16,7 +17,8 @@ namespace ccake {
 
 enum Row {
   R_X1, R_X2, R_X3, R_U1, R_U2, R_U3, R_S, R_NB, R_NS, R_NQ, R_B,
-  R_P11, R_P12, R_P13, R_P22, R_P23, R_P33, NROW
+  R_P11, R_P12, R_P13, R_P22, R_P23, R_P33,
+  R_JB1, R_JB2, R_JB3, R_JS1, R_JS2, R_JS3, R_JQ1, R_JQ2, R_JQ3, NROW
 };
 
 // auxiliary per-particle outputs of a right-hand-side evaluation (debug/parity)
@@ -38,6 +40,10 @@ enum Th {
 enum Rec { Q_PP, Q_A11, Q_A12, Q_A13, Q_A21, Q_A22, Q_A23, Q_A31, Q_A32, Q_A33,
            Q_U1, Q_U2, Q_U3, Q_V1, Q_V2, Q_V3, NREC };
 
+// neighbour record of the diffusion sums (FP64, written by pass 1):
+// alpha_q = mu_q/T and F^k_q/sigma*^2 with F = J - v J^0 (row QD_FB1 + 3q + k-1)
+enum DRec { QD_AB, QD_AS, QD_AQ, QD_FB1, QD_FB2, QD_FB3, QD_FS1, QD_FS2, QD_FS3, QD_FQ1, QD_FQ2, QD_FQ3, NDREC };
+
 // warm-start record of the EoS inversion (carried with the particle): the
 // last root of the analytic backup EoS and, when the table answered, the last
 // root of the table interpolant (W_TT = 0 when there is none)
@@ -46,9 +52,13 @@ enum Warm { W_GT, W_GMUB, W_GMUS, W_GMUQ, W_TT, W_TMUB, W_TMUS, W_TMUQ, NWARM };
 // density sums of a particle (lab frame, kernel normalisation applied) and its neighbour count
 enum DSum { DS_SIG, DS_S, DS_NB, DS_NS, DS_NQ, DS_NNB, NDSUM };
 
-// gradient sums of a particle: force F_i, d_k u^j (row-major k*3+j, divided by sigma*), div v
+// gradient sums of a particle: force F_i, d_k u^j (row-major k*3+j, divided by sigma*), div v,
+// d_i e (freeze-out), and with diffusion d_k alpha_q (row GS_DAB1 + 3q + k-1, divided by
+// sigma*) and the flux sums sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad W (GS_DJB + q)
 enum GSum { GS_F1, GS_F2, GS_F3, GS_DU11, GS_DU12, GS_DU13, GS_DU21, GS_DU22, GS_DU23, GS_DU31, GS_DU32,
-            GS_DU33, GS_DIVV, GS_DE1, GS_DE2, GS_DE3, NGSUM };
+            GS_DU33, GS_DIVV, GS_DE1, GS_DE2, GS_DE3,
+            GS_DAB1, GS_DAB2, GS_DAB3, GS_DAS1, GS_DAS2, GS_DAS3, GS_DAQ1, GS_DAQ2, GS_DAQ3,
+            GS_DJB, GS_DJS, GS_DJQ, NGSUM };
 
 enum EosKind { EOS_CONFORMAL = 0, EOS_TABLE = 1, EOS_GAS = 2 };
 
@@ -107,6 +117,10 @@ struct Params {
   double eta_over_s, zeta_peak, zeta_Tpeak, zeta_width;
   double taupi_coeff, tauPi_ratio;
   double c_PiPi, c_Pipi, c_pipi, c_piPi;
+  int32_t diffusion, pad_d;
+  double kappa_T2[9]; // kappa_{qq'}/T^2, row-major (diffusion)
+  double tauJ_coeff;  // tau_J = tauJ_coeff / T
+  double c_JJ;        // coefficient of -tau_J J theta
   double cell_edge;   // >= 2h + skin
   const SourceSet* src = nullptr;  // external sources (device), or none
 };
@@ -165,6 +179,7 @@ struct BatchDev {
   double* th;        // [NTH][cap]
   double* rec;       // [NREC][cap] fp64 neighbour records
   float* recf;       // [NREC][cap] fp32 neighbour records (mixed precision)
+  double* drec;      // [NDREC][cap] fp64 neighbour records of the diffusion sums
   double* warm;      // home warm start [NWARM][cap]
   double* warms;     // sorted warm start [NWARM][cap]
   double* dsum;      // [NDSUM][cap] density sums (sorted order)

@@ -254,4 +254,76 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
   }
 }
 
+// BSQ charge diffusion ("BSQ diffusion", eq. min_dif_rel, eq. charge_conservation,
+// eq. dsdnrewr), evaluated at the solved acceleration (the momentum rows do not
+// depend on the currents: Landau frame, and the pressure does not respond to
+// the charge moved).  V^k_q = J^k_q / sigma, J^0 = G_k u^k J^k / gamma:
+//   gamma sigma dV^i/dx0 = (kappa_{qq'} g^{ii} d_i alpha_{q'} - J^i) / tau_J
+//                          + (1 - c_JJ) J^i theta - u^i J^nu Du_nu
+//                          - Christoffel terms (eta: (gamma J^3 + u^3 J^0) / tau),
+//   dN_q/dx0 gains -d/dx0[(G_k u^k V^k) / gamma^2] - sqrt(-g) divF_q,
+// with divF_q = sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad W, F = J - v J^0
+// (the change of the particle's charge N + sqrt(-g) J^0/sigma* is the flux
+// through its boundary); kappa_{qq'} = kappa_T2 T^2, tau_J = tauJ_coeff / T.
+template <int D>
+__device__ inline void diffusion_rates(const Params& prm, const EomIn& in, const EomOut& o, const double V[3][3],
+                                       const double dal[3][3], const double divF[3], double dV[3][3],
+                                       double dNd[3]) {
+  const bool hyp = prm.hyperbolic != 0;
+  const double t = in.t;
+  const double G[4] = {0.0, 1.0, 1.0, hyp ? t * t : 1.0};
+  const double Gd[4] = {0.0, 0.0, 0.0, hyp ? 2.0 * t : 0.0};
+  const double g[4] = {1.0, -1.0, -1.0, -G[3]};
+  const double sqrtg = hyp ? t : 1.0;
+  const double it = hyp ? 1.0 / t : 0.0;
+  const double g033 = hyp ? t : 0.0;
+  const double gam = in.u[0];
+  const double u3 = D == 3 ? in.u[3] : 0.0;
+  const double* a = o.a;
+  const double dgam = (G[1] * in.u[1] * a[1] + G[2] * in.u[2] * a[2] + G[3] * u3 * a[3] + 0.5 * Gd[3] * u3 * u3) / gam;
+  double Dl[4];
+  Dl[0] = g[0] * (gam * dgam + g033 * u3 * u3);
+  Dl[1] = g[1] * (gam * a[1]);
+  Dl[2] = g[2] * (gam * a[2]);
+  Dl[3] = g[3] * (gam * a[3] + 2.0 * it * gam * u3);
+  const double T = in.T, T2 = T * T;
+  const double tauJ = prm.tauJ_coeff / T;
+  const double igs = 1.0 / (gam * in.sigma);
+  const double th = o.theta;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    double J[3], J0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      J[k] = k < D ? in.sigma * V[q][k] : 0.0;
+      J0 += G[1 + k] * in.u[1 + k] * J[k];
+    }
+    J0 /= gam;
+    double JDu = J0 * Dl[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) JDu += J[k] * Dl[1 + k];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (i >= D) {
+        dV[q][i] = 0.0;
+        continue;
+      }
+      double target = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) target += prm.kappa_T2[3 * q + r] * T2 * (1.0 / g[1 + i]) * dal[r][i];
+      double val = (target - J[i]) / tauJ + (1.0 - prm.c_JJ) * J[i] * th - in.u[1 + i] * JDu;
+      if (i == 2) val -= it * (gam * J[2] + u3 * J0);
+      dV[q][i] = val * igs;
+    }
+    double X = 0.0, dX = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      X += G[1 + k] * in.u[1 + k] * V[q][k];
+      dX += (Gd[1 + k] * in.u[1 + k] + G[1 + k] * a[1 + k]) * V[q][k] + G[1 + k] * in.u[1 + k] * dV[q][k];
+    }
+    const double dY = dX / (gam * gam) - 2.0 * X * dgam / (gam * gam * gam);
+    dNd[q] = -dY - sqrtg * divF[q];
+  }
+}
+
 }  // namespace ccake

@@ -128,10 +128,19 @@ __global__ void __launch_bounds__(256) k_totals(BatchDev b, Params prm, double* 
       const int64_t j = E.p_base + jj;
       const double* Y = b.Ys;
       acc[0] += row(Y, cap, R_S, j);
-      for (int q = 0; q < 3; ++q) acc[1 + q] += row(Y, cap, R_NB + q, j);
       double u[4] = {0.0, row(Y, cap, R_U1, j), row(Y, cap, R_U2, j), prm.dim == 3 ? row(Y, cap, R_U3, j) : 0.0};
       const double gam = sqrt(1.0 + u[1] * u[1] + u[2] * u[2] + G3 * u[3] * u[3]);
       u[0] = gam;
+      // charge of a particle: N_q, plus sqrt(-g) J^0_q / sigma* = (G_k u^k V^k_q) / gamma^2 with diffusion
+      for (int q = 0; q < 3; ++q) {
+        double Nq = row(Y, cap, R_NB + q, j);
+        if (prm.diffusion) {
+          double X = 0.0;
+          for (int k = 0; k < prm.dim; ++k) X += Gk[1 + k] * u[1 + k] * row(Y, cap, R_JB1 + 3 * q + k, j);
+          Nq += X / (gam * gam);
+        }
+        acc[1 + q] += Nq;
+      }
       const double ss = b.th[(int64_t)T_SIGSTAR * cap + j];
       const double sigma = ss / (gam * sqg);
       const double p = b.th[(int64_t)T_P * cap + j], w = b.th[(int64_t)T_E * cap + j] + p;

@@ -44,6 +44,14 @@ bool validate_config(const ccake_config* c, std::string* why) {
     if (!(c->eta_over_s > 0.0)) { *why = "viscous runs need eta_over_s > 0"; return false; }
     if (!(c->taupi_coeff > 0.0) || !(c->tauPi_ratio > 0.0)) { *why = "relaxation-time coefficients must be > 0"; return false; }
   }
+  if (c->diffusion != 0 && c->diffusion != 1) { *why = "diffusion must be 0 or 1"; return false; }
+  if (c->diffusion) {
+    if (c->ncharge != 3) { *why = "diffusion needs ncharge 3"; return false; }
+    if (!(c->tauJ_coeff > 0.0) || !std::isfinite(c->tauJ_coeff)) { *why = "tauJ_coeff must be > 0"; return false; }
+    if (!std::isfinite(c->c_JJ)) { *why = "c_JJ must be finite"; return false; }
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(c->kappa_T2[i])) { *why = "kappa_T2 must be finite"; return false; }
+  }
   return true;
 }
 
@@ -66,6 +74,11 @@ Params to_params(const ccake_config& c) {
   p.c_Pipi = c.c_Pipi;
   p.c_pipi = c.c_pipi;
   p.c_piPi = c.c_piPi;
+  p.diffusion = c.diffusion ? 1 : 0;
+  p.pad_d = 0;
+  for (int i = 0; i < 9; ++i) p.kappa_T2[i] = c.diffusion ? c.kappa_T2[i] : 0.0;
+  p.tauJ_coeff = c.diffusion ? c.tauJ_coeff : 1.0;
+  p.c_JJ = c.diffusion ? c.c_JJ : 0.0;
   p.cell_edge = 2.0 * c.h + c.skin;
   return p;
 }
@@ -81,6 +94,9 @@ uint32_t live_rows(const Params& p) {
     m |= (1u << R_P11) | (1u << R_P12) | (1u << R_P22) | (1u << R_P33);
     if (p.dim == 3) m |= (1u << R_P13) | (1u << R_P23);
   }
+  if (p.diffusion)
+    for (int q = 0; q < 3; ++q)
+      for (int k = 0; k < p.dim; ++k) m |= 1u << (R_JB1 + 3 * q + k);
   return m;
 }
 
@@ -105,6 +121,7 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.th = take(&o, D8 * NTH * cap);
   L.rec = take(&o, D8 * NREC * cap);
   L.recf = take(&o, sizeof(float) * NREC * cap);
+  L.drec = take(&o, D8 * NDREC * cap);
   L.warm = take(&o, D8 * NWARM * cap);
   L.warms = take(&o, D8 * NWARM * cap);
   L.dsum = take(&o, D8 * NDSUM * cap);
@@ -134,6 +151,7 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.th = (double*)(base + L.th);
   b.rec = (double*)(base + L.rec);
   b.recf = (float*)(base + L.recf);
+  b.drec = (double*)(base + L.drec);
   b.warm = (double*)(base + L.warm);
   b.warms = (double*)(base + L.warms);
   b.dsum = (double*)(base + L.dsum);

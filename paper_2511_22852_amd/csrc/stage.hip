@@ -254,6 +254,25 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
     else
       b.rec[(int64_t)r * cap + j] = rec[r];
   }
+  // record of the diffusion sums (FP64 in both precisions): alpha_q = mu_q/T and
+  // F^k_q / sigma*^2 with F = J - v J^0, J^k = sigma V^k, J^0 = G_k u^k J^k / gamma
+  if (NQ && prm.diffusion) {
+    const double Gq[4] = {0.0, 1.0, 1.0, G3};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double J[3], J0 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        J[k] = k < D ? sigma * row(Y, cap, R_JB1 + 3 * q + k, j) : 0.0;
+        J0 += Gq[1 + k] * u[1 + k] * J[k];
+      }
+      J0 /= gam;
+      b.drec[(int64_t)(QD_AB + q) * cap + j] = th.mu[q] / th.T;
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+        b.drec[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] = (J[k] - (u[1 + k] / gam) * J0) * is2;
+    }
+  }
   if (aux) {
     const int64_t ii = b.ids[j];
     const int64_t n = E.n;
@@ -387,6 +406,109 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   }
   A.template reduce<L>();
   if (lane == 0) write_grad<D, VISC, MIXED>(b, prm, j, A);
+}
+
+// Pair sums of the BSQ diffusion ("BSQ diffusion"; "Derivatives in
+// relativistic SPH"), FP64 in both precisions, a team of L lanes per particle
+// as in the gradient pass:
+//   d_k alpha_q = (1/sigma*_a) sum_b (alpha_b - alpha_a) d_k W_ab        (n = 1)
+//   divF_q      = sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad_a W_ab   (n = -1)
+// with F = J - v J^0, so the flux from a to b is minus the flux from b to a.
+template <int D>
+__global__ void __launch_bounds__(256) k_diff(BatchDev b, Params prm, const double* __restrict__ Y, int64_t nslots) {
+  constexpr int L = Team<D>::L;
+  constexpr int ROWS = RowBlock<D>::ROWS;
+  __shared__ int32_t s_lo[Team<D>::PER_BLOCK][ROWS], s_hi[Team<D>::PER_BLOCK][ROWS];
+  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t j = tid / L;
+  const int lane = (int)(tid % L);
+  if (j >= nslots) return;
+  const int e = b.ev[j];
+  if (e < 0) return;
+  const EventDev& E = b.evt[e];
+  const int64_t cap = b.cap;
+  const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
+  const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
+  const double* dr = b.drec;
+  double al[3], Fa[3][3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    al[q] = dr[(int64_t)(QD_AB + q) * cap + j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Fa[q][k] = k < D ? dr[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] : 0.0;
+  }
+  double da[3][3], dj[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    dj[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) da[q][k] = 0.0;
+  }
+  const int team = (int)threadIdx.x / L;
+  team_rows<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+  RowCursor<L, ROWS> cur;
+  cur.start(s_lo[team], s_hi[team], lane);
+  const int32_t self = (int32_t)j;
+  for (;;) {
+    int32_t k[PAIR_U];
+    bool v[PAIR_U];
+    take(cur, self, k, v);
+    if (!v[0]) break;
+    double xb[PAIR_U][3], d2[PAIR_U];
+    bool ok[PAIR_U];
+#pragma unroll
+    for (int u = 0; u < PAIR_U; ++u) {
+      xb[u][0] = row(Y, cap, R_X1, k[u]);
+      xb[u][1] = row(Y, cap, R_X2, k[u]);
+      xb[u][2] = D == 3 ? row(Y, cap, R_X3, k[u]) : 0.0;
+      d2[u] = dist2<D>(xa, xb[u]);
+      ok[u] = v[u] && d2[u] < r2max && d2[u] > 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PAIR_U; ++u) {
+      const int32_t m = ok[u] ? k[u] : self;
+      double ab[3], Fb[3][3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        ab[q] = dr[(int64_t)(QD_AB + q) * cap + m];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) Fb[q][kk] = kk < D ? dr[(int64_t)(QD_FB1 + 3 * q + kk) * cap + m] : 0.0;
+      }
+      if (ok[u]) {
+        const double r = sqrt(d2[u]);
+        const double f = spline_dw(r * ih) / r;
+        double dW[3];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) dW[kk] = kk < D ? f * (xa[kk] - xb[u][kk]) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const double dal = ab[q] - al[q];
+#pragma unroll
+          for (int kk = 0; kk < D; ++kk) {
+            da[q][kk] += dal * dW[kk];
+            dj[q] += (Fa[q][kk] + Fb[q][kk]) * dW[kk];
+          }
+        }
+      }
+    }
+    if (!v[PAIR_U - 1]) break;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    dj[q] = team_sum<L>(dj[q]);
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk) da[q][kk] = team_sum<L>(da[q][kk]);
+  }
+  if (lane == 0) {
+    const double fsd = sigma_d<D>(h) / h;
+    const double isg = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      b.gsum[(int64_t)(GS_DJB + q) * cap + j] = dj[q] * fsd;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) b.gsum[(int64_t)(GS_DAB1 + 3 * q + kk) * cap + j] = kk < D ? da[q][kk] * isg : 0.0;
+    }
+  }
 }
 
 // Spatial gradient of the energy density for the freeze-out surface
@@ -550,6 +672,20 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
   }
   EomOut o;
   eom_solve<D, VISC>(prm, in, o);
+  double dV[3][3], dNd[3] = {0.0, 0.0, 0.0};
+  if (prm.diffusion) {
+    double V[3][3], dal[3][3], dF[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dF[q] = b.gsum[(int64_t)(GS_DJB + q) * cap + j];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        V[q][k] = k < D ? row(Y, cap, R_JB1 + 3 * q + k, j) : 0.0;
+        dal[q][k] = k < D ? b.gsum[(int64_t)(GS_DAB1 + 3 * q + k) * cap + j] : 0.0;
+      }
+    }
+    diffusion_rates<D>(prm, in, o, V, dal, dF, dV, dNd);
+  }
 
   double f[NROW];
 #pragma unroll
@@ -562,6 +698,16 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
   f[R_S] = o.dS;
 #pragma unroll
   for (int q = 0; q < 3; ++q) f[R_NB + q] = q < prm.ncharge ? o.dN[q] : 0.0;
+  if (prm.diffusion) {
+    // the charge moved by diffusion, and the entropy it carries (R^S = -mu/T)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      f[R_NB + q] += dNd[q];
+      f[R_S] -= T_[(int64_t)(T_MUB + q) * cap + j] * dNd[q] / in.T;
+#pragma unroll
+      for (int k = 0; k < D; ++k) f[R_JB1 + 3 * q + k] = dV[q][k];
+    }
+  }
   if (VISC) {
     f[R_B] = o.dB;
     f[R_P11] = o.dP[1][1];
@@ -649,7 +795,8 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
     const bool live = (r <= R_X1 + D - 1) || (r >= R_U1 && r <= R_U1 + D - 1) || r == R_S ||
                       (r >= R_NB && r < R_NB + prm.ncharge) ||
                       (VISC && (r == R_B || r == R_P11 || r == R_P12 || r == R_P22 || r == R_P33 ||
-                                (D == 3 && (r == R_P13 || r == R_P23))));
+                                (D == 3 && (r == R_P13 || r == R_P23)))) ||
+                      (prm.diffusion && r >= R_JB1 && ((r - R_JB1) % 3) < D);
     if (!live) continue;
     double val;
     if (mode == 0) {
@@ -696,6 +843,7 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
   if (mk) (void)hipEventRecord(mk[2], s);
   if (!rates) return;
   hipLaunchKernelGGL((k_grad<D, VISC, MIXED>), dim3(gt), dim3(256), 0, s, b, prm, Y, stage, nslots);
+  if (prm.diffusion) hipLaunchKernelGGL((k_diff<D>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
   if (aux) hipLaunchKernelGGL((k_fo_grad<D>), dim3(gp), dim3(128), 0, s, b, prm, Y, nslots);
   if (mk) (void)hipEventRecord(mk[3], s);
   hipLaunchKernelGGL((k_eom<D, VISC>), dim3(gp), dim3(128), 0, s, b, prm, Y, stage, mode, nslots, fout, aux);

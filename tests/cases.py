@@ -19,10 +19,15 @@ def table(size="small"):
 
 
 def make(O, B, *, dim=2, hyperbolic=True, viscous=False, ncharge=0, h=0.3, eos="conformal",
-         density_mode=0, precision=0, table_size="small", coeffs=None, skin=None, sources=None):
+         density_mode=0, precision=0, table_size="small", coeffs=None, skin=None, sources=None,
+         diffusion=None):
+    """diffusion: None (off) or a dict of kappa_T2, tauJ_coeff, c_JJ (empty
+    dict: the defaults of both sides)."""
     tr = dict(TRANSPORT) if viscous else {}
     if coeffs:
         tr.update(coeffs)
+    if diffusion is not None:
+        tr.update(dict(diffusion=True, **diffusion))
     prm = O.params(dim=dim, hyperbolic=hyperbolic, viscous=viscous, ncharge=ncharge, h=h, use_cells=1,
                    density_mode=density_mode, source_specs=sources, **tr)
     cfg = B.config(dim=dim, hyperbolic=hyperbolic, viscous=viscous, precision=precision, ncharge=ncharge,
