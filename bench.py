@@ -178,10 +178,11 @@ def algorithmic_model(dim, viscous, ncharge, mixed, smoothed=True):
     }
 
 
-def run_gpu(B, I, w, eos, precision, steps, warmup):
+def run_gpu(B, I, w, eos, precision, steps, warmup, diffusion=False):
     import torch
     cfg = B.config(dim=2, hyperbolic=True, viscous=True, precision=precision, ncharge=3, h=w.h,
-                   eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02)
+                   eta_over_s=0.08, zeta_peak=0.02, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02,
+                   diffusion=diffusion)
     sim = B.Sim(cfg, eos, w.n)
     sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
     if warmup:
@@ -376,6 +377,7 @@ def main():
     ap.add_argument("--steps-3d", type=int, default=10,
                     help="timed steps of each 3+1D configuration (0 = skip them)")
     ap.add_argument("--no-offline", action="store_true", help="skip the offline-inverter run of the event")
+    ap.add_argument("--no-diffusion", action="store_true", help="skip the BSQ-diffusion run of the event")
     ap.add_argument("--only-3d", action="store_true",
                     help="only time the 1.2 M-particle 3+1D event in mixed precision (profiling runs)")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both",
@@ -509,6 +511,21 @@ def main():
         print(f"[bench] offline EoS: {out['offline_eos_mixed']['ms_per_step']:.4f} ms/step", file=sys.stderr,
               flush=True)
         eos_off.close()
+    if not args.no_diffusion:
+        # the same event with BSQ charge diffusion (the paper's full kappa/T^2
+        # matrix, tau_J = 0.2/T): currents in the state, their pair sums and
+        # relaxation in every stage
+        try:
+            r = run_gpu(B, I, w, eos, B.MIXED, args.steps, args.warmup, diffusion=True)
+            out["bsq_diffusion_mixed"] = {
+                "value": w.n * args.steps / r["elapsed"], "ms_per_step": r["elapsed"] / args.steps * 1e3,
+                "kernel_ms_per_step": [m / args.steps for m in r["ms"]],
+                "kappa_over_T2": "paper's full BSQ matrix", "tauJ": "0.2/T",
+            }
+            print(f"[bench] BSQ diffusion: {out['bsq_diffusion_mixed']['ms_per_step']:.4f} ms/step", file=sys.stderr,
+                  flush=True)
+        except B.CcakeError as err:
+            out["bsq_diffusion_mixed"] = {"error": str(err)}
     if args.steps_3d > 0:
         w2 = I.lumpy_3d_workload()
         other = {}

@@ -57,9 +57,10 @@ def eos_offline(B):
     return e.build_inverted(3, -2, 3, 18, nx=(11, 7, 9), x_lo=(0.0, -0.03, -0.02), x_hi=(0.1, 0.03, 0.06))
 
 
-@pytest.mark.parametrize("precision,inverter", [(0, "online"), (1, "online"), (1, "offline")])
+@pytest.mark.parametrize("precision,inverter", [(0, "online"), (1, "online"), (1, "offline"), (1, "diffusion")])
 def test_alone_equals_in_mix(B, eos, eos_offline, precision, inverter):
-    cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=0.24, precision=precision, **TR)
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=0.24, precision=precision,
+                   diffusion=inverter == "diffusion", **TR)
     eos = eos_offline if inverter == "offline" else eos
     evs = events(8)
     steps = [10 + 3 * i for i in range(len(evs))]
