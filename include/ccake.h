@@ -236,7 +236,7 @@ ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, const ccake_
 ccake_status ccake_init_particles(ccake_sim* sim, double t0, const double* xi, const double* u, int32_t dens_kind,
                                   const double* dens, int32_t mem);
 
-/* Raw state upload / download in the 17-row exchange format (checkpoint and
+/* Raw state upload / download in the CCAKE_NROW-row exchange format (checkpoint and
  * restore).  get_state synchronises.                                         */
 ccake_status ccake_set_state(ccake_sim* sim, double t, const double* y, int32_t mem);
 ccake_status ccake_get_state(ccake_sim* sim, double* y, int32_t mem);
@@ -293,7 +293,7 @@ ccake_status ccake_set_profiling(ccake_sim* sim, int32_t enable);
 ccake_status ccake_kernel_times(ccake_sim* sim, double ms[CCAKE_NPROF], int64_t launches[CCAKE_NPROF]);
 
 /* One evaluation of the right-hand side at the current state, without
- * stepping: rates f [17][n] and diagnostics aux [CCAKE_NAUX][n] (either may be
+ * stepping: rates f [CCAKE_NROW][n] and diagnostics aux [CCAKE_NAUX][n] (either may be
  * NULL), caller order.  Synchronises.                                        */
 ccake_status ccake_rhs(ccake_sim* sim, double* f, double* aux, int32_t mem);
 
@@ -301,7 +301,8 @@ ccake_status ccake_rhs(ccake_sim* sim, double* f, double* aux, int32_t mem);
 ccake_status ccake_read(ccake_sim* sim, int32_t field, double* out, int32_t mem);
 
 /* Totals at the current state: out[8] = (S, N_B, N_S, N_Q, E, M_1, M_2, M_3)
- * with E = sum sqrt(-g) T^00/sigma* and M_i = sum sqrt(-g) G_ii T^0i/sigma*
+ * with E = sum sqrt(-g) T^00/sigma* and M_i = sum sqrt(-g) G_ii T^0i/sigma*;
+ * with diffusion a particle's charge is N_q + sqrt(-g) J^0_q/sigma*
  * (conserved energy and momentum in Cartesian coordinates; "Exact
  * conservation").  cnt (optional) receives the counters.  Synchronises.     */
 ccake_status ccake_totals(ccake_sim* sim, double* out, ccake_counters* cnt);
@@ -339,7 +340,7 @@ typedef struct ccake_event_result {
   int32_t status;         /* ccake_status of the event */
   int32_t steps;
   double t_submit, t_admit, t_finish;  /* seconds on the server's clock */
-  double* state;          /* host [17][n], owned by the server until ccake_server_release */
+  double* state;          /* host [CCAKE_NROW][n], owned by the server until ccake_server_release */
   double totals[8];
 } ccake_event_result;
 
