@@ -1,10 +1,9 @@
-// Per-pair arithmetic of the SPH sums, shared by the kernels that read the
-// candidates from global memory (one team of lanes per particle, any batch)
-// and the kernels that stage a cell's neighbourhood in LDS first (single
-// events).  Both visit the same candidates in the same order per lane and
-// merge the lanes with the same butterfly.  Floating-point contraction is off
-// on the whole pair path and the fused multiply-adds are written out, so the
-// two give the same bits.
+// Per-pair arithmetic of the SPH sums of the pair kernels (one team of lanes
+// per particle, candidates read from global memory, any batch).  Every lane
+// visits its candidates in a fixed order and the lanes are merged with a
+// fixed butterfly, so results do not depend on the batch or the launch.
+// Floating-point contraction is off on the whole pair path and the fused
+// multiply-adds are written out.
 //
 //   density sums ("SPH interpretation of a fluid element"):
 //     sigma* = sum_b W_ab, s* = sum_b S_b W_ab, n*_q = sum_b N_q,b W_ab
@@ -13,8 +12,9 @@
 //              + G_i sum_b [A^{ji}_a/sigma*_a^2 + A^{ji}_b/sigma*_b^2] d_j W_ab   (n = -1)
 //     d_k u^j = (1/sigma*_a) sum_b (u^j_b - u^j_a) d_k W_ab                      (n = 1)
 //     div v   = (1/sigma*_a) sum_b (v_b - v_a) . grad W_ab
-// In the FP32 (mixed) form every sum is compensated (Kahan) and the kernel
-// uses the hardware square root; the pair test is FP64 in both forms.
+// In the FP32 (mixed) form every lane's sum is compensated (Kahan), the
+// lanes' partials are merged in FP64, and the kernel uses the hardware square
+// root; the pair test is FP64 in both forms.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -40,15 +40,11 @@ __device__ __forceinline__ int team_sum_i(int v) {
   return v;
 }
 
+// a lane's compensated FP32 partial, merged across the team in FP64 (one
+// FP64 add per butterfly level instead of a compensated FP32 merge)
 template <int L>
 __device__ __forceinline__ double team_sum_k(Kahan k) {
-#pragma unroll
-  for (int off = L / 2; off >= 1; off >>= 1) {
-    const float s2 = __shfl_xor(k.s, off, 64);
-    const float c2 = __shfl_xor(k.c, off, 64);
-    k.merge(s2, c2);
-  }
-  return k.value();
+  return team_sum<L>(k.value());
 }
 
 // ---------------------------------------------------------------------------
@@ -193,6 +189,82 @@ struct GradAcc {
 #pragma unroll
       for (int nu = 0; nu < D; ++nu) du[kk][nu] = MIXED ? team_sum_k<L>(kdu[kk][nu]) : team_sum<L>(du[kk][nu]);
     dv = MIXED ? team_sum_k<L>(kdv) : team_sum<L>(dv);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// BSQ diffusion sums ("BSQ diffusion"), FP64 in both precisions, formed in the
+// gradient pass from the same accepted pairs:
+//   d_k alpha_q = (1/sigma*_a) sum_b (alpha_b - alpha_a) d_k W_ab        (n = 1)
+//   divF_q      = sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad_a W_ab   (n = -1)
+// with alpha = mu/T and F = J - v J^0 (so the flux from a to b is minus the
+// flux from b to a).
+template <int D>
+struct DiffAcc {
+  double al[3], Fa[3][3];
+  double da[3][3], dj[3];
+
+  __device__ __forceinline__ void init(const double* __restrict__ dr, int64_t cap, int64_t j) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      al[q] = dr[(int64_t)(QD_AB + q) * cap + j];
+      dj[q] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        Fa[q][k] = k < D ? dr[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] : 0.0;
+        da[q][k] = 0.0;
+      }
+    }
+  }
+
+  // the neighbour's record: alpha_q and F^k_q / sigma*^2
+  __device__ __forceinline__ static void load(const double* __restrict__ dr, int64_t cap, int32_t m, double ab[3],
+                                              double Fb[3][3]) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      ab[q] = dr[(int64_t)(QD_AB + q) * cap + m];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Fb[q][k] = k < D ? dr[(int64_t)(QD_FB1 + 3 * q + k) * cap + m] : 0.0;
+    }
+  }
+
+  __device__ __forceinline__ void add(const double xa[3], const double xb[3], double d2, double ih, const double ab[3],
+                                      const double Fb[3][3]) {
+    if (!(d2 > 0.0)) return;  // self pair: grad W = 0
+    const double r = sqrt(d2);
+    const double f = spline_dw(r * ih) / r;
+    double dW[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dW[k] = k < D ? f * (xa[k] - xb[k]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double dal = ab[q] - al[q];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        da[q][k] += dal * dW[k];
+        dj[q] += (Fa[q][k] + Fb[q][k]) * dW[k];
+      }
+    }
+  }
+
+  template <int L>
+  __device__ __forceinline__ void reduce() {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      dj[q] = team_sum<L>(dj[q]);
+#pragma unroll
+      for (int k = 0; k < D; ++k) da[q][k] = team_sum<L>(da[q][k]);
+    }
+  }
+
+  // gradient sums rows: d_k alpha_q (kernel normalisation, 1/sigma*) and divF_q
+  __device__ __forceinline__ void write(double* gsum, int64_t cap, int64_t j, double fsd, double isg) const {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      gsum[(int64_t)(GS_DJB + q) * cap + j] = dj[q] * fsd;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gsum[(int64_t)(GS_DAB1 + 3 * q + k) * cap + j] = k < D ? da[q][k] * isg : 0.0;
+    }
   }
 };
 

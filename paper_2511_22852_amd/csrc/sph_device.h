@@ -79,15 +79,6 @@ struct Kahan {
     c = (t - s) - y;
     s = t;
   }
-  // merge another compensated sum (TwoSum of the heads, compensations added)
-  __device__ __forceinline__ void merge(float s2, float c2) {
-#pragma clang fp contract(off)
-    float t = s + s2;
-    float bp = t - s;
-    float err = (s - (t - bp)) + (s2 - bp);
-    c = c + c2 - err;
-    s = t;
-  }
   __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 

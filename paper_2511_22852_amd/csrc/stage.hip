@@ -8,7 +8,8 @@
 //              the neighbour record of pass 2
 //   k_grad     team of L lanes per particle: n = -1 force sums of p + Pi and
 //              of the viscous tensor, n = 1 sums of d_k u^j and div v
-//              ("Derivatives in relativistic SPH")
+//              ("Derivatives in relativistic SPH"); with BSQ diffusion also
+//              d_k (mu/T) and the n = -1 flux sums of the currents
 //   k_eom      one thread per particle: local M du/dx0 = F solve, relaxation
 //              rates, Heun update
 //
@@ -20,7 +21,7 @@
 // several loads in flight across row boundaries instead of one dependent
 // round trip per candidate.  Candidates of particles in the same cell
 // coincide, so the lanes of a wave read the same addresses.  In mixed precision the pair terms are formed and accumulated in
-// FP32 with Kahan compensation per lane and compensated merges across lanes;
+// FP32 with Kahan compensation per lane, and the lanes' partials are merged in FP64;
 // the pair test itself is always the exact FP64 one.
 #include <hip/hip_runtime.h>
 
@@ -348,7 +349,8 @@ __device__ __forceinline__ void write_grad(const BatchDev& b, const Params& prm,
   b.gsum[(int64_t)GS_DIVV * cap + j] = A.dv * isg;
 }
 
-template <int D, bool VISC, bool MIXED>
+// DIFF: also the BSQ diffusion sums (DiffAcc) over the same accepted pairs
+template <int D, bool VISC, bool MIXED, bool DIFF>
 __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
                                               int64_t nslots) {
   constexpr int L = Team<D>::L;
@@ -366,6 +368,8 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   const double r2max = (2.0 * prm.h) * (2.0 * prm.h);
   GradAcc<D, VISC, MIXED> A;
   grad_setup<D, VISC, MIXED>(b, prm, Y, E.t + stage * E.dt, j, A);
+  DiffAcc<D> DA;
+  if (DIFF) DA.init(b.drec, cap, j);
   const int team = (int)threadIdx.x / L;
   team_rows<D, L>(b, E, b.keys[j], A.xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
   RowCursor<L, ROWS> cur;
@@ -400,113 +404,22 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
           bA[q][i] = (VISC && q < D && i < D) ? rb[(int64_t)(Q_A11 + q * 3 + i) * cap + m] : RT(0);
       }
       const RT bpp = rb[(int64_t)Q_PP * cap + m];
-      if (ok[u]) A.add(xb[u], d2[u], bpp, bA, bU, bV);
+      double ab[3], Fb[3][3];
+      if (DIFF) DiffAcc<D>::load(b.drec, cap, m, ab, Fb);
+      if (ok[u]) {
+        A.add(xb[u], d2[u], bpp, bA, bU, bV);
+        if (DIFF) DA.add(A.xa, xb[u], d2[u], A.ih, ab, Fb);
+      }
     }
     if (!v[PAIR_U - 1]) break;
   }
   A.template reduce<L>();
-  if (lane == 0) write_grad<D, VISC, MIXED>(b, prm, j, A);
-}
-
-// Pair sums of the BSQ diffusion ("BSQ diffusion"; "Derivatives in
-// relativistic SPH"), FP64 in both precisions, a team of L lanes per particle
-// as in the gradient pass:
-//   d_k alpha_q = (1/sigma*_a) sum_b (alpha_b - alpha_a) d_k W_ab        (n = 1)
-//   divF_q      = sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad_a W_ab   (n = -1)
-// with F = J - v J^0, so the flux from a to b is minus the flux from b to a.
-template <int D>
-__global__ void __launch_bounds__(256) k_diff(BatchDev b, Params prm, const double* __restrict__ Y, int64_t nslots) {
-  constexpr int L = Team<D>::L;
-  constexpr int ROWS = RowBlock<D>::ROWS;
-  __shared__ int32_t s_lo[Team<D>::PER_BLOCK][ROWS], s_hi[Team<D>::PER_BLOCK][ROWS];
-  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t j = tid / L;
-  const int lane = (int)(tid % L);
-  if (j >= nslots) return;
-  const int e = b.ev[j];
-  if (e < 0) return;
-  const EventDev& E = b.evt[e];
-  const int64_t cap = b.cap;
-  const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
-  const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
-  const double* dr = b.drec;
-  double al[3], Fa[3][3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    al[q] = dr[(int64_t)(QD_AB + q) * cap + j];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) Fa[q][k] = k < D ? dr[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] : 0.0;
-  }
-  double da[3][3], dj[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    dj[q] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) da[q][k] = 0.0;
-  }
-  const int team = (int)threadIdx.x / L;
-  team_rows<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
-  RowCursor<L, ROWS> cur;
-  cur.start(s_lo[team], s_hi[team], lane);
-  const int32_t self = (int32_t)j;
-  for (;;) {
-    int32_t k[PAIR_U];
-    bool v[PAIR_U];
-    take(cur, self, k, v);
-    if (!v[0]) break;
-    double xb[PAIR_U][3], d2[PAIR_U];
-    bool ok[PAIR_U];
-#pragma unroll
-    for (int u = 0; u < PAIR_U; ++u) {
-      xb[u][0] = row(Y, cap, R_X1, k[u]);
-      xb[u][1] = row(Y, cap, R_X2, k[u]);
-      xb[u][2] = D == 3 ? row(Y, cap, R_X3, k[u]) : 0.0;
-      d2[u] = dist2<D>(xa, xb[u]);
-      ok[u] = v[u] && d2[u] < r2max && d2[u] > 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < PAIR_U; ++u) {
-      const int32_t m = ok[u] ? k[u] : self;
-      double ab[3], Fb[3][3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        ab[q] = dr[(int64_t)(QD_AB + q) * cap + m];
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) Fb[q][kk] = kk < D ? dr[(int64_t)(QD_FB1 + 3 * q + kk) * cap + m] : 0.0;
-      }
-      if (ok[u]) {
-        const double r = sqrt(d2[u]);
-        const double f = spline_dw(r * ih) / r;
-        double dW[3];
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) dW[kk] = kk < D ? f * (xa[kk] - xb[u][kk]) : 0.0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const double dal = ab[q] - al[q];
-#pragma unroll
-          for (int kk = 0; kk < D; ++kk) {
-            da[q][kk] += dal * dW[kk];
-            dj[q] += (Fa[q][kk] + Fb[q][kk]) * dW[kk];
-          }
-        }
-      }
-    }
-    if (!v[PAIR_U - 1]) break;
-  }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    dj[q] = team_sum<L>(dj[q]);
-#pragma unroll
-    for (int kk = 0; kk < D; ++kk) da[q][kk] = team_sum<L>(da[q][kk]);
-  }
+  if (DIFF) DA.template reduce<L>();
   if (lane == 0) {
-    const double fsd = sigma_d<D>(h) / h;
-    const double isg = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      b.gsum[(int64_t)(GS_DJB + q) * cap + j] = dj[q] * fsd;
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) b.gsum[(int64_t)(GS_DAB1 + 3 * q + kk) * cap + j] = kk < D ? da[q][kk] * isg : 0.0;
+    write_grad<D, VISC, MIXED>(b, prm, j, A);
+    if (DIFF) {
+      const double fsd = sigma_d<D>(prm.h) / prm.h;
+      DA.write(b.gsum, cap, j, fsd, fsd / b.th[(int64_t)T_SIGSTAR * cap + j]);
     }
   }
 }
@@ -842,8 +755,10 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
     hipLaunchKernelGGL((k_eos<D, VISC, MIXED, 0>), dim3(gp), dim3(128), 0, s, b, prm, eos, Y, stage, nslots, aux);
   if (mk) (void)hipEventRecord(mk[2], s);
   if (!rates) return;
-  hipLaunchKernelGGL((k_grad<D, VISC, MIXED>), dim3(gt), dim3(256), 0, s, b, prm, Y, stage, nslots);
-  if (prm.diffusion) hipLaunchKernelGGL((k_diff<D>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
+  if (prm.diffusion)
+    hipLaunchKernelGGL((k_grad<D, VISC, MIXED, true>), dim3(gt), dim3(256), 0, s, b, prm, Y, stage, nslots);
+  else
+    hipLaunchKernelGGL((k_grad<D, VISC, MIXED, false>), dim3(gt), dim3(256), 0, s, b, prm, Y, stage, nslots);
   if (aux) hipLaunchKernelGGL((k_fo_grad<D>), dim3(gp), dim3(128), 0, s, b, prm, Y, nslots);
   if (mk) (void)hipEventRecord(mk[3], s);
   hipLaunchKernelGGL((k_eom<D, VISC>), dim3(gp), dim3(128), 0, s, b, prm, Y, stage, mode, nslots, fout, aux);
