@@ -282,9 +282,11 @@ ccake_status ccake_set_sources(ccake_sim* sim, int32_t nsrc, const ccake_source*
 ccake_status ccake_check(ccake_sim* sim);
 
 /* Measurement support.  With profiling enabled, ccake_step launches its
- * kernels directly (no HIP graph) with HIP timing events recorded on the
- * simulation's stream around the binning kernels and around each kernel of
- * both Heun stages, and synchronises at the end of the call.  Enabling resets
+ * kernels directly (no HIP graph) on the simulation's stream, with HIP timing
+ * events recorded around the binning kernels and, for each kernel of both
+ * Heun stages, by the kernel's own dispatch (start and stop, so the gaps
+ * between launches are not counted), and synchronises at the end of the
+ * call.  Enabling resets
  * the accumulators.  ccake_kernel_times returns, per group (0 binning, 1
  * density sums, 2 EoS inversion, 3 gradient sums, 4 equations of motion and
  * update), the summed milliseconds and the number of launches.              */

@@ -529,7 +529,9 @@ extern "C" ccake_status ccake_time(const ccake_sim* s, double* t) {
   return CCAKE_OK;
 }
 
-static const int PROF_MARKS = 12;  // 2 around the binning, 5 around each stage's kernels
+// 2 around the binning, then per stage the start and stop events of its four
+// kernels (recorded by their dispatches)
+static const int PROF_MARKS = 18;
 
 // One Heun step.  With rebin, the particles are binned and gathered into cell
 // order first.  Without, the step runs on the home arrays, which the previous
@@ -576,10 +578,10 @@ static ccake_status collect_profile(ccake_sim* s, int nsteps) {
     s->prof_ms[0] += a;
     s->prof_n[0] += 1;
     for (int st = 0; st < 2; ++st) {
-      const hipEvent_t* q = m + 2 + 5 * st;
+      const hipEvent_t* q = m + 2 + 8 * st;
       for (int g = 0; g < 4; ++g) {
         float x = 0.f;
-        HIPCHK(s, hipEventElapsedTime(&x, q[g], q[g + 1]));
+        HIPCHK(s, hipEventElapsedTime(&x, q[2 * g], q[2 * g + 1]));
         s->prof_ms[1 + g] += x;
         s->prof_n[1 + g] += 1;
       }

@@ -23,6 +23,7 @@
 // coincide, so the lanes of a wave read the same addresses.  In mixed precision the pair terms are formed and accumulated in
 // FP32 with Kahan compensation per lane, and the lanes' partials are merged in FP64;
 // the pair test itself is always the exact FP64 one.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -735,34 +736,47 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
 // ---------------------------------------------------------------------------
 static inline unsigned nblocks(int64_t threads, int bs) { return (unsigned)((threads + bs - 1) / bs); }
 
+// A stage kernel launch.  With profiling events (ev = {start, stop}) the
+// dispatch itself records them, so a group's time is its kernel's execution
+// without the gaps between launches.
+#define CCAKE_STAGE_LAUNCH(EV, KERNEL, GRID, BLOCK, ...)                                  \
+  do {                                                                                    \
+    if (EV)                                                                               \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, s, (EV)[0], (EV)[1], 0, __VA_ARGS__); \
+    else                                                                                  \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, s, __VA_ARGS__);                         \
+  } while (0)
+
+// mk (profiling): 8 events, start and stop of the density, EoS, gradient and
+// update kernels
 template <int D, bool VISC, bool MIXED>
 static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, const double* Y,
                     int stage, int mode, double* fout, double* aux, bool rates, hipStream_t s,
                     const hipEvent_t* mk) {
   constexpr int L = Team<D>::L;
   const unsigned gt = nblocks(nslots * L, 256), gp = nblocks(nslots, 128);
-  if (mk) (void)hipEventRecord(mk[0], s);
+  const hipEvent_t* ed = mk ? mk + 0 : nullptr;
+  const hipEvent_t* ee = mk ? mk + 2 : nullptr;
+  const hipEvent_t* eg = mk ? mk + 4 : nullptr;
+  const hipEvent_t* em = mk ? mk + 6 : nullptr;
   if (prm.density_mode != 0)
-    hipLaunchKernelGGL((k_density<D, MIXED, 0>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 0>), dim3(gt), dim3(256), b, prm, Y, nslots);
   else if (prm.ncharge)
-    hipLaunchKernelGGL((k_density<D, MIXED, 4>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 4>), dim3(gt), dim3(256), b, prm, Y, nslots);
   else
-    hipLaunchKernelGGL((k_density<D, MIXED, 1>), dim3(gt), dim3(256), 0, s, b, prm, Y, nslots);
-  if (mk) (void)hipEventRecord(mk[1], s);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 1>), dim3(gt), dim3(256), b, prm, Y, nslots);
   if (prm.ncharge)
-    hipLaunchKernelGGL((k_eos<D, VISC, MIXED, 3>), dim3(gp), dim3(128), 0, s, b, prm, eos, Y, stage, nslots, aux);
+    CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 3>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux);
   else
-    hipLaunchKernelGGL((k_eos<D, VISC, MIXED, 0>), dim3(gp), dim3(128), 0, s, b, prm, eos, Y, stage, nslots, aux);
-  if (mk) (void)hipEventRecord(mk[2], s);
+    CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 0>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux);
   if (!rates) return;
   if (prm.diffusion)
-    hipLaunchKernelGGL((k_grad<D, VISC, MIXED, true>), dim3(gt), dim3(256), 0, s, b, prm, Y, stage, nslots);
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, true>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
   else
-    hipLaunchKernelGGL((k_grad<D, VISC, MIXED, false>), dim3(gt), dim3(256), 0, s, b, prm, Y, stage, nslots);
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, false>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
+  // diagnostic evaluations only (never profiled)
   if (aux) hipLaunchKernelGGL((k_fo_grad<D>), dim3(gp), dim3(128), 0, s, b, prm, Y, nslots);
-  if (mk) (void)hipEventRecord(mk[3], s);
-  hipLaunchKernelGGL((k_eom<D, VISC>), dim3(gp), dim3(128), 0, s, b, prm, Y, stage, mode, nslots, fout, aux);
-  if (mk) (void)hipEventRecord(mk[4], s);
+  CCAKE_STAGE_LAUNCH(em, (k_eom<D, VISC>), dim3(gp), dim3(128), b, prm, Y, stage, mode, nslots, fout, aux);
 }
 
 template <int D, bool VISC, bool MIXED>
@@ -770,7 +784,7 @@ static void passes_t(const BatchDev& b, const Params& prm, const EosDev& eos, in
                      double* fout, double* aux, hipStream_t s, const hipEvent_t* marks) {
   if (which == 0) {
     stage_t<D, VISC, MIXED>(b, prm, eos, nslots, b.Ys, 0, 0, nullptr, nullptr, true, s, marks);
-    stage_t<D, VISC, MIXED>(b, prm, eos, nslots, b.Y1, 1, 1, nullptr, nullptr, true, s, marks ? marks + 5 : nullptr);
+    stage_t<D, VISC, MIXED>(b, prm, eos, nslots, b.Y1, 1, 1, nullptr, nullptr, true, s, marks ? marks + 8 : nullptr);
   } else {
     stage_t<D, VISC, MIXED>(b, prm, eos, nslots, b.Ys, 0, 2, fout, aux, fout != nullptr, s, nullptr);
   }
