@@ -110,6 +110,10 @@ struct SourceSet {
 #define CCAKE_SUBCELLS 2
 #endif
 constexpr int SUBCELLS = CCAKE_SUBCELLS;
+// 2+1D: the first and last candidate slots of a particle's 2*SUBCELLS + 1
+// neighbour rows, found by the density pass and reused by the gradient pass
+// of the same stage
+constexpr int ROW_CACHE = 2 * (2 * SUBCELLS + 1);
 
 struct Params {
   int32_t dim, hyperbolic, viscous, ncharge, density_mode, mixed;
@@ -191,6 +195,7 @@ struct BatchDev {
   int32_t* keys;     // local cell key (sorted order)
   int32_t* perm;     // sorted slot -> home slot
   double* xbin;      // x^1 of each slot at its event's last binning (sorted order)
+  int32_t* rows;     // [ROW_CACHE][cap] 2+1D row bounds (lo, hi per row) of the current stage
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

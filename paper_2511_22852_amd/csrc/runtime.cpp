@@ -134,6 +134,7 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.keys = take(&o, I4 * cap);
   L.perm = take(&o, I4 * cap);
   L.xbin = take(&o, D8 * cap);
+  L.rows = take(&o, I4 * ROW_CACHE * cap);
   L.cs = take(&o, I4 * (ccap + 1));
   L.cf = take(&o, I4 * (ccap + 1));
   L.evt = take(&o, sizeof(EventDev) * nev);
@@ -163,6 +164,7 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.keys = (int32_t*)(base + L.keys);
   b.perm = (int32_t*)(base + L.perm);
   b.xbin = (double*)(base + L.xbin);
+  b.rows = (int32_t*)(base + L.rows);
   b.cell_start = (int32_t*)(base + L.cs);
   b.cell_fill = (int32_t*)(base + L.cf);
   b.evt = (EventDev*)(base + L.evt);

@@ -316,6 +316,33 @@ __device__ __forceinline__ void team_rows(const BatchDev& b, const EventDev& E, 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 2+1D row cache: the density pass stores the team's row bounds of particle
+// j (lane r writes row r), the gradient pass of the same stage reads them back
+// into its LDS rows instead of searching again (same positions, same cells).
+template <int D, int L>
+__device__ __forceinline__ void rows_store(const BatchDev& b, int64_t j, int lane, const int32_t* lo,
+                                           const int32_t* hi) {
+  static_assert(D == 2 && 2 * RowBlock<D>::ROWS == ROW_CACHE, "row cache is for 2+1D rows");
+  for (int r = lane; r < RowBlock<D>::ROWS; r += L) {
+    b.rows[(int64_t)(2 * r) * b.cap + j] = lo[r];
+    b.rows[(int64_t)(2 * r + 1) * b.cap + j] = hi[r];
+  }
+}
+
+template <int D, int L>
+__device__ __forceinline__ void rows_load(const BatchDev& b, int64_t j, int lane, int32_t* __restrict__ lo,
+                                          int32_t* __restrict__ hi) {
+  static_assert(D == 2 && 2 * RowBlock<D>::ROWS == ROW_CACHE, "row cache is for 2+1D rows");
+  for (int r = lane; r < RowBlock<D>::ROWS; r += L) {
+    lo[r] = b.rows[(int64_t)(2 * r) * b.cap + j];
+    hi[r] = b.rows[(int64_t)(2 * r + 1) * b.cap + j];
+  }
+  // the rows are read back by other lanes of the same wave
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Walk of one lane of a team over the concatenation of the team's rows: the
 // lane takes positions lane, lane + L, lane + 2L, ... of that sequence, so
 // that the L lanes together visit every candidate exactly once, each lane in

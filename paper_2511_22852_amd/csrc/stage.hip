@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
   const int team = (int)threadIdx.x / L;
   team_rows<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+  if constexpr (D == 2) rows_store<D, L>(b, j, lane, s_lo[team], s_hi[team]);
   RowCursor<L, ROWS> cur;
   cur.start(s_lo[team], s_hi[team], lane);
   DensAcc<MIXED, NS> A;
@@ -372,7 +373,11 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   DiffAcc<D> DA;
   if (DIFF) DA.init(b.drec, cap, j);
   const int team = (int)threadIdx.x / L;
-  team_rows<D, L>(b, E, b.keys[j], A.xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+  // 2+1D: the rows the density pass of this stage found for the same particle
+  if constexpr (D == 2)
+    rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
+  else
+    team_rows<D, L>(b, E, b.keys[j], A.xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
   RowCursor<L, ROWS> cur;
   cur.start(s_lo[team], s_hi[team], lane);
   const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
