@@ -97,6 +97,9 @@ __global__ void k_grid(BatchDev b, Params prm, int dim) {
   E->backup = 0;
   E->newton_iters = 0;
   if (!E->active || !E->rebin) return;
+  // a batch-wide serial per binning: row bounds cached per slot are valid
+  // while the slot's stamp equals its event's serial
+  E->bin_serial = atomicAdd(b.serial, 1u) + 1u;
   double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
   bool empty = false;
   for (int k = 0; k < dim; ++k) {

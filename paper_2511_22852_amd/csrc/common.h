@@ -149,6 +149,8 @@ struct EventDev {
   uint32_t newton_iters; // total Newton iterations (last stage)
   int32_t rebin;      // this step bins the event (else it keeps its cells and order)
   int32_t need_bin;   // the next step must bin (fresh state)
+  uint32_t bin_serial;// batch-wide serial of this event's last binning (0: none yet)
+  int32_t pad_bs;
   double disp;        // displacement bound sum(dt max(1, 1/x0)) since the last binning
   // bounding-box accumulators of the next binning: order-preserving integer
   // images of the coordinates (reset to the empty box after every use)
@@ -195,7 +197,9 @@ struct BatchDev {
   int32_t* keys;     // local cell key (sorted order)
   int32_t* perm;     // sorted slot -> home slot
   double* xbin;      // x^1 of each slot at its event's last binning (sorted order)
-  int32_t* rows;     // [ROW_CACHE][cap] 2+1D row bounds (lo, hi per row) of the current stage
+  int32_t* rows;     // [ROW_CACHE][cap] 2+1D row bounds (lo, hi per row), valid for one binning
+  uint32_t* rowstamp;// [cap] bin_serial of the binning the slot's rows belong to (~0: none)
+  uint32_t* serial;  // batch-wide binning counter
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

@@ -135,6 +135,8 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.perm = take(&o, I4 * cap);
   L.xbin = take(&o, D8 * cap);
   L.rows = take(&o, I4 * ROW_CACHE * cap);
+  L.rowstamp = take(&o, I4 * cap);
+  L.serial = take(&o, I4);
   L.cs = take(&o, I4 * (ccap + 1));
   L.cf = take(&o, I4 * (ccap + 1));
   L.evt = take(&o, sizeof(EventDev) * nev);
@@ -165,6 +167,8 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.perm = (int32_t*)(base + L.perm);
   b.xbin = (double*)(base + L.xbin);
   b.rows = (int32_t*)(base + L.rows);
+  b.rowstamp = (uint32_t*)(base + L.rowstamp);
+  b.serial = (uint32_t*)(base + L.serial);
   b.cell_start = (int32_t*)(base + L.cs);
   b.cell_fill = (int32_t*)(base + L.cf);
   b.evt = (EventDev*)(base + L.evt);
@@ -399,6 +403,9 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
   hipError_t he = hipMemcpy(s->b.ev, ev.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (ccap + 1));
   if (he == hipSuccess) he = hipMemset(s->base + L.src, 0, sizeof(SourceSet));
+  // no slot has rows of a binning yet; binnings are numbered from 1
+  if (he == hipSuccess) he = hipMemset(s->b.rowstamp, 0xFF, sizeof(uint32_t) * n);
+  if (he == hipSuccess) he = hipMemset(s->b.serial, 0, sizeof(uint32_t));
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) {
     ccake_destroy(s);

@@ -320,7 +320,7 @@ __device__ __forceinline__ void team_rows(const BatchDev& b, const EventDev& E, 
 // j (lane r writes row r), the gradient pass of the same stage reads them back
 // into its LDS rows instead of searching again (same positions, same cells).
 template <int D, int L>
-__device__ __forceinline__ void rows_store(const BatchDev& b, int64_t j, int lane, const int32_t* lo,
+__device__ __forceinline__ void rows_keep(const BatchDev& b, int64_t j, int lane, const int32_t* lo,
                                            const int32_t* hi) {
   static_assert(D == 2 && 2 * RowBlock<D>::ROWS == ROW_CACHE, "row cache is for 2+1D rows");
   for (int r = lane; r < RowBlock<D>::ROWS; r += L) {
