@@ -40,6 +40,28 @@ __device__ __forceinline__ int team_sum_i(int v) {
   return v;
 }
 
+// FP64 team sums through LDS: lane k of the team stores its NV partials at
+// buf[k * NV + v]; after a wavefront barrier (a team lies inside one wave)
+// lane v < NV adds value v of the L lanes in lane order and returns it (the
+// other lanes return 0).  One store and L loads and adds per lane instead of
+// log2(L) dependent cross-lane exchanges per value.
+template <int L, int NV>
+__device__ __forceinline__ double team_sums_lds(double* __restrict__ buf, int lane, const double (&v)[NV]) {
+#pragma clang fp contract(off)
+  static_assert(NV <= L, "one value per lane");
+#pragma unroll
+  for (int q = 0; q < NV; ++q) buf[lane * NV + q] = v[q];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double acc = 0.0;
+  if (lane < NV) {
+#pragma unroll
+    for (int k = 0; k < L; ++k) acc += buf[k * NV + lane];
+  }
+  return acc;
+}
+
 // a lane's compensated FP32 partial, merged across the team in FP64 (one
 // FP64 add per butterfly level instead of a compensated FP32 merge)
 template <int L>
@@ -83,6 +105,14 @@ struct DensAcc {
 #pragma unroll
       for (int q = 0; q < NS; ++q) sv[q] = fma(v[q], W, sv[q]);
     }
+  }
+
+  // this lane's partial sums (sigma*, S, N_B, N_S, N_Q) and candidate count
+  __device__ __forceinline__ void partials(double (&p)[6]) const {
+    p[0] = MIXED ? ks.value() : ss;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[1 + q] = q < NS ? (MIXED ? kv[q].value() : sv[q]) : 0.0;
+    p[5] = (double)nnb;
   }
 
   // team totals: sigma*, s*, n*_B, n*_S, n*_Q (without sigma_d), neighbours
@@ -178,6 +208,18 @@ struct GradAcc {
         dv = fma((double)bV[kk] - aV[kk], dW[kk], dv);
       }
     }
+  }
+
+  // this lane's partial sums: F_i, d_k u^j (row-major), div v
+  static constexpr int NP = D + D * D + 1;
+  __device__ __forceinline__ void partials(double (&p)[NP]) const {
+#pragma unroll
+    for (int i = 0; i < D; ++i) p[i] = MIXED ? kF[i].value() : F[i];
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+      for (int nu = 0; nu < D; ++nu) p[D + kk * D + nu] = MIXED ? kdu[kk][nu].value() : du[kk][nu];
+    p[NP - 1] = MIXED ? kdv.value() : dv;
   }
 
   template <int L>

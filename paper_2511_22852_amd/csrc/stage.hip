@@ -141,10 +141,19 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
     }
     if (!v[PAIR_U - 1]) break;
   }
-  double sums[5];
-  int nnb;
-  A.template reduce<L>(sums, &nnb);
-  if (lane == 0) write_density<D>(b, prm, j, sums, nnb);
+  if constexpr (D == 2) {
+    // lane v < 6 forms row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
+    __shared__ double s_red[Team<D>::PER_BLOCK][L * 6];
+    double part[6];
+    A.partials(part);
+    const double tot = team_sums_lds<L, 6>(s_red[team], lane, part);
+    if (lane < 6) b.dsum[(int64_t)(DS_SIG + lane) * b.cap + j] = lane == 5 ? tot : tot * sigma_d<D>(prm.h);
+  } else {
+    double sums[5];
+    int nnb;
+    A.template reduce<L>(sums, &nnb);
+    if (lane == 0) write_density<D>(b, prm, j, sums, nnb);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -431,10 +440,35 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
     }
     if (!v[PAIR_U - 1]) break;
   }
-  A.template reduce<L>();
+  if constexpr (D == 2) {
+    // lane v < 7 forms gradient sum v: F_1, F_2, d_k u^j (k, j = 1, 2), div v
+    constexpr int NP = GradAcc<D, VISC, MIXED>::NP;
+    __shared__ double s_red[Team<D>::PER_BLOCK][L * NP];
+    double part[NP];
+    A.partials(part);
+    const double tot = team_sums_lds<L, NP>(s_red[team], lane, part);
+    if (lane < NP) {
+      const double fsd = sigma_d<D>(prm.h) / prm.h;
+      int row;
+      double scale = fsd;
+      if (lane < D) {
+        row = GS_F1 + lane;
+      } else if (lane < NP - 1) {
+        const int kk = (lane - D) / D, nu = (lane - D) % D;
+        row = GS_DU11 + kk * 3 + nu;
+        scale = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
+      } else {
+        row = GS_DIVV;
+        scale = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
+      }
+      b.gsum[(int64_t)row * cap + j] = tot * scale;
+    }
+  } else {
+    A.template reduce<L>();
+  }
   if (DIFF) DA.template reduce<L>();
   if (lane == 0) {
-    write_grad<D, VISC, MIXED>(b, prm, j, A);
+    if constexpr (D != 2) write_grad<D, VISC, MIXED>(b, prm, j, A);
     if (DIFF) {
       const double fsd = sigma_d<D>(prm.h) / prm.h;
       DA.write(b.gsum, cap, j, fsd, fsd / b.th[(int64_t)T_SIGSTAR * cap + j]);
