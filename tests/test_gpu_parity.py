@@ -207,12 +207,18 @@ def test_lumpy_viscous_trajectory_fp64(B, O):
         assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))
 
 
+BENCH_SKIN_H = 0.25   # the benchmark's binning skin of this event, in units of h
+
+
 def test_full_size_lumpy_step(B, O):
     """The 40,000-particle viscous BSQ event (200 x 200 at 0.08 fm, h = 0.24)
-    in the launch configuration of the benchmark: one FP64 Heun step from the
-    initial condition, every particle compared."""
+    in the launch configuration of the benchmark (its skin, so its binning
+    schedule and cached neighbour rows): one FP64 Heun step from the initial
+    condition within 1e-12, then 11 more (three binning intervals) within
+    1e-9, every particle compared."""
     w = I.lumpy_2d_workload()
-    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", table_size="full", h=w.h)
+    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", table_size="full", h=w.h,
+                            skin=BENCH_SKIN_H * w.h)
     y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
     yo, aux_o, bad = O.heun_step(prm, oe, w.t0, w.dt, y)
     assert bad == 0
@@ -224,6 +230,31 @@ def test_full_size_lumpy_step(B, O):
     for r in range(O.NVAR):
         if np.abs(yo[r]).max() > 0:
             assert rel_inf(yg[r], yo[r]) <= 1e-12, (r, rel_inf(yg[r], yo[r]))
+    _, yo, _ = O.evolve(prm, oe, w.t0 + w.dt, w.dt, 11, yo)
+    sim.step(w.dt, 11)
+    sim.check()
+    yg = sim.get_state()
+    for r in range(O.NVAR):
+        if np.abs(yo[r]).max() > 0:
+            assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))
+
+
+def test_full_size_lumpy_mixed(B, O):
+    """The benchmark's own run of the event (mixed precision, its skin), 24
+    steps, against the FP64 oracle: relative L2 of e and n_B within 1e-4."""
+    w = I.lumpy_2d_workload()
+    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", table_size="full", h=w.h,
+                            skin=BENCH_SKIN_H * w.h, precision=B.MIXED)
+    y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    t, yo, _ = O.evolve(prm, oe, w.t0, w.dt, 24, y)
+    _, aux_o, _ = O.rhs(prm, oe, t, yo)
+    sim = B.Sim(cfg, ge, w.n)
+    sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    sim.step(w.dt, 24)
+    sim.check()
+    _, aux_g = sim.rhs()
+    assert rel_l2(aux_g[O.A_E], aux_o[O.A_E]) <= 1e-4
+    assert rel_l2(aux_g[O.A_NB], aux_o[O.A_NB]) <= 1e-4
 
 
 # -------------------------------------------------------- mixed precision ---
