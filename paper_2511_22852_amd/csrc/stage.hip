@@ -16,7 +16,7 @@
 // The neighbour loops give each of L consecutive lanes every L-th candidate
 // of the particle's trimmed cell rows and combine the partial sums with a
 // fixed butterfly of lane shuffles, so the result is deterministic.  Each lane
-// takes its candidates PAIR_U at a time: the positions of all PAIR_U are
+// takes its candidates U at a time (PairU): the positions of all U are
 // loaded together, then the operands of the accepted ones, so that a lane has
 // several loads in flight across row boundaries instead of one dependent
 // round trip per candidate.  Candidates of particles in the same cell
@@ -47,19 +47,26 @@ struct Team {
   static constexpr int L = D == 2 ? CCAKE_TEAM2 : CCAKE_TEAM3;
   static constexpr int PER_BLOCK = 256 / L;
 };
-// candidates per lane in flight in the pair loops
-#ifndef CCAKE_PAIR_U
-#define CCAKE_PAIR_U 2
+// candidates per lane in flight in the pair loops (2D, 3D; measured best:
+// the 3D loops are longer and issue-bound, so more loads in flight pay)
+#ifndef CCAKE_PAIR_U2
+#define CCAKE_PAIR_U2 2
 #endif
-constexpr int PAIR_U = CCAKE_PAIR_U;
+#ifndef CCAKE_PAIR_U3
+#define CCAKE_PAIR_U3 4
+#endif
+template <int D>
+struct PairU {
+  static constexpr int U = D == 2 ? CCAKE_PAIR_U2 : CCAKE_PAIR_U3;
+};
 
-// Takes this lane's next PAIR_U candidates from the cursor: slot k[u] and
+// Takes this lane's next U candidates from the cursor: slot k[u] and
 // whether it exists (v[u]); missing ones point at the lane's own particle,
 // so every load stays in bounds.
-template <class Cursor>
-__device__ __forceinline__ void take(Cursor& cur, int32_t self, int32_t k[PAIR_U], bool v[PAIR_U]) {
+template <int U, class Cursor>
+__device__ __forceinline__ void take(Cursor& cur, int32_t self, int32_t k[U], bool v[U]) {
 #pragma unroll
-  for (int u = 0; u < PAIR_U; ++u) {
+  for (int u = 0; u < U; ++u) {
     v[u] = cur.valid();
     k[u] = self;
     if (v[u]) k[u] = cur.next();
@@ -117,10 +124,11 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   DensAcc<MIXED, NS> A;
   A.init();
   const int32_t self = (int32_t)j;
+  constexpr int PAIR_U = PairU<D>::U;
   for (;;) {
     int32_t k[PAIR_U];
     bool v[PAIR_U];
-    take(cur, self, k, v);
+    take<PAIR_U>(cur, self, k, v);
     if (!v[0]) break;
     double d2[PAIR_U];
     bool ok[PAIR_U];
@@ -403,10 +411,11 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   cur.start(s_lo[team], s_hi[team], lane);
   const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
   const int32_t self = (int32_t)j;
+  constexpr int PAIR_U = PairU<D>::U;
   for (;;) {
     int32_t k[PAIR_U];
     bool v[PAIR_U];
-    take(cur, self, k, v);
+    take<PAIR_U>(cur, self, k, v);
     if (!v[0]) break;
     double xb[PAIR_U][3], d2[PAIR_U];
     bool ok[PAIR_U];
