@@ -447,29 +447,36 @@ def main():
     value64 = w.n * args.steps / res["fp64"]["elapsed"]
     model = algorithmic_model(2, True, 3, True)
 
-    # roofline of the dominant kernel of the headline (mixed) run
-    names = GROUPS
+    # roofline of each stage kernel of the headline (mixed) run; the
+    # dominant one (largest time) is the reported roofline
+    def kernel_roofline(k):
+        name = GROUPS[k]
+        avg_s = head["ms"][k] / head["launches"][k] / 1e3
+        nbytes = w.n * model[name]["bytes"]
+        flops = w.n * head["nnb"] * model[name]["pair_flops"]
+        t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+        t_alu = flops / (VALU_PEAK_TFLOPS * 1e12)
+        if t_hbm >= t_alu:
+            r = dict(bound="hbm", achieved=nbytes / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+        else:
+            r = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s")
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = measured_traffic(name)
+        r["kernel"] = name
+        r["avg_launch_us"] = avg_s * 1e6
+        r["algorithmic_bytes_per_launch"] = nbytes
+        r["algorithmic_flops_per_launch"] = flops
+        r["compensation_flops_per_launch"] = w.n * head["nnb"] * model[name]["comp_flops"]
+        # issued vector-ALU instructions (counters) against the issue rate
+        cs = counter_summary(name)
+        if cs and "valu_wave_instructions_per_dispatch" in cs:
+            r["valu_issue_frac"] = float(cs["valu_wave_instructions_per_dispatch"]) / (avg_s * VALU_ISSUE_PER_S)
+        return r
+
     k = max(range(1, len(GROUPS)), key=lambda i: head["ms"][i])
-    avg_s = head["ms"][k] / head["launches"][k] / 1e3
-    nbytes = w.n * model[names[k]]["bytes"]
-    flops = w.n * head["nnb"] * model[names[k]]["pair_flops"]
-    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
-    t_alu = flops / (VALU_PEAK_TFLOPS * 1e12)
-    if t_hbm >= t_alu:
-        roof = dict(bound="hbm", achieved=nbytes / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-    else:
-        roof = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(names[k])
-    roof["kernel"] = names[k]
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["algorithmic_bytes_per_launch"] = nbytes
-    roof["algorithmic_flops_per_launch"] = flops
-    roof["compensation_flops_per_launch"] = w.n * head["nnb"] * model[names[k]]["comp_flops"]
-    # issued vector-ALU instructions (counters) against the issue rate
-    cs = counter_summary(names[k])
-    if cs and "valu_wave_instructions_per_dispatch" in cs:
-        roof["valu_issue_frac"] = float(cs["valu_wave_instructions_per_dispatch"]) / (avg_s * VALU_ISSUE_PER_S)
+    roof = kernel_roofline(k)
+    roof_all = {GROUPS[i]: {key: v for key, v in kernel_roofline(i).items() if key != "kernel"}
+                for i in range(1, len(GROUPS))}
 
     out = {
         "metric": METRIC,
@@ -491,11 +498,12 @@ def main():
         "mixed_over_fp64": value / value64,
         "kernel_ms_per_step": {"mixed": [m / args.steps for m in head["ms"]],
                                "fp64": [m / args.steps for m in res["fp64"]["ms"]],
-                               "groups": names},
+                               "groups": GROUPS},
         # counters of the last step: both Heun stages invert every particle once
         "eos_backup_fraction_last_step": head["backup"] / (2 * w.n),
         "eos_mean_newton_iterations_last_step": head["newton_iters"] / (2 * w.n),
         "roofline": roof,
+        "roofline_by_kernel": roof_all,
     }
     if not args.no_offline:
         # the offline inverter (the paper's GPU path) on the same event: the
