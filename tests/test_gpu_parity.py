@@ -239,6 +239,36 @@ def test_full_size_lumpy_step(B, O):
             assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))
 
 
+def test_cached_rows_at_relativistic_speeds(B, O):
+    """The 2+1D neighbour rows are searched once per binning and kept until
+    the next one, valid because a binning is redone before twice the
+    displacement bound exceeds the skin.  Particles moving at up to 0.95 c in
+    random directions close pairs at nearly twice that rate, the tight case
+    of the bound: over three binning intervals (skin 0.25 h) the GPU state
+    must follow the oracle's (which searches all pairs at every stage)."""
+    side, dx, h = 30, 0.1, 0.3
+    xi = I.lattice((side, side), dx, -0.5 * dx * (side - 1))
+    n = xi.shape[1]
+    rng = np.random.default_rng(21)
+    speed = rng.uniform(0.8, 0.95, n)
+    phi = rng.uniform(0.0, 2 * np.pi, n)
+    gam = 1.0 / np.sqrt(1.0 - speed ** 2)
+    u = np.stack([gam * speed * np.cos(phi), gam * speed * np.sin(phi)])
+    dens = np.zeros((4, n))
+    dens[0] = 20.0 + 5.0 * rng.random(n)
+    prm, oe, cfg, ge = make(O, B, dim=2, hyperbolic=False, h=h, skin=0.25 * h)
+    y = O.init(prm, oe, 0.0, xi, u, 0, dens)
+    nsteps = 18
+    _, yo, _ = O.evolve(prm, oe, 0.0, 0.005, nsteps, y)
+    sim = B.Sim(cfg, ge, n)
+    sim.set_state(0.0, y)
+    sim.step(0.005, nsteps)
+    sim.check()
+    yg = sim.get_state()
+    for r in (O.V_X1, O.V_X2, O.V_U1, O.V_U2, O.V_S):
+        assert rel_inf(yg[r], yo[r]) <= 1e-9, (r, rel_inf(yg[r], yo[r]))
+
+
 def test_full_size_lumpy_mixed(B, O):
     """The benchmark's own run of the event (mixed precision, its skin), 24
     steps, against the FP64 oracle: relative L2 of e and n_B within 1e-4."""
