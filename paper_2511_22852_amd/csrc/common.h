@@ -110,10 +110,10 @@ struct SourceSet {
 #define CCAKE_SUBCELLS 2
 #endif
 constexpr int SUBCELLS = CCAKE_SUBCELLS;
-// 2+1D: the first and last candidate slots of a particle's 2*SUBCELLS + 1
-// neighbour rows, found by the density pass and reused by the gradient pass
-// of the same stage
-constexpr int ROW_CACHE = 2 * (2 * SUBCELLS + 1);
+// the first and last candidate slots of a particle's neighbour rows
+// ((2*SUBCELLS + 1) rows in 2+1D, (2*SUBCELLS + 1)^2 in 3+1D), searched at the
+// first density pass after a binning and reused until the next binning
+constexpr int ROW_CACHE = 2 * (2 * SUBCELLS + 1) * (2 * SUBCELLS + 1);
 
 struct Params {
   int32_t dim, hyperbolic, viscous, ncharge, density_mode, mixed;
@@ -197,7 +197,7 @@ struct BatchDev {
   int32_t* keys;     // local cell key (sorted order)
   int32_t* perm;     // sorted slot -> home slot
   double* xbin;      // x^1 of each slot at its event's last binning (sorted order)
-  int32_t* rows;     // [ROW_CACHE][cap] 2+1D row bounds (lo, hi per row), valid for one binning
+  int32_t* rows;     // [ROW_CACHE][cap] row bounds (lo, hi per row), valid for one binning
   uint32_t* rowstamp;// [cap] bin_serial of the binning the slot's rows belong to (~0: none)
   uint32_t* serial;  // batch-wide binning counter
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell

@@ -316,13 +316,13 @@ __device__ __forceinline__ void team_rows(const BatchDev& b, const EventDev& E, 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 2+1D row cache: the density pass stores the team's row bounds of particle
-// j (lane r writes row r), the gradient pass of the same stage reads them back
-// into its LDS rows instead of searching again (same positions, same cells).
+// Row cache: the density pass stores the team's row bounds of particle j
+// (lanes r, r + L, ... write rows r, r + L, ...); later passes read them back
+// into their LDS rows instead of searching again.
 template <int D, int L>
 __device__ __forceinline__ void rows_keep(const BatchDev& b, int64_t j, int lane, const int32_t* lo,
                                            const int32_t* hi) {
-  static_assert(D == 2 && 2 * RowBlock<D>::ROWS == ROW_CACHE, "row cache is for 2+1D rows");
+  static_assert(2 * RowBlock<D>::ROWS <= ROW_CACHE, "row cache too small");
   for (int r = lane; r < RowBlock<D>::ROWS; r += L) {
     b.rows[(int64_t)(2 * r) * b.cap + j] = lo[r];
     b.rows[(int64_t)(2 * r + 1) * b.cap + j] = hi[r];
@@ -332,7 +332,7 @@ __device__ __forceinline__ void rows_keep(const BatchDev& b, int64_t j, int lane
 template <int D, int L>
 __device__ __forceinline__ void rows_load(const BatchDev& b, int64_t j, int lane, int32_t* __restrict__ lo,
                                           int32_t* __restrict__ hi) {
-  static_assert(D == 2 && 2 * RowBlock<D>::ROWS == ROW_CACHE, "row cache is for 2+1D rows");
+  static_assert(2 * RowBlock<D>::ROWS <= ROW_CACHE, "row cache too small");
   for (int r = lane; r < RowBlock<D>::ROWS; r += L) {
     lo[r] = b.rows[(int64_t)(2 * r) * b.cap + j];
     hi[r] = b.rows[(int64_t)(2 * r + 1) * b.cap + j];

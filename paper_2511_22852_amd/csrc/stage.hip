@@ -105,19 +105,15 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
   const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
   const int team = (int)threadIdx.x / L;
-  if constexpr (D == 2) {
-    // rows found at the first pass after a binning, kept until the next
-    // binning: a pair within 2h now was within 2h + skin then, because the
-    // binning is redone before twice the displacement bound exceeds the skin
-    if (b.rowstamp[j] == E.bin_serial) {
-      rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
-    } else {
-      team_rows<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
-      rows_keep<D, L>(b, j, lane, s_lo[team], s_hi[team]);
-      if (lane == 0) b.rowstamp[j] = E.bin_serial;
-    }
+  // rows found at the first pass after a binning, kept until the next
+  // binning: a pair within 2h now was within 2h + skin then, because the
+  // binning is redone before twice the displacement bound exceeds the skin
+  if (b.rowstamp[j] == E.bin_serial) {
+    rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
   } else {
     team_rows<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+    rows_keep<D, L>(b, j, lane, s_lo[team], s_hi[team]);
+    if (lane == 0) b.rowstamp[j] = E.bin_serial;
   }
   RowCursor<L, ROWS> cur;
   cur.start(s_lo[team], s_hi[team], lane);
@@ -402,11 +398,8 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   DiffAcc<D> DA;
   if (DIFF) DA.init(b.drec, cap, j);
   const int team = (int)threadIdx.x / L;
-  // 2+1D: the rows the density pass of this stage used for the same particle
-  if constexpr (D == 2)
-    rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
-  else
-    team_rows<D, L>(b, E, b.keys[j], A.xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+  // the rows the density pass of this stage used for the same particle
+  rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
   RowCursor<L, ROWS> cur;
   cur.start(s_lo[team], s_hi[team], lane);
   const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
