@@ -1,7 +1,8 @@
 // Per-pair arithmetic of the SPH sums of the pair kernels (one team of lanes
 // per particle, candidates read from global memory, any batch).  Every lane
 // visits its candidates in a fixed order and the lanes are merged with a
-// fixed butterfly, so results do not depend on the batch or the launch.
+// fixed order (through LDS, lane by lane), so results do not depend on the
+// batch or the launch.
 // Floating-point contraction is off on the whole pair path and the fused
 // multiply-adds are written out.
 //
@@ -33,13 +34,6 @@ __device__ __forceinline__ double team_sum(double v) {
   return v;
 }
 
-template <int L>
-__device__ __forceinline__ int team_sum_i(int v) {
-#pragma unroll
-  for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // FP64 team sums through LDS: lane k of the team stores its NV partials at
 // buf[k * NV + v]; after a wavefront barrier (a team lies inside one wave)
 // lane v < NV adds value v of the L lanes in lane order and returns it (the
@@ -60,13 +54,6 @@ __device__ __forceinline__ double team_sums_lds(double* __restrict__ buf, int la
     for (int k = 0; k < L; ++k) acc += buf[k * NV + lane];
   }
   return acc;
-}
-
-// a lane's compensated FP32 partial, merged across the team in FP64 (one
-// FP64 add per butterfly level instead of a compensated FP32 merge)
-template <int L>
-__device__ __forceinline__ double team_sum_k(Kahan k) {
-  return team_sum<L>(k.value());
 }
 
 // ---------------------------------------------------------------------------
@@ -113,15 +100,6 @@ struct DensAcc {
 #pragma unroll
     for (int q = 0; q < 4; ++q) p[1 + q] = q < NS ? (MIXED ? kv[q].value() : sv[q]) : 0.0;
     p[5] = (double)nnb;
-  }
-
-  // team totals: sigma*, s*, n*_B, n*_S, n*_Q (without sigma_d), neighbours
-  template <int L>
-  __device__ __forceinline__ void reduce(double out[5], int* count) {
-    out[0] = MIXED ? team_sum_k<L>(ks) : team_sum<L>(ss);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) out[1 + q] = q < NS ? (MIXED ? team_sum_k<L>(kv[q]) : team_sum<L>(sv[q])) : 0.0;
-    *count = team_sum_i<L>(nnb);
   }
 };
 
@@ -220,17 +198,6 @@ struct GradAcc {
 #pragma unroll
       for (int nu = 0; nu < D; ++nu) p[D + kk * D + nu] = MIXED ? kdu[kk][nu].value() : du[kk][nu];
     p[NP - 1] = MIXED ? kdv.value() : dv;
-  }
-
-  template <int L>
-  __device__ __forceinline__ void reduce() {
-#pragma unroll
-    for (int i = 0; i < D; ++i) F[i] = MIXED ? team_sum_k<L>(kF[i]) : team_sum<L>(F[i]);
-#pragma unroll
-    for (int kk = 0; kk < D; ++kk)
-#pragma unroll
-      for (int nu = 0; nu < D; ++nu) du[kk][nu] = MIXED ? team_sum_k<L>(kdu[kk][nu]) : team_sum<L>(du[kk][nu]);
-    dv = MIXED ? team_sum_k<L>(kdv) : team_sum<L>(dv);
   }
 };
 

@@ -14,8 +14,9 @@
 //              rates, Heun update
 //
 // The neighbour loops give each of L consecutive lanes every L-th candidate
-// of the particle's trimmed cell rows and combine the partial sums with a
-// fixed butterfly of lane shuffles, so the result is deterministic.  Each lane
+// of the particle's trimmed cell rows and combine the partial sums in a fixed
+// order through LDS (lane v adds value v of the team's lanes in lane order),
+// so the result is deterministic.  Each lane
 // takes its candidates U at a time (PairU): the positions of all U are
 // loaded together, then the operands of the accepted ones, so that a lane has
 // several loads in flight across row boundaries instead of one dependent
@@ -71,19 +72,6 @@ __device__ __forceinline__ void take(Cursor& cur, int32_t self, int32_t k[U], bo
     k[u] = self;
     if (v[u]) k[u] = cur.next();
   }
-}
-
-template <int D>
-__device__ __forceinline__ void write_density(const BatchDev& b, const Params& prm, int64_t j, const double sums[5],
-                                              int nnb) {
-  const int64_t cap = b.cap;
-  const double sd = sigma_d<D>(prm.h);
-  b.dsum[(int64_t)DS_SIG * cap + j] = sums[0] * sd;
-  b.dsum[(int64_t)DS_S * cap + j] = sums[1] * sd;
-  b.dsum[(int64_t)DS_NB * cap + j] = sums[2] * sd;
-  b.dsum[(int64_t)DS_NS * cap + j] = sums[3] * sd;
-  b.dsum[(int64_t)DS_NQ * cap + j] = sums[4] * sd;
-  b.dsum[(int64_t)DS_NNB * cap + j] = (double)nnb;
 }
 
 // ---------------------------------------------------------------------------
@@ -145,19 +133,12 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
     }
     if (!v[PAIR_U - 1]) break;
   }
-  if constexpr (D == 2) {
-    // lane v < 6 forms row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
-    __shared__ double s_red[Team<D>::PER_BLOCK][L * 6];
-    double part[6];
-    A.partials(part);
-    const double tot = team_sums_lds<L, 6>(s_red[team], lane, part);
-    if (lane < 6) b.dsum[(int64_t)(DS_SIG + lane) * b.cap + j] = lane == 5 ? tot : tot * sigma_d<D>(prm.h);
-  } else {
-    double sums[5];
-    int nnb;
-    A.template reduce<L>(sums, &nnb);
-    if (lane == 0) write_density<D>(b, prm, j, sums, nnb);
-  }
+  // lane v < 6 forms row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
+  __shared__ double s_red[Team<D>::PER_BLOCK][L * 6];
+  double part[6];
+  A.partials(part);
+  const double tot = team_sums_lds<L, 6>(s_red[team], lane, part);
+  if (lane < 6) b.dsum[(int64_t)(DS_SIG + lane) * b.cap + j] = lane == 5 ? tot : tot * sigma_d<D>(prm.h);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,21 +342,6 @@ __device__ __forceinline__ void grad_setup(const BatchDev& b, const Params& prm,
   A.init();
 }
 
-template <int D, bool VISC, bool MIXED>
-__device__ __forceinline__ void write_grad(const BatchDev& b, const Params& prm, int64_t j,
-                                           const GradAcc<D, VISC, MIXED>& A) {
-  const int64_t cap = b.cap;
-  const double fsd = sigma_d<D>(prm.h) / prm.h;
-  const double isg = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
-#pragma unroll
-  for (int i = 0; i < D; ++i) b.gsum[(int64_t)(GS_F1 + i) * cap + j] = A.F[i] * fsd;
-#pragma unroll
-  for (int kk = 0; kk < D; ++kk)
-#pragma unroll
-    for (int nu = 0; nu < D; ++nu) b.gsum[(int64_t)(GS_DU11 + kk * 3 + nu) * cap + j] = A.du[kk][nu] * isg;
-  b.gsum[(int64_t)GS_DIVV * cap + j] = A.dv * isg;
-}
-
 // DIFF: also the BSQ diffusion sums (DiffAcc) over the same accepted pairs
 template <int D, bool VISC, bool MIXED, bool DIFF>
 __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
@@ -442,8 +408,8 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
     }
     if (!v[PAIR_U - 1]) break;
   }
-  if constexpr (D == 2) {
-    // lane v < 7 forms gradient sum v: F_1, F_2, d_k u^j (k, j = 1, 2), div v
+  {
+    // lane v < NP forms gradient sum v: F_i, d_k u^j (row-major), div v
     constexpr int NP = GradAcc<D, VISC, MIXED>::NP;
     __shared__ double s_red[Team<D>::PER_BLOCK][L * NP];
     double part[NP];
@@ -465,12 +431,9 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       }
       b.gsum[(int64_t)row * cap + j] = tot * scale;
     }
-  } else {
-    A.template reduce<L>();
   }
   if (DIFF) DA.template reduce<L>();
   if (lane == 0) {
-    if constexpr (D != 2) write_grad<D, VISC, MIXED>(b, prm, j, A);
     if (DIFF) {
       const double fsd = sigma_d<D>(prm.h) / prm.h;
       DA.write(b.gsum, cap, j, fsd, fsd / b.th[(int64_t)T_SIGSTAR * cap + j]);
