@@ -114,6 +114,61 @@ def test_bjorken_israel_stewart(oracle_mod, coef):
     assert abs(y[O.V_U1, c]) < 1e-10 and abs(y[O.V_U2, c]) < 1e-10
 
 
+@pytest.mark.parametrize("coef", COEFFS)
+def test_bjorken_israel_stewart_3d(oracle_mod, coef):
+    """The same Bjorken ODEs through the 3+1D path: a lattice uniform in
+    (x, y, eta) at rest in Milne coordinates, so the eta-direction terms
+    (Christoffel symbols, tau^2 pi^{eta eta}, the 3x3 solve) are exercised."""
+    O = oracle_mod
+    AG = 19 * math.pi ** 2 / 36
+    eta_s, zpk, zT, zw = 0.08, 0.05, 0.17 / HBARC, 0.02 / HBARC
+    T0 = 0.2 / HBARC
+    s0 = 4 * AG * T0 ** 3
+    side, dx, h = 19, 0.1, 0.15
+    xi = I.lattice((side, side, side), dx, -0.5 * dx * (side - 1))
+    n = xi.shape[1]
+    dens = np.stack([np.full(n, s0), np.zeros(n), np.zeros(n), np.zeros(n)])
+    prm = O.params(dim=3, hyperbolic=True, viscous=True, ncharge=0, h=h, eta_over_s=eta_s,
+                   zeta_peak=zpk, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, use_cells=1, **coef)
+    eos = O.eos_gas()
+    t0, dt, nsteps = 0.6, 0.005, 40   # before the edges' rarefaction reaches the centre
+    y = O.init(prm, eos, t0, xi, np.zeros_like(xi), 0, dens)
+    c = int(np.argmin((xi ** 2).sum(0)))
+    _, aux0, _ = O.rhs(prm, eos, t0, y)
+    t, y, _ = O.evolve(prm, eos, t0, dt, nsteps, y)
+    _, aux, _ = O.rhs(prm, eos, t, y)
+    sigma = aux[O.A_SIGSTAR, c] / (aux[O.A_GAMMA, c] * t)
+    e_sph = aux[O.A_E, c]
+    Pi_sph = sigma * y[O.V_B, c]
+    pi_sph = -t * t * sigma * y[O.V_P33, c]
+
+    def f(tau, Y):
+        e, Pi, pi = Y
+        T = (e / (3 * AG)) ** 0.25
+        s = 4 * AG * T ** 3
+        w = 4 * e / 3
+        eta = eta_s * s
+        zeta = s * zpk * math.exp(-(T - zT) ** 2 / (2 * zw * zw))
+        taupi = 5 * eta / w
+        de = -(w + Pi - pi) / tau
+        dPi = -(Pi + zeta / tau) / taupi - coef["c_PiPi"] * Pi / tau + coef["c_Pipi"] * pi / tau
+        dpi = -(pi - 4 * eta / (3 * tau)) / taupi - coef["c_pipi"] * pi / tau + 2 / 3 * coef["c_piPi"] * Pi / tau
+        return [de, dPi, dpi]
+
+    sol = solve_ivp(f, (t0, t), [aux0[O.A_E, c], 0.0, 0.0], method="DOP853", rtol=1e-12, atol=1e-14)
+    e_ex, Pi_ex, pi_ex = sol.y[:, -1]
+    assert abs(e_sph / e_ex - 1) < 2e-4
+    assert abs(Pi_sph - Pi_ex) < 2e-3 * abs(Pi_ex)
+    assert abs(pi_sph - pi_ex) < 2e-3 * abs(pi_ex)
+    # transverse shear pi^xx = pi^yy = pi/2, no flow, no off-diagonal stress
+    assert abs(sigma * y[O.V_P11, c] / (pi_ex / 2) - 1) < 2e-3
+    assert abs(sigma * y[O.V_P22, c] / (pi_ex / 2) - 1) < 2e-3
+    for r in (O.V_U1, O.V_U2, O.V_U3):
+        assert abs(y[r, c]) < 1e-10
+    for r in (O.V_P12, O.V_P13, O.V_P23):
+        assert abs(y[r, c]) < 1e-10 * abs(y[O.V_P11, c])
+
+
 def lumpy_cartesian(O, density_mode, seed=3, side=36):
     w = I.lumpy_2d_workload(n_side=side, spacing=0.1, h=0.15, seed=seed, n_hot=12, radius=1.0,
                             width=0.4, rhoB=0.02, rhoQ=0.01)
