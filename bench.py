@@ -493,7 +493,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lumpy_2d_viscous_bsq_40k", "particles": w.n, "h_fm": w.h, "dt_fm": w.dt,
                    "tau0_fm": w.t0, "eos": "massless-gas table 64x32x32x32 + analytic backup",
-                   "precision": "mixed", "mean_neighbours": head["nnb"]},
+                   "precision": "mixed", "mean_neighbours": head["nnb"], "skin_h": HEADLINE_SKIN_H},
         "fp64": {"value": value64, "ms_per_step": res["fp64"]["elapsed"] / args.steps * 1e3},
         "mixed_over_fp64": value / value64,
         "kernel_ms_per_step": {"mixed": [m / args.steps for m in head["ms"]],
