@@ -59,3 +59,28 @@ def test_oracle_neighbour_count_is_the_ball_share(oracle_mod):
         outer = int(np.count_nonzero(r2 < (2 * h) ** 2 * (1 + 1e-9)))
         assert inner <= nnb <= outer, (nnb, inner, outer)
         assert abs(nnb / (math.pi / 6 * n_est) - 1) < 0.05, (nnb, n_est)
+
+
+def golden_matrix():
+    K, tau = [], None
+    with open(os.path.join(HERE, "golden", "bsq_diffusion_matrix.txt")) as fh:
+        for line in fh:
+            if line.startswith("kappa_T2"):
+                K.append([float(v) for v in line.split()[1:]])
+            elif line.startswith("tau_T"):
+                tau = [float(v) for v in line.split()[1:]]
+    return np.array(K), np.array(tau)
+
+
+def test_printed_diffusion_matrix(oracle_mod):
+    """The printed kappa/T^2 matrix is the oracle's default, is symmetric
+    (Onsager) and positive definite, so the diffusion terms produce entropy:
+    -J . grad(alpha) = kappa_{qq'} grad(alpha_q) . grad(alpha_q') >= 0; the
+    printed relaxation times are the default tau_J = 0.2 / T."""
+    K, tau = golden_matrix()
+    assert np.array_equal(np.asarray(oracle_mod.KAPPA_T2_BSQ), K)
+    assert np.array_equal(K, K.T)
+    assert np.linalg.eigvalsh(K).min() > 0.0
+    assert np.all(tau == 0.2)
+    prm = oracle_mod.params(dim=2, ncharge=3, diffusion=True)
+    assert prm.tauJ_coeff == 0.2 and list(prm.kappa_T2) == list(K.flat)
