@@ -89,6 +89,7 @@ typedef struct {
   double kappa_T2[9];  /* kappa_{qq'} / T^2, row-major q*3+q' (constant matrix) */
   double tauJ_coeff;   /* tau_{qq'} = tauJ_coeff delta_{qq'} / T */
   double c_JJ;         /* coefficient of -tau_J J^mu theta (reading; 0 by default) */
+  double c_pisig;      /* Lambda_pipi / (beta tau_pi) of the ADNH term pi_lambda^<mu sigma^nu>lambda */
 } orc_params;
 
 /* One external source of energy-momentum and charge (eq. conservation_source;
@@ -925,8 +926,13 @@ static void geom_at(int hyperbolic, double t, geom *m)
  * Relaxation (eq. min_bul_rel, eq. min_she_rel, DNMR-type couplings):
  *     DPi = -(Pi + zeta theta)/tau_Pi - c_PiPi Pi theta + c_Pipi pi:sigma
  *     gamma d(pi^ij/sigma)/dx0 = (1/sigma)[(2 eta sigma^ij - pi^ij)/tau_pi
- *         + (1 - c_pipi) pi^ij theta + c_piPi Pi sigma^ij
+ *         + (1 - c_pipi) pi^ij theta + c_piPi Pi sigma^ij + c_pisig Q^ij
  *         - (u^i pi^{jl} + u^j pi^{il}) Du_l - u^l (Gam^i_lk pi^kj + Gam^j_lk pi^ik)]
+ * with the ADNH shear term of eq. diffusion-evol, Q^{mu nu} = pi_lambda^<mu
+ * sigma^nu>lambda: the symmetric, traceless, transverse part of
+ * A^{mu nu} = pi^{mu lambda} g_{lambda lambda} sigma^{lambda nu}; both factors are
+ * transverse, so Q^{mu nu} = (A^{mu nu} + A^{nu mu})/2 - Delta^{mu nu} pi:sigma / 3
+ * (the term's theta/3 part has the form of the c_pipi term).
  * Entropy (eq. dsdnrewr, no diffusion):
  *     gamma sigma T dS/dx0 = u.I - mu_q I_q - Pi theta + pi:sigma.
  * External sources (eq. conservation_source): u.I adds to D eps (eq.
@@ -980,6 +986,7 @@ typedef struct {
   double divF[3];     /* sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad W  (~ d_i F^i / sigma*) */
   double kapJ[3][3];  /* diffusion matrix kappa_{qq'} */
   double tauJ, cJJ;
+  double cpisig;
 } pctx;
 
 typedef struct {
@@ -1042,6 +1049,15 @@ static void eom_eval(const pctx *c, const double a[4], pout *o)
       for (int j = i; j < 4; ++j) {
         double val = (2.0 * c->eta * sig[i][j] - c->pi[i][j]) / c->taupi
                    + (1.0 - c->cpipi) * c->pi[i][j] * theta + c->cpiPi * c->Pi * sig[i][j];
+        if (c->cpisig != 0.0) {
+          double Aij = 0.0, Aji = 0.0;
+          for (int l = 0; l < 4; ++l) {
+            Aij += c->pi[i][l] * m->g[l] * sig[l][j];
+            Aji += c->pi[j][l] * m->g[l] * sig[l][i];
+          }
+          double Delta = (i == j ? m->ginv[i] : 0.0) - u[i] * u[j];
+          val += c->cpisig * (0.5 * (Aij + Aji) - Delta * pisig / 3.0);
+        }
         for (int l = 0; l < 4; ++l) val -= (u[i] * c->pi[j][l] + u[j] * c->pi[i][l]) * Dl[l];
         for (int l = 0; l < 4; ++l)
           for (int k = 0; k < 4; ++k)
@@ -1324,6 +1340,7 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
       c.cPipi = prm->c_Pipi;
       c.cpipi = prm->c_pipi;
       c.cpiPi = prm->c_piPi;
+      c.cpisig = prm->c_pisig;
       sources_at(prm, &m, t, y, n, a, c.I, c.Iq);
       for (int q = 0; q < 3; ++q) {
         c.mu[q] = q < prm->ncharge ? qa->th.mu[q] : 0.0;

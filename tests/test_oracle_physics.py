@@ -55,8 +55,12 @@ def test_gubser_to_tau2_dense(oracle_mod):
     assert le < 0.03 and lu < 0.02
 
 
+# minimal IS; first-order couplings; and the ADNH shear term
+# c_pisig pi_lambda^<mu sigma^nu>lambda, which in Bjorken flow adds
+# c_pisig pi / (3 tau) to d pi / d tau (pi^xx = pi^yy = pi/2, tau^2 pi^etaeta = -pi)
 COEFFS = [dict(c_PiPi=1.0, c_Pipi=0.0, c_pipi=4 / 3, c_piPi=0.0),
-          dict(c_PiPi=0.7, c_Pipi=0.3, c_pipi=1.1, c_piPi=0.2)]
+          dict(c_PiPi=0.7, c_Pipi=0.3, c_pipi=1.1, c_piPi=0.2),
+          dict(c_PiPi=1.0, c_Pipi=0.0, c_pipi=4 / 3, c_piPi=0.0, c_pisig=0.9)]
 
 
 @pytest.mark.parametrize("coef", COEFFS)
@@ -102,7 +106,8 @@ def test_bjorken_israel_stewart(oracle_mod, coef):
         w, eta, zeta, taupi, tauPi = thermo(e)
         de = -(w + Pi - pi) / tau
         dPi = -(Pi + zeta / tau) / tauPi - coef["c_PiPi"] * Pi / tau + coef["c_Pipi"] * pi / tau
-        dpi = -(pi - 4 * eta / (3 * tau)) / taupi - coef["c_pipi"] * pi / tau + 2 / 3 * coef["c_piPi"] * Pi / tau
+        dpi = (-(pi - 4 * eta / (3 * tau)) / taupi - coef["c_pipi"] * pi / tau + 2 / 3 * coef["c_piPi"] * Pi / tau
+               + coef.get("c_pisig", 0.0) * pi / (3 * tau))
         return [de, dPi, dpi]
 
     sol = solve_ivp(f, (t0, t), [aux0[O.A_E, c], 0.0, 0.0], method="DOP853", rtol=1e-12, atol=1e-14)
@@ -152,7 +157,8 @@ def test_bjorken_israel_stewart_3d(oracle_mod, coef):
         taupi = 5 * eta / w
         de = -(w + Pi - pi) / tau
         dPi = -(Pi + zeta / tau) / taupi - coef["c_PiPi"] * Pi / tau + coef["c_Pipi"] * pi / tau
-        dpi = -(pi - 4 * eta / (3 * tau)) / taupi - coef["c_pipi"] * pi / tau + 2 / 3 * coef["c_piPi"] * Pi / tau
+        dpi = (-(pi - 4 * eta / (3 * tau)) / taupi - coef["c_pipi"] * pi / tau + 2 / 3 * coef["c_piPi"] * Pi / tau
+               + coef.get("c_pisig", 0.0) * pi / (3 * tau))
         return [de, dPi, dpi]
 
     sol = solve_ivp(f, (t0, t), [aux0[O.A_E, c], 0.0, 0.0], method="DOP853", rtol=1e-12, atol=1e-14)
