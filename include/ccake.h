@@ -119,7 +119,10 @@ typedef struct ccake_server ccake_server;
  *                  J - v J^0 and the entropy by -mu_q/T per unit charge moved
  *   kappa_T2       kappa_{qq'}/T^2, row-major (B, S, Q), constant
  *   tauJ_coeff     tau_J = tauJ_coeff / T (the paper's example: 0.2)
- *   c_JJ           coefficient of the -c_JJ tau_J J^mu theta term (0 by default) */
+ *   c_JJ           coefficient of the -c_JJ tau_J J^mu theta term (0 by default)
+ *   c_pisig        coefficient (Lambda_pipi / (beta tau_pi) of eq. diffusion-evol)
+ *                  of the shear term pi_lambda^<mu sigma^nu>lambda; 0 by default,
+ *                  must be finite, read only by viscous runs */
 typedef struct ccake_config {
   int32_t dim, coords, viscous, precision, ncharge, density_mode;
   double h;
@@ -131,6 +134,7 @@ typedef struct ccake_config {
   int32_t diffusion, pad0;
   double kappa_T2[9];
   double tauJ_coeff, c_JJ;
+  double c_pisig;
 } ccake_config;
 
 /* Per-event counters of the last evaluation (ccake_totals). */

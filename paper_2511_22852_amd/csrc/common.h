@@ -125,6 +125,7 @@ struct Params {
   double kappa_T2[9]; // kappa_{qq'}/T^2, row-major (diffusion)
   double tauJ_coeff;  // tau_J = tauJ_coeff / T
   double c_JJ;        // coefficient of -tau_J J theta
+  double c_pisig;     // coefficient of the ADNH shear term pi_lambda^<i sigma^j>lambda
   double cell_edge;   // >= 2h + skin
   const SourceSet* src = nullptr;  // external sources (device), or none
 };

@@ -11,7 +11,7 @@
 //   DPi = -(Pi + zeta theta)/tau_Pi - c_PiPi Pi theta + c_Pipi pi:sigma
 //         (eq. min_bul_rel; the c's are the first-order couplings of eq. dnmr)
 //   gamma d(pi^{ij}/sigma)/dx0 = (1/sigma)[(2 eta sigma^{ij} - pi^{ij})/tau_pi
-//         + (1 - c_pipi) pi^{ij} theta + c_piPi Pi sigma^{ij}
+//         + (1 - c_pipi) pi^{ij} theta + c_piPi Pi sigma^{ij} + c_pisig pi_l^<i sigma^j>l
 //         - (u^i pi^{jl} + u^j pi^{il}) Du_l - Christoffel terms]   (eq. min_she_rel)
 //   Dp = -c_s^2 w theta + (dp/de)_n (-Pi theta + pi:sigma + u.I)
 //   momentum: d/dx0[(w+Pi) Q_i/sigma + G_i pi^{0i}/(sigma gamma)]
@@ -150,6 +150,19 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
       for (int j = i; j < 4; ++j) {
         Aff val = (1.0 / in.taupi) * ((2.0 * in.eta) * sg[i][j] + (-in.pi[i][j])) +
                   ((1.0 - prm.c_pipi) * in.pi[i][j]) * theta + (prm.c_piPi * Pi) * sg[i][j];
+        if (prm.c_pisig != 0.0) {
+          // pi_lambda^<i sigma^j>lambda: both factors are transverse, so the
+          // projection is the symmetric part of pi^{il} g_ll sigma^{lj} minus
+          // Delta^{ij} pi:sigma / 3
+          Aff Aij = aff(0.0), Aji = aff(0.0);
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            Aij = Aij + (in.pi[i][l] * g[l]) * sg[l][j];
+            Aji = Aji + (in.pi[j][l] * g[l]) * sg[l][i];
+          }
+          const double Delta = (i == j ? gi[i] : 0.0) - uu[i] * uu[j];
+          val = val + prm.c_pisig * (0.5 * (Aij + Aji) + (-Delta / 3.0) * pisig);
+        }
 #pragma unroll
         for (int l = 0; l < 4; ++l) val = val - (uu[i] * in.pi[j][l] + uu[j] * in.pi[i][l]) * Dl[l];
         double chr = 0.0;

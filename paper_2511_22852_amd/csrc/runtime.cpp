@@ -43,6 +43,7 @@ bool validate_config(const ccake_config* c, std::string* why) {
   if (c->viscous) {
     if (!(c->eta_over_s > 0.0)) { *why = "viscous runs need eta_over_s > 0"; return false; }
     if (!(c->taupi_coeff > 0.0) || !(c->tauPi_ratio > 0.0)) { *why = "relaxation-time coefficients must be > 0"; return false; }
+    if (!std::isfinite(c->c_pisig)) { *why = "c_pisig must be finite"; return false; }
   }
   if (c->diffusion != 0 && c->diffusion != 1) { *why = "diffusion must be 0 or 1"; return false; }
   if (c->diffusion) {
@@ -79,6 +80,7 @@ Params to_params(const ccake_config& c) {
   for (int i = 0; i < 9; ++i) p.kappa_T2[i] = c.diffusion ? c.kappa_T2[i] : 0.0;
   p.tauJ_coeff = c.diffusion ? c.tauJ_coeff : 1.0;
   p.c_JJ = c.diffusion ? c.c_JJ : 0.0;
+  p.c_pisig = c.viscous ? c.c_pisig : 0.0;
   p.cell_edge = 2.0 * c.h + c.skin;
   return p;
 }

@@ -90,6 +90,13 @@ RATE_CASES = {
                                       coeffs=dict(c_PiPi=0.7, c_Pipi=0.3, c_pipi=1.1, c_piPi=0.2)), visc=True),
     "lumpy3d_visc_table": dict(wl=lumpy3d_small, kw=dict(dim=3, viscous=True, ncharge=3, eos="table", h=0.3),
                                visc=True),
+    # with the ADNH shear term pi_lambda^<mu sigma^nu>lambda (eq. diffusion-evol)
+    "lumpy2d_visc_adnh": dict(wl=lambda: lumpy_small(rhoB=0.005, rhoQ=0.002),
+                              kw=dict(dim=2, viscous=True, ncharge=3, eos="table", h=0.24,
+                                      coeffs=dict(c_PiPi=0.7, c_Pipi=0.3, c_pipi=1.1, c_piPi=0.2, c_pisig=0.9)),
+                              visc=True),
+    "lumpy3d_visc_adnh": dict(wl=lumpy3d_small, kw=dict(dim=3, viscous=True, ncharge=3, eos="table", h=0.3,
+                                                        coeffs=dict(c_pisig=-0.6)), visc=True),
     "lumpy3d_ideal_cartesian": dict(wl=lumpy3d_small, kw=dict(dim=3, hyperbolic=False, ncharge=3, eos="gas", h=0.3),
                                     visc=False),
 }
@@ -158,7 +165,8 @@ def test_rate_parity_fp64(B, O, name):
         assert np.all(np.abs(gg - og) <= tol * scale + 1e-300), (g0, np.max(np.abs(gg - og) / (scale + 1e-300)))
 
 
-@pytest.mark.parametrize("name", ["gubser2d_ideal", "lumpy2d_visc_table_inside", "lumpy3d_visc_table"])
+@pytest.mark.parametrize("name", ["gubser2d_ideal", "lumpy2d_visc_table_inside", "lumpy3d_visc_table",
+                                  "lumpy3d_visc_adnh"])
 def test_heun_step_parity_fp64(B, O, name):
     prm, oe, cfg, ge, y, t0 = prepared(B, O, name)
     dt = 0.005
@@ -192,9 +200,10 @@ def test_gubser_trajectory_fp64(B, O):
     assert rel_inf(e_g, aux_final[O.A_E]) <= 1e-9
 
 
-def test_lumpy_viscous_trajectory_fp64(B, O):
+@pytest.mark.parametrize("coeffs", [None, dict(c_pipi=1.1, c_piPi=0.2, c_pisig=0.9)], ids=["minimal_is", "adnh"])
+def test_lumpy_viscous_trajectory_fp64(B, O, coeffs):
     w = lumpy_small(side=40)
-    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", h=w.h)
+    prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", h=w.h, coeffs=coeffs)
     y = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
     n = 60
     _, yo, _ = O.evolve(prm, oe, w.t0, w.dt, n, y)
