@@ -68,6 +68,7 @@ class Params(ctypes.Structure):
         ("diffusion", ctypes.c_int32), ("pad2", ctypes.c_int32),
         ("kappa_T2", ctypes.c_double * 9), ("tauJ_coeff", ctypes.c_double),
         ("c_JJ", ctypes.c_double), ("c_pisig", ctypes.c_double),
+        ("d_JPi", ctypes.c_double * 3),
     ]
 
 
@@ -186,8 +187,10 @@ def params(dim=2, hyperbolic=True, viscous=False, ncharge=0, h=0.3, eta_over_s=0
            zeta_peak=0.0, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, taupi_coeff=5.0,
            tauPi_ratio=1.0, c_PiPi=1.0, c_Pipi=0.0, c_pipi=4.0 / 3.0, c_piPi=0.0,
            use_cells=None, nthreads=0, density_mode=0, source_specs=None, diffusion=False,
-           kappa_T2=KAPPA_T2_BSQ, tauJ_coeff=0.2, c_JJ=0.0, c_pisig=0.0) -> Params:
+           kappa_T2=KAPPA_T2_BSQ, tauJ_coeff=0.2, c_JJ=0.0, c_pisig=0.0, d_JPi=(0.0, 0.0, 0.0)) -> Params:
     p = Params()
+    for q in range(3):
+        p.d_JPi[q] = float(d_JPi[q])
     p.c_pisig = c_pisig
     p.diffusion = int(bool(diffusion))
     kT = np.asarray(kappa_T2, dtype=np.float64).reshape(3, 3)

@@ -90,6 +90,7 @@ typedef struct {
   double tauJ_coeff;   /* tau_{qq'} = tauJ_coeff delta_{qq'} / T */
   double c_JJ;         /* coefficient of -tau_J J^mu theta (reading; 0 by default) */
   double c_pisig;      /* Lambda_pipi / (beta tau_pi) of the ADNH term pi_lambda^<mu sigma^nu>lambda */
+  double d_JPi[3];     /* delta_JPi^q / beta of the ADNH diffusion term -kappa_qq' delta_JPi^q'/beta nabla^mu Pi */
 } orc_params;
 
 /* One external source of energy-momentum and charge (eq. conservation_source;
@@ -954,7 +955,13 @@ static void geom_at(int hyperbolic, double t, geom *m)
  *   - the theta term of eq. min_dif_rel (coefficient 1/(2 beta), beta not
  *     given) enters as -c_JJ tau_J J theta with a caller-supplied c_JJ;
  *   - the pressure does not respond to diffusion ((dp/dn_q)_e = 0, as for
- *     the sources), so the momentum solve is unchanged (R^i_b = 0).
+ *     the sources), so the momentum solve is unchanged (R^i_b = 0);
+ *   - the ADNH bulk-gradient coupling of eq. diffusion-evol,
+ *     -kappa_{qq'} delta_JPi^{q'}/beta nabla^mu Pi, written in the same
+ *     metric as the alpha term: the target becomes
+ *     kappa_{qq'} g^{ii} (d_i alpha_{q'} + d_JPi[q'] d_i Pi), with
+ *     d_JPi = delta_JPi/beta caller-supplied (0 by default) and d_i Pi the
+ *     n = 1 SPH gradient, like d_i alpha.
  * Relaxation, with Delta^mu_nu D J^nu = DJ^mu + u^mu J^nu Du_nu and
  * DJ^i = gamma dJ^i/dx0 + u^l Gam^i_lk J^k, D sigma = -sigma theta:
  *     gamma sigma dV^i/dx0 = (kappa_{qq'} g^{ii} d_i alpha_{q'} - J^i)/tau_J
@@ -983,6 +990,8 @@ typedef struct {
   double J[3][4];     /* J^mu_q (J^0 from orthogonality) */
   double V[3][4];     /* J^k_q / sigma (state) */
   double dalpha[3][4];/* d_k alpha_q, n = 1 form */
+  double dPi[4];      /* d_k Pi, n = 1 form */
+  double dJPi[3];     /* delta_JPi^q / beta */
   double divF[3];     /* sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad W  (~ d_i F^i / sigma*) */
   double kapJ[3][3];  /* diffusion matrix kappa_{qq'} */
   double tauJ, cJJ;
@@ -1079,7 +1088,8 @@ static void eom_eval(const pctx *c, const double a[4], pout *o)
       for (int nu = 0; nu < 4; ++nu) JDu += c->J[q][nu] * Dl[nu];
       for (int i = 1; i <= c->D; ++i) {
         double target = 0.0;
-        for (int r = 0; r < 3; ++r) target += c->kapJ[q][r] * m->ginv[i] * c->dalpha[r][i];
+        for (int r = 0; r < 3; ++r)
+          target += c->kapJ[q][r] * m->ginv[i] * (c->dalpha[r][i] + c->dJPi[r] * c->dPi[i]);
         double val = (target - c->J[q][i]) / c->tauJ + (1.0 - c->cJJ) * c->J[q][i] * theta - u[i] * JDu;
         for (int l = 0; l < 4; ++l)
           for (int k = 0; k < 4; ++k) val -= u[l] * m->Gam[i][l][k] * c->J[q][k];
@@ -1279,7 +1289,7 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
       const pass1_t *qa = &P1[a];
       int64_t cnt = neighbours(prm, &g, y, n, a, &buf, &cap);
       double F[4] = {0, 0, 0, 0}, dudx[4][4], divv = 0.0, de[4] = {0, 0, 0, 0};
-      double dal[3][4], divF[3] = {0, 0, 0};
+      double dal[3][4], divF[3] = {0, 0, 0}, dPi[4] = {0, 0, 0, 0};
       memset(dudx, 0, sizeof dudx);
       memset(dal, 0, sizeof dal);
       for (int64_t j = 0; j < cnt; ++j) {
@@ -1300,12 +1310,14 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
           divv += (qb->v[k] - qa->v[k]) * dW[k];
           de[k] += (qb->th.e - qa->th.e) * dW[k];
         }
-        if (prm->diffusion)
+        if (prm->diffusion) {
+          for (int k = 1; k <= D; ++k) dPi[k] += (qb->Pi - qa->Pi) * dW[k];
           for (int c = 0; c < 3; ++c)
             for (int k = 1; k <= D; ++k) {
               dal[c][k] += (qb->alpha[c] - qa->alpha[c]) * dW[k];
               divF[c] += (qa->F_over_s2[c][k] + qb->F_over_s2[c][k]) * dW[k];
             }
+        }
       }
       pctx c;
       memset(&c, 0, sizeof c);
@@ -1359,6 +1371,8 @@ static int rhs_impl(const orc_params *prm, const orc_eos *eos, double t, int64_t
         }
         c.tauJ = prm->tauJ_coeff / qa->th.T;
         c.cJJ = prm->c_JJ;
+        for (int k = 1; k <= D; ++k) c.dPi[k] = dPi[k] / qa->sigstar;
+        for (int r = 0; r < 3; ++r) c.dJPi[r] = prm->d_JPi[r];
       }
 
       double zero[4] = {0, 0, 0, 0}, M[4][4], rhs[4], acc_u[4] = {0, 0, 0, 0};

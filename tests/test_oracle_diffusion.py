@@ -332,3 +332,54 @@ def test_flux_relative_to_moving_particles(oracle_mod):
         dQ = (f[O.V_NB + q] + dY)[win]
         ref = -k * j0[q] * np.cos(k * xi[0][win]) / gam ** 2 / sstar[win]
         assert np.abs(dQ - ref).max() < 0.05 * np.abs(ref).max(), q      # kernel smoothing ~3.5%
+
+
+def bulk_gradient_error(O, dx, h, hyperbolic=False):
+    """The ADNH coupling of the currents to the bulk-pressure gradient (eq.
+    diffusion-evol, -kappa_qq' delta_JPi^q'/beta nabla^mu Pi, converted to the
+    mostly-minus metric like the kappa nabla alpha term): at rest with no
+    charge, J = 0 and Pi = P0 cos(kx), switching delta_JPi/beta = d on adds
+    kappa_qq' d_q' g^xx d_x Pi / (tau_J sigma) to the rate of V^x_q and
+    nothing to V^y_q."""
+    lam, tc, P0 = 4.0, 0.5, 0.05 * E0
+    t0 = 1.3 if hyperbolic else 0.0
+    sqg = t0 if hyperbolic else 1.0
+    K = np.asarray(O.KAPPA_T2_BSQ)
+    d = np.array([0.7, -0.4, 0.25]) / E0
+    xi, k, _, eos, _ = static_event(O, dx, h, np.zeros(3), lam, K, tc, hyperbolic=hyperbolic, t0=t0)
+    out = {}
+    for tag, dd in (("off", np.zeros(3)), ("on", d)):
+        prm = O.params(dim=2, hyperbolic=hyperbolic, viscous=True, ncharge=3, h=h, use_cells=1, diffusion=True,
+                       kappa_T2=K, tauJ_coeff=tc, eta_over_s=0.1, d_JPi=dd)
+        dens = np.zeros((4, xi.shape[1]))
+        dens[0] = E0
+        y = O.init(prm, eos, t0, xi, np.zeros_like(xi), 1, dens)
+        _, aux, _ = O.rhs(prm, eos, t0, y)
+        sig = aux[O.A_SIGSTAR] / sqg
+        y[O.V_B] = P0 * np.cos(k * xi[0]) / sig
+        f, aux, bad = O.rhs(prm, eos, t0, y)
+        assert bad == 0
+        out[tag] = (f, aux, sig)
+    f1, aux, sig = out["on"]
+    f0 = out["off"][0]
+    win = (np.abs(xi[0]) < 4.0) & (np.abs(xi[1]) < 1.0)
+    T = aux[O.A_T][win]
+    dxPi = -k * P0 * np.sin(k * xi[0][win])
+    err = []
+    for q in range(3):
+        ref = (K[q] @ d) * T * T * (-1.0) * dxPi / ((tc / T) * sig[win])
+        got = f1[O.V_JB1 + 3 * q][win] - f0[O.V_JB1 + 3 * q][win]
+        err.append(np.abs(got - ref).max() / np.abs(ref).max())
+        assert np.abs(f1[O.V_JB2 + 3 * q][win] - f0[O.V_JB2 + 3 * q][win]).max() < 1e-4 * np.abs(ref).max()
+    for r in range(O.NVAR):
+        if not O.V_JB1 <= r < O.V_JB1 + 9:
+            assert np.array_equal(f1[r], f0[r]), r
+    return max(err)
+
+
+@pytest.mark.parametrize("hyperbolic", [False, True])
+def test_bulk_gradient_coupling(oracle_mod, hyperbolic):
+    e1 = bulk_gradient_error(oracle_mod, 0.1, 0.3, hyperbolic)
+    e2 = bulk_gradient_error(oracle_mod, 0.05, 0.15, hyperbolic)
+    assert e1 < 0.05, e1
+    assert e2 < e1 / 3, (e1, e2)
