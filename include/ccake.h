@@ -122,7 +122,12 @@ typedef struct ccake_server ccake_server;
  *   c_JJ           coefficient of the -c_JJ tau_J J^mu theta term (0 by default)
  *   c_pisig        coefficient (Lambda_pipi / (beta tau_pi) of eq. diffusion-evol)
  *                  of the shear term pi_lambda^<mu sigma^nu>lambda; 0 by default,
- *                  must be finite, read only by viscous runs */
+ *                  must be finite, read only by viscous runs
+ *   d_JPi          delta_JPi^q / beta (B, S, Q) of the coupling of the currents
+ *                  to the bulk-pressure gradient (eq. diffusion-evol): the
+ *                  relaxation target becomes kappa_{qq'} g^{ii} (d_i alpha_{q'}
+ *                  + d_JPi[q'] d_i Pi); 0 by default, must be finite, read only
+ *                  by viscous runs with diffusion */
 typedef struct ccake_config {
   int32_t dim, coords, viscous, precision, ncharge, density_mode;
   double h;
@@ -135,6 +140,7 @@ typedef struct ccake_config {
   double kappa_T2[9];
   double tauJ_coeff, c_JJ;
   double c_pisig;
+  double d_JPi[3];
 } ccake_config;
 
 /* Per-event counters of the last evaluation (ccake_totals). */

@@ -63,7 +63,7 @@ class Config(ctypes.Structure):
         ("c_piPi", ctypes.c_double), ("skin", ctypes.c_double),
         ("diffusion", ctypes.c_int32), ("pad0", ctypes.c_int32),
         ("kappa_T2", ctypes.c_double * 9), ("tauJ_coeff", ctypes.c_double), ("c_JJ", ctypes.c_double),
-        ("c_pisig", ctypes.c_double),
+        ("c_pisig", ctypes.c_double), ("d_JPi", ctypes.c_double * 3),
     ]
 
 
@@ -186,7 +186,7 @@ def _ptr(a):
 def config(dim=2, hyperbolic=True, viscous=False, precision=FP64, ncharge=0, density_mode=DENS_SMOOTHED,
            h=0.3, eta_over_s=0.0, zeta_peak=0.0, zeta_Tpeak_GeV=0.17, zeta_width_GeV=0.02, taupi_coeff=5.0,
            tauPi_ratio=1.0, c_PiPi=1.0, c_Pipi=0.0, c_pipi=4.0 / 3.0, c_piPi=0.0, skin=None,
-           diffusion=False, kappa_T2=KAPPA_T2_BSQ, tauJ_coeff=0.2, c_JJ=0.0, c_pisig=0.0) -> Config:
+           diffusion=False, kappa_T2=KAPPA_T2_BSQ, tauJ_coeff=0.2, c_JJ=0.0, c_pisig=0.0, d_JPi=(0.0, 0.0, 0.0)) -> Config:
     c = Config()
     c.diffusion = int(bool(diffusion))
     kT = [float(v) for row in kappa_T2 for v in row]
@@ -195,6 +195,8 @@ def config(dim=2, hyperbolic=True, viscous=False, precision=FP64, ncharge=0, den
         c.kappa_T2[i] = kT[i]
     c.tauJ_coeff, c.c_JJ = tauJ_coeff, c_JJ
     c.c_pisig = c_pisig
+    for q in range(3):
+        c.d_JPi[q] = float(d_JPi[q])
     c.dim, c.coords, c.viscous = dim, HYPERBOLIC if hyperbolic else CARTESIAN, int(viscous)
     c.precision, c.ncharge, c.density_mode = int(precision), ncharge, density_mode
     c.h, c.eta_over_s = h, eta_over_s

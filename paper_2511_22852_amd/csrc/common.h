@@ -41,8 +41,8 @@ enum Rec { Q_PP, Q_A11, Q_A12, Q_A13, Q_A21, Q_A22, Q_A23, Q_A31, Q_A32, Q_A33,
            Q_U1, Q_U2, Q_U3, Q_V1, Q_V2, Q_V3, NREC };
 
 // neighbour record of the diffusion sums (FP64, written by pass 1):
-// alpha_q = mu_q/T and F^k_q/sigma*^2 with F = J - v J^0 (row QD_FB1 + 3q + k-1)
-enum DRec { QD_AB, QD_AS, QD_AQ, QD_FB1, QD_FB2, QD_FB3, QD_FS1, QD_FS2, QD_FS3, QD_FQ1, QD_FQ2, QD_FQ3, NDREC };
+// alpha_q = mu_q/T and F^k_q/sigma*^2 with F = J - v J^0 (row QD_FB1 + 3q + k-1), and Pi
+enum DRec { QD_AB, QD_AS, QD_AQ, QD_FB1, QD_FB2, QD_FB3, QD_FS1, QD_FS2, QD_FS3, QD_FQ1, QD_FQ2, QD_FQ3, QD_PI, NDREC };
 
 // warm-start record of the EoS inversion (carried with the particle): the
 // last root of the analytic backup EoS and, when the table answered, the last
@@ -54,11 +54,12 @@ enum DSum { DS_SIG, DS_S, DS_NB, DS_NS, DS_NQ, DS_NNB, NDSUM };
 
 // gradient sums of a particle: force F_i, d_k u^j (row-major k*3+j, divided by sigma*), div v,
 // d_i e (freeze-out), and with diffusion d_k alpha_q (row GS_DAB1 + 3q + k-1, divided by
-// sigma*) and the flux sums sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad W (GS_DJB + q)
+// sigma*) and the flux sums sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad W (GS_DJB + q);
+// d_k Pi (GS_DPI1 + k-1, divided by sigma*)
 enum GSum { GS_F1, GS_F2, GS_F3, GS_DU11, GS_DU12, GS_DU13, GS_DU21, GS_DU22, GS_DU23, GS_DU31, GS_DU32,
             GS_DU33, GS_DIVV, GS_DE1, GS_DE2, GS_DE3,
             GS_DAB1, GS_DAB2, GS_DAB3, GS_DAS1, GS_DAS2, GS_DAS3, GS_DAQ1, GS_DAQ2, GS_DAQ3,
-            GS_DJB, GS_DJS, GS_DJQ, NGSUM };
+            GS_DJB, GS_DJS, GS_DJQ, GS_DPI1, GS_DPI2, GS_DPI3, NGSUM };
 
 enum EosKind { EOS_CONFORMAL = 0, EOS_TABLE = 1, EOS_GAS = 2 };
 
@@ -126,6 +127,7 @@ struct Params {
   double tauJ_coeff;  // tau_J = tauJ_coeff / T
   double c_JJ;        // coefficient of -tau_J J theta
   double c_pisig;     // coefficient of the ADNH shear term pi_lambda^<i sigma^j>lambda
+  double d_JPi[3];    // delta_JPi^q / beta: currents coupled to nabla Pi (diffusion)
   double cell_edge;   // >= 2h + skin
   const SourceSet* src = nullptr;  // external sources (device), or none
 };

@@ -280,7 +280,7 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
 // through its boundary); kappa_{qq'} = kappa_T2 T^2, tau_J = tauJ_coeff / T.
 template <int D>
 __device__ inline void diffusion_rates(const Params& prm, const EomIn& in, const EomOut& o, const double V[3][3],
-                                       const double dal[3][3], const double divF[3], double dV[3][3],
+                                       const double dal[3][3], const double dPi[3], const double divF[3], double dV[3][3],
                                        double dNd[3]) {
   const bool hyp = prm.hyperbolic != 0;
   const double t = in.t;
@@ -323,7 +323,8 @@ __device__ inline void diffusion_rates(const Params& prm, const EomIn& in, const
       }
       double target = 0.0;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) target += prm.kappa_T2[3 * q + r] * T2 * (1.0 / g[1 + i]) * dal[r][i];
+      for (int r = 0; r < 3; ++r)
+        target += prm.kappa_T2[3 * q + r] * T2 * (1.0 / g[1 + i]) * (dal[r][i] + prm.d_JPi[r] * dPi[i]);
       double val = (target - J[i]) / tauJ + (1.0 - prm.c_JJ) * J[i] * th - in.u[1 + i] * JDu;
       if (i == 2) val -= it * (gam * J[2] + u3 * J0);
       dV[q][i] = val * igs;

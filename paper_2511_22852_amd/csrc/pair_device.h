@@ -210,14 +210,16 @@ struct GradAcc {
 // flux from b to a).
 template <int D>
 struct DiffAcc {
-  double al[3], Fa[3][3];
-  double da[3][3], dj[3];
+  double al[3], Fa[3][3], Pa;
+  double da[3][3], dj[3], dp[3];
 
-  __device__ __forceinline__ void init(const double* __restrict__ dr, int64_t cap, int64_t j) {
+  __device__ __forceinline__ void init(const double* __restrict__ dr, int64_t cap, int64_t j, bool with_pi) {
+    Pa = with_pi ? dr[(int64_t)QD_PI * cap + j] : 0.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       al[q] = dr[(int64_t)(QD_AB + q) * cap + j];
       dj[q] = 0.0;
+      dp[q] = 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         Fa[q][k] = k < D ? dr[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] : 0.0;
@@ -226,9 +228,11 @@ struct DiffAcc {
     }
   }
 
-  // the neighbour's record: alpha_q and F^k_q / sigma*^2
+  // the neighbour's record: alpha_q, F^k_q / sigma*^2 and, when the
+  // bulk-gradient coupling is on (uniform over the grid), Pi
   __device__ __forceinline__ static void load(const double* __restrict__ dr, int64_t cap, int32_t m, double ab[3],
-                                              double Fb[3][3]) {
+                                              double Fb[3][3], double& Pb, bool with_pi) {
+    Pb = with_pi ? dr[(int64_t)QD_PI * cap + m] : 0.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       ab[q] = dr[(int64_t)(QD_AB + q) * cap + m];
@@ -238,13 +242,16 @@ struct DiffAcc {
   }
 
   __device__ __forceinline__ void add(const double xa[3], const double xb[3], double d2, double ih, const double ab[3],
-                                      const double Fb[3][3]) {
+                                      const double Fb[3][3], double Pb) {
     if (!(d2 > 0.0)) return;  // self pair: grad W = 0
     const double r = sqrt(d2);
     const double f = spline_dw(r * ih) / r;
     double dW[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) dW[k] = k < D ? f * (xa[k] - xb[k]) : 0.0;
+    const double dPb = Pb - Pa;
+#pragma unroll
+    for (int k = 0; k < D; ++k) dp[k] += dPb * dW[k];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const double dal = ab[q] - al[q];
@@ -261,6 +268,7 @@ struct DiffAcc {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       dj[q] = team_sum<L>(dj[q]);
+      if (q < D) dp[q] = team_sum<L>(dp[q]);
 #pragma unroll
       for (int k = 0; k < D; ++k) da[q][k] = team_sum<L>(da[q][k]);
     }
@@ -271,6 +279,7 @@ struct DiffAcc {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       gsum[(int64_t)(GS_DJB + q) * cap + j] = dj[q] * fsd;
+      gsum[(int64_t)(GS_DPI1 + q) * cap + j] = q < D ? dp[q] * isg : 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) gsum[(int64_t)(GS_DAB1 + 3 * q + k) * cap + j] = k < D ? da[q][k] * isg : 0.0;
     }

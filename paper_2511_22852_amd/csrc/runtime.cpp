@@ -50,6 +50,8 @@ bool validate_config(const ccake_config* c, std::string* why) {
     if (c->ncharge != 3) { *why = "diffusion needs ncharge 3"; return false; }
     if (!(c->tauJ_coeff > 0.0) || !std::isfinite(c->tauJ_coeff)) { *why = "tauJ_coeff must be > 0"; return false; }
     if (!std::isfinite(c->c_JJ)) { *why = "c_JJ must be finite"; return false; }
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(c->d_JPi[q])) { *why = "d_JPi must be finite"; return false; }
     for (int i = 0; i < 9; ++i)
       if (!std::isfinite(c->kappa_T2[i])) { *why = "kappa_T2 must be finite"; return false; }
   }
@@ -81,6 +83,7 @@ Params to_params(const ccake_config& c) {
   p.tauJ_coeff = c.diffusion ? c.tauJ_coeff : 1.0;
   p.c_JJ = c.diffusion ? c.c_JJ : 0.0;
   p.c_pisig = c.viscous ? c.c_pisig : 0.0;
+  for (int q = 0; q < 3; ++q) p.d_JPi[q] = (c.diffusion && c.viscous) ? c.d_JPi[q] : 0.0;
   p.cell_edge = 2.0 * c.h + c.skin;
   return p;
 }

@@ -277,6 +277,7 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
       }
       J0 /= gam;
       b.drec[(int64_t)(QD_AB + q) * cap + j] = th.mu[q] / th.T;
+      if (q == 0) b.drec[(int64_t)QD_PI * cap + j] = Pi;
 #pragma unroll
       for (int k = 0; k < D; ++k)
         b.drec[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] = (J[k] - (u[1 + k] / gam) * J0) * is2;
@@ -362,7 +363,8 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   GradAcc<D, VISC, MIXED> A;
   grad_setup<D, VISC, MIXED>(b, prm, Y, E.t + stage * E.dt, j, A);
   DiffAcc<D> DA;
-  if (DIFF) DA.init(b.drec, cap, j);
+  const bool with_pi = DIFF && (prm.d_JPi[0] != 0.0 || prm.d_JPi[1] != 0.0 || prm.d_JPi[2] != 0.0);
+  if (DIFF) DA.init(b.drec, cap, j, with_pi);
   const int team = (int)threadIdx.x / L;
   // the rows the density pass of this stage used for the same particle
   rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
@@ -399,11 +401,11 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
           bA[q][i] = (VISC && q < D && i < D) ? rb[(int64_t)(Q_A11 + q * 3 + i) * cap + m] : RT(0);
       }
       const RT bpp = rb[(int64_t)Q_PP * cap + m];
-      double ab[3], Fb[3][3];
-      if (DIFF) DiffAcc<D>::load(b.drec, cap, m, ab, Fb);
+      double ab[3], Fb[3][3], Pb = 0.0;
+      if (DIFF) DiffAcc<D>::load(b.drec, cap, m, ab, Fb, Pb, with_pi);
       if (ok[u]) {
         A.add(xb[u], d2[u], bpp, bA, bU, bV);
-        if (DIFF) DA.add(A.xa, xb[u], d2[u], A.ih, ab, Fb);
+        if (DIFF) DA.add(A.xa, xb[u], d2[u], A.ih, ab, Fb, Pb);
       }
     }
     if (!v[PAIR_U - 1]) break;
@@ -604,17 +606,18 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
   eom_solve<D, VISC>(prm, in, o);
   double dV[3][3], dNd[3] = {0.0, 0.0, 0.0};
   if (prm.diffusion) {
-    double V[3][3], dal[3][3], dF[3];
+    double V[3][3], dal[3][3], dF[3], dPi[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       dF[q] = b.gsum[(int64_t)(GS_DJB + q) * cap + j];
+      dPi[q] = q < D ? b.gsum[(int64_t)(GS_DPI1 + q) * cap + j] : 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         V[q][k] = k < D ? row(Y, cap, R_JB1 + 3 * q + k, j) : 0.0;
         dal[q][k] = k < D ? b.gsum[(int64_t)(GS_DAB1 + 3 * q + k) * cap + j] : 0.0;
       }
     }
-    diffusion_rates<D>(prm, in, o, V, dal, dF, dV, dNd);
+    diffusion_rates<D>(prm, in, o, V, dal, dPi, dF, dV, dNd);
   }
 
   double f[NROW];

@@ -17,6 +17,8 @@ pytestmark = pytest.mark.gpu
 
 DIFF = dict(kappa_T2=4 * np.asarray(((0.0482, -0.0482, 0.0), (-0.0482, 0.1447, 0.0147), (0.0, 0.0147, 0.0880))),
             tauJ_coeff=0.3, c_JJ=0.4)
+# with the ADNH coupling of the currents to the bulk-pressure gradient (eq. diffusion-evol)
+DIFF_PI = dict(DIFF, d_JPi=(0.2, -0.1, 0.05))
 
 
 @pytest.fixture(scope="module")
@@ -52,7 +54,7 @@ CASES = {
 }
 
 
-def case_state(O, B, name, precision=0, seed=5):
+def case_state(O, B, name, precision=0, seed=5, diffusion=DIFF):
     c = CASES[name]
     if c["dim"] == 2:
         w = I.lumpy_2d_workload(n_side=40, seed=seed, n_hot=10, radius=1.0, rhoB=0.005, rhoQ=0.002)
@@ -61,16 +63,18 @@ def case_state(O, B, name, precision=0, seed=5):
                                 rhoB=0.005, rhoQ=0.002)
     t0 = w.t0 if c["hyperbolic"] else 0.0
     prm, oe, cfg, ge = make(O, B, dim=c["dim"], hyperbolic=c["hyperbolic"], viscous=c["viscous"], ncharge=3,
-                            eos=c["eos"], h=w.h, precision=precision, diffusion=DIFF)
+                            eos=c["eos"], h=w.h, precision=precision, diffusion=diffusion)
     y = O.init(prm, oe, t0, w.xi, w.u, w.dens_kind, w.dens)
     y = perturb(O, y, c["dim"], c["viscous"], seed=seed + 1)
     y = with_currents(O, y, c["dim"], seed=seed + 2)
     return w, t0, prm, oe, cfg, ge, y
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_rate_parity(B, O, name):
-    w, t0, prm, oe, cfg, ge, y = case_state(O, B, name)
+@pytest.mark.parametrize("name,diff", [(n, DIFF) for n in CASES] +
+                         [(n, DIFF_PI) for n in ("2d_milne_viscous_table", "3d_milne_viscous_table")],
+                         ids=list(CASES) + ["2d_milne_viscous_table_dJPi", "3d_milne_viscous_table_dJPi"])
+def test_rate_parity(B, O, name, diff):
+    w, t0, prm, oe, cfg, ge, y = case_state(O, B, name, diffusion=diff)
     f_o, aux_o, bad = O.rhs(prm, oe, t0, y)
     assert bad == 0
     sim = B.Sim(cfg, ge, w.n)
@@ -90,9 +94,10 @@ def test_rate_parity(B, O, name):
     sim.close()
 
 
+@pytest.mark.parametrize("diff", [DIFF, DIFF_PI], ids=["kappa", "kappa_dJPi"])
 @pytest.mark.parametrize("name", ["2d_milne_viscous_table", "3d_milne_viscous_table"])
-def test_heun_step_parity(B, O, name):
-    w, t0, prm, oe, cfg, ge, y = case_state(O, B, name, seed=7)
+def test_heun_step_parity(B, O, name, diff):
+    w, t0, prm, oe, cfg, ge, y = case_state(O, B, name, seed=7, diffusion=diff)
     yo, _, bad = O.heun_step(prm, oe, t0, w.dt, y)
     assert bad == 0
     sim = B.Sim(cfg, ge, w.n)
@@ -106,8 +111,9 @@ def test_heun_step_parity(B, O, name):
     sim.close()
 
 
-def test_trajectory_and_totals(B, O):
-    w, t0, prm, oe, cfg, ge, y = case_state(O, B, "2d_milne_viscous_table", seed=9)
+@pytest.mark.parametrize("diff", [DIFF, DIFF_PI], ids=["kappa", "kappa_dJPi"])
+def test_trajectory_and_totals(B, O, diff):
+    w, t0, prm, oe, cfg, ge, y = case_state(O, B, "2d_milne_viscous_table", seed=9, diffusion=diff)
     n = 40
     _, yo, _ = O.evolve(prm, oe, t0, w.dt, n, y)
     sim = B.Sim(cfg, ge, w.n)
