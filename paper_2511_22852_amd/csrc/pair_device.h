@@ -207,14 +207,14 @@ struct GradAcc {
 //   d_k alpha_q = (1/sigma*_a) sum_b (alpha_b - alpha_a) d_k W_ab        (n = 1)
 //   divF_q      = sum_b (F_a/sigma*_a^2 + F_b/sigma*_b^2) . grad_a W_ab   (n = -1)
 // with alpha = mu/T and F = J - v J^0 (so the flux from a to b is minus the
-// flux from b to a).
-template <int D>
+// flux from b to a).  PI: also d_k Pi (the bulk-gradient coupling).
+template <int D, bool PI>
 struct DiffAcc {
   double al[3], Fa[3][3], Pa;
   double da[3][3], dj[3], dp[3];
 
-  __device__ __forceinline__ void init(const double* __restrict__ dr, int64_t cap, int64_t j, bool with_pi) {
-    Pa = with_pi ? dr[(int64_t)QD_PI * cap + j] : 0.0;
+  __device__ __forceinline__ void init(const double* __restrict__ dr, int64_t cap, int64_t j) {
+    Pa = PI ? dr[(int64_t)QD_PI * cap + j] : 0.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       al[q] = dr[(int64_t)(QD_AB + q) * cap + j];
@@ -228,11 +228,10 @@ struct DiffAcc {
     }
   }
 
-  // the neighbour's record: alpha_q, F^k_q / sigma*^2 and, when the
-  // bulk-gradient coupling is on (uniform over the grid), Pi
+  // the neighbour's record: alpha_q, F^k_q / sigma*^2 and (PI) Pi
   __device__ __forceinline__ static void load(const double* __restrict__ dr, int64_t cap, int32_t m, double ab[3],
-                                              double Fb[3][3], double& Pb, bool with_pi) {
-    Pb = with_pi ? dr[(int64_t)QD_PI * cap + m] : 0.0;
+                                              double Fb[3][3], double& Pb) {
+    Pb = PI ? dr[(int64_t)QD_PI * cap + m] : 0.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       ab[q] = dr[(int64_t)(QD_AB + q) * cap + m];
@@ -249,9 +248,11 @@ struct DiffAcc {
     double dW[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) dW[k] = k < D ? f * (xa[k] - xb[k]) : 0.0;
-    const double dPb = Pb - Pa;
+    if (PI) {
+      const double dPb = Pb - Pa;
 #pragma unroll
-    for (int k = 0; k < D; ++k) dp[k] += dPb * dW[k];
+      for (int k = 0; k < D; ++k) dp[k] += dPb * dW[k];
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const double dal = ab[q] - al[q];
@@ -268,7 +269,7 @@ struct DiffAcc {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       dj[q] = team_sum<L>(dj[q]);
-      if (q < D) dp[q] = team_sum<L>(dp[q]);
+      if (PI && q < D) dp[q] = team_sum<L>(dp[q]);
 #pragma unroll
       for (int k = 0; k < D; ++k) da[q][k] = team_sum<L>(da[q][k]);
     }
@@ -279,7 +280,7 @@ struct DiffAcc {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       gsum[(int64_t)(GS_DJB + q) * cap + j] = dj[q] * fsd;
-      gsum[(int64_t)(GS_DPI1 + q) * cap + j] = q < D ? dp[q] * isg : 0.0;
+      gsum[(int64_t)(GS_DPI1 + q) * cap + j] = (PI && q < D) ? dp[q] * isg : 0.0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) gsum[(int64_t)(GS_DAB1 + 3 * q + k) * cap + j] = k < D ? da[q][k] * isg : 0.0;
     }

@@ -344,7 +344,7 @@ __device__ __forceinline__ void grad_setup(const BatchDev& b, const Params& prm,
 }
 
 // DIFF: also the BSQ diffusion sums (DiffAcc) over the same accepted pairs
-template <int D, bool VISC, bool MIXED, bool DIFF>
+template <int D, bool VISC, bool MIXED, int DIFF>
 __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
                                               int64_t nslots) {
   constexpr int L = Team<D>::L;
@@ -362,9 +362,8 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   const double r2max = (2.0 * prm.h) * (2.0 * prm.h);
   GradAcc<D, VISC, MIXED> A;
   grad_setup<D, VISC, MIXED>(b, prm, Y, E.t + stage * E.dt, j, A);
-  DiffAcc<D> DA;
-  const bool with_pi = DIFF && (prm.d_JPi[0] != 0.0 || prm.d_JPi[1] != 0.0 || prm.d_JPi[2] != 0.0);
-  if (DIFF) DA.init(b.drec, cap, j, with_pi);
+  DiffAcc<D, DIFF == 2> DA;
+  if (DIFF) DA.init(b.drec, cap, j);
   const int team = (int)threadIdx.x / L;
   // the rows the density pass of this stage used for the same particle
   rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
@@ -402,7 +401,7 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       }
       const RT bpp = rb[(int64_t)Q_PP * cap + m];
       double ab[3], Fb[3][3], Pb = 0.0;
-      if (DIFF) DiffAcc<D>::load(b.drec, cap, m, ab, Fb, Pb, with_pi);
+      if (DIFF) DiffAcc<D, DIFF == 2>::load(b.drec, cap, m, ab, Fb, Pb);
       if (ok[u]) {
         A.add(xb[u], d2[u], bpp, bA, bU, bV);
         if (DIFF) DA.add(A.xa, xb[u], d2[u], A.ih, ab, Fb, Pb);
@@ -789,10 +788,13 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
   else
     CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 0>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux);
   if (!rates) return;
-  if (prm.diffusion)
-    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, true>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
+  // diffusion sums: 1 without, 2 with the bulk-pressure gradient
+  if (prm.diffusion && (prm.d_JPi[0] != 0.0 || prm.d_JPi[1] != 0.0 || prm.d_JPi[2] != 0.0))
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 2>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
+  else if (prm.diffusion)
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 1>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
   else
-    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, false>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 0>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
   // diagnostic evaluations only (never profiled)
   if (aux) hipLaunchKernelGGL((k_fo_grad<D>), dim3(gp), dim3(128), 0, s, b, prm, Y, nslots);
   CCAKE_STAGE_LAUNCH(em, (k_eom<D, VISC>), dim3(gp), dim3(128), b, prm, Y, stage, mode, nslots, fout, aux);
