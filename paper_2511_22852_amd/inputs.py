@@ -81,6 +81,26 @@ def gubser_ideal(tau, x, y, q=1.0, That0=None, e_ref_GeV=10.0):
     return e, ux, uy
 
 
+def shifted_gubser_ideal(tau, x, y, eta, t_shift=0.5, q=1.0, e_ref_GeV=80.0):
+    """Ideal Gubser flow translated in Minkowski time, t -> t + t_shift
+    ("Code validation", eqs. tau_prime, eta_prime and
+    shifted_viscous_Gubser_e, _ur, _utau, _ueta): with
+    tau' = sqrt(tau^2 + 2 t_shift tau cosh(eta) + t_shift^2),
+        e = e_G(tau', r),  u^r = u^r_G(tau', r),
+        u^eta = -u^tau_G(tau', r) t_shift sinh(eta) / (tau tau').
+    The Gubser solution is normalised so that e_G(tau' = 1 fm, r = 0) =
+    e_ref_GeV GeV/fm^3, i.e. the shifted one has that value at
+    (tau, r, eta) = (1 fm - t_shift, 0, 0), the paper's normalisation point
+    for t_shift = 0.5 fm.  Returns e [fm^-4] and (u^x, u^y, u^eta)."""
+    taup = np.sqrt(tau * tau + 2.0 * t_shift * tau * np.cosh(eta) + t_shift * t_shift)
+    e, ux, uy = gubser_ideal(taup, x, y, q=q, e_ref_GeV=e_ref_GeV)
+    r2 = x * x + y * y
+    den = np.sqrt(1.0 + 2.0 * q * q * (taup * taup + r2) + q ** 4 * (taup * taup - r2) ** 2)
+    utau_g = (1.0 + q * q * (taup * taup + r2)) / den
+    ueta = -utau_g * t_shift * np.sinh(eta) / (tau * taup)
+    return e, ux, uy, ueta
+
+
 @dataclass
 class Workload:
     """A ready-to-run particle set: positions (D, n), flow u^i (D, n),
@@ -115,6 +135,22 @@ def gubser_workload(n_side=51, spacing=0.2, h=0.3, hyperbolic=True, t0=1.0, dt=0
     dens[0] = e
     return Workload("gubser_2d", 2, hyperbolic, xi, np.stack([ux, uy]), dens, 1, t0, dt,
                     int(round((t_end - t0) / dt)), h, False, 0)
+
+
+def shifted_gubser_workload(spacing=0.2, deta=0.2, h=0.3, half_xy=3.2, half_eta=1.6, t0=1.0, dt=0.01,
+                            t_end=1.4, t_shift=0.5):
+    """3+1D lattice in (x, y, eta) with the ideal shifted-Gubser state at
+    tau0 = 1 fm (t_shift = 0.5 fm, q = 1/fm, e_G(tau' = 1, 0) = 80 GeV/fm^3,
+    the paper's "Code validation" set-up on a smaller box and a coarser
+    lattice); conformal EoS f* = 11, ideal, no charges."""
+    nxy = int(round(2 * half_xy / spacing)) + 1
+    neta = int(round(2 * half_eta / deta)) + 1
+    xi = lattice((nxy, nxy, neta), (spacing, spacing, deta), (-half_xy, -half_xy, -half_eta))
+    e, ux, uy, ueta = shifted_gubser_ideal(t0, xi[0], xi[1], xi[2], t_shift=t_shift)
+    dens = np.zeros((4, xi.shape[1]))
+    dens[0] = e
+    return Workload("shifted_gubser_3d", 3, True, xi, np.stack([ux, uy, ueta]), dens, 1, t0, dt,
+                    int(round((t_end - t0) / dt)), h, False, 0, extra=dict(t_shift=t_shift))
 
 
 # ---------------------------------------------------------------------------
