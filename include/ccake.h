@@ -325,6 +325,15 @@ ccake_status ccake_totals(ccake_sim* sim, double* out, ccake_counters* cnt);
  * the total (pairs beyond cap are counted but not written).  Synchronises.  */
 ccake_status ccake_debug_pairs(ccake_sim* sim, int64_t cap, int32_t* a, int32_t* b, int64_t* npairs);
 
+/* Test support: the pairs that the density pass of the next step accepts,
+ * exported by that pass itself (the same kernel, neighbour tiles and pair
+ * test) at the current positions through the neighbour rows of the last
+ * binning, without binning again ("Neighbor search" and the kernel support
+ * of "Kernel function": |x_a - x_b|^2 < (2h)^2, self included).  Same output
+ * convention as ccake_debug_pairs.  CCAKE_E_STATE when the next step bins
+ * first (right after initialisation or a state upload).  Synchronises.      */
+ccake_status ccake_debug_pairs_cached(ccake_sim* sim, int64_t cap, int32_t* a, int32_t* b, int64_t* npairs);
+
 ccake_status ccake_destroy(ccake_sim* sim);
 
 /* ------------------------------------------------------------ serving ---- */

@@ -36,10 +36,12 @@ KAPPA_T2_BSQ = ((0.0482, -0.0482, 0.0), (-0.0482, 0.1447, 0.0147), (0.0, 0.0147,
 
 EXPORTS = [
     "ccake_eos_create_conformal", "ccake_eos_create_gas", "ccake_eos_create_table",
-    "ccake_eos_destroy", "ccake_eos_invert", "ccake_eos_build_inverted", "ccake_eos_offline_eval",
+    "ccake_eos_destroy", "ccake_eos_invert", "ccake_eos_build_inverted",
+    "ccake_eos_offline_eval",
     "ccake_workspace_bytes", "ccake_create",
     "ccake_init_particles", "ccake_set_state", "ccake_get_state", "ccake_time", "ccake_step",
     "ccake_check", "ccake_set_sources", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
+    "ccake_debug_pairs_cached",
     "ccake_destroy", "ccake_server_create", "ccake_server_submit", "ccake_server_poll",
     "ccake_server_drain", "ccake_server_release", "ccake_server_stats", "ccake_server_destroy",
     "ccake_last_error",
@@ -149,6 +151,7 @@ def lib():
             "ccake_read": [vp, i32, vp, i32],
             "ccake_totals": [vp, dp, ctypes.POINTER(Counters)],
             "ccake_debug_pairs": [vp, i64, vp, vp, ctypes.POINTER(i64)],
+            "ccake_debug_pairs_cached": [vp, i64, vp, vp, ctypes.POINTER(i64)],
             "ccake_destroy": [vp],
             "ccake_server_create": [ctypes.POINTER(vp), ctypes.POINTER(Config), vp, ctypes.c_size_t, i64, i32,
                                     dbl, vp],
@@ -245,9 +248,9 @@ class Eos:
         out = torch.empty_like(x)
         it = torch.empty(n, dtype=torch.int32, device=device)
         stream = torch.cuda.current_stream(device)
-        _check(lib().ccake_eos_invert(self.h, mode, ncharge, n, ctypes.c_void_p(x.data_ptr()),
-                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(it.data_ptr()),
-                                      ctypes.c_void_p(stream.cuda_stream)), self.h)
+        fn = lib().ccake_eos_invert
+        _check(fn(self.h, mode, ncharge, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                  ctypes.c_void_p(it.data_ptr()), ctypes.c_void_p(stream.cuda_stream)), self.h)
         return out.cpu().numpy(), it.cpu().numpy()
 
     def build_inverted(self, ncharge, decade_lo, decade_hi, per_decade, nx=(2, 2, 2), x_lo=(0.0, 0.0, 0.0),
@@ -386,15 +389,18 @@ class Sim:
                                   ctypes.byref(cnt)), self.h)
         return out, cnt
 
-    def pairs(self):
-        """Neighbour pairs (a, b) sorted by (a, b)."""
+    def pairs(self, cached=False):
+        """Neighbour pairs (a, b) sorted by (a, b); cached: the pairs the next
+        step's density pass accepts through the last binning's rows
+        (ccake_debug_pairs_cached), else those of a fresh binning."""
         import torch
+        fn = lib().ccake_debug_pairs_cached if cached else lib().ccake_debug_pairs
         cnt = ctypes.c_int64()
-        _check(lib().ccake_debug_pairs(self.h, 0, None, None, ctypes.byref(cnt)), self.h)
+        _check(fn(self.h, 0, None, None, ctypes.byref(cnt)), self.h)
         a = torch.empty(max(cnt.value, 1), dtype=torch.int32, device=self.device)
         b = torch.empty_like(a)
-        _check(lib().ccake_debug_pairs(self.h, cnt.value, ctypes.c_void_p(a.data_ptr()),
-                                       ctypes.c_void_p(b.data_ptr()), ctypes.byref(cnt)), self.h)
+        _check(fn(self.h, cnt.value, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                  ctypes.byref(cnt)), self.h)
         a = a[:cnt.value].cpu().numpy().astype(np.int64)
         b = b[:cnt.value].cpu().numpy().astype(np.int64)
         order = np.lexsort((b, a))

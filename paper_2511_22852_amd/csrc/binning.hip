@@ -15,6 +15,8 @@
 //            sorted by x^1; clears the counts for the next binning
 //   k_permute gather of the state, warm starts, ids and keys into cell order,
 //            and the binning-time x^1 of every slot
+//   k_rows   every slot's neighbour rows, cut to the x^1 interval its
+//            particle can reach before the next binning
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,9 +99,6 @@ __global__ void k_grid(BatchDev b, Params prm, int dim) {
   E->backup = 0;
   E->newton_iters = 0;
   if (!E->active || !E->rebin) return;
-  // a batch-wide serial per binning: row bounds cached per slot are valid
-  // while the slot's stamp equals its event's serial
-  E->bin_serial = atomicAdd(b.serial, 1u) + 1u;
   double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
   bool empty = false;
   for (int k = 0; k < dim; ++k) {
@@ -117,20 +116,28 @@ __global__ void k_grid(BatchDev b, Params prm, int dim) {
     if (E->n > 0) E->capacity_err += 1;  // every coordinate non-finite
   }
   double edge = prm.cell_edge / SUBCELLS;
-  int64_t nc[3] = {1, 1, 1}, tot = 1;
-  // coarsen the grid (never below the cutoff) until it fits the capacity
-  for (int it = 0; it < 64; ++it) {
-    tot = 1;
-    for (int k = 0; k < dim; ++k) {
-      nc[k] = (int64_t)floor((hi[k] - lo[k]) / edge) + 1;
-      tot *= nc[k];
+  int64_t nc[3] = {1, 1, 1};
+  bool fits = false;
+  // coarsen the grid (never below the cutoff) until it fits the capacity;
+  // cell counts in FP64 so that no extent overflows an integer
+  for (int it = 0; it < 64 && !fits; ++it) {
+    double tot = 1.0;
+    for (int k = 0; k < dim; ++k) tot *= floor((hi[k] - lo[k]) / edge) + 1.0;
+    if (tot + 1.0 <= (double)E->c_cap) {
+      fits = true;
+    } else {
+      edge *= 1.25;
     }
-    if (tot + 1 <= E->c_cap) break;
-    edge *= 1.25;
   }
-  if (tot + 1 > E->c_cap) {
+  if (fits) {
+    for (int k = 0; k < dim; ++k) nc[k] = (int64_t)floor((hi[k] - lo[k]) / edge) + 1;
+  } else {
+    // one cell that covers the whole event: the pair sums stay complete
+    // (every particle is a candidate of every other), the event is flagged
     E->capacity_err += 1;
-    for (int k = 0; k < 3; ++k) nc[k] = 1;
+    double ext = 0.0;
+    for (int k = 0; k < dim; ++k) ext = fmax(ext, hi[k] - lo[k]);
+    edge = ext + prm.cell_edge;
   }
   for (int k = 0; k < 3; ++k) {
     E->lo[k] = lo[k];
@@ -343,6 +350,30 @@ __global__ void __launch_bounds__(256) k_permute(BatchDev b, int64_t nslots, uin
   }
 }
 
+// Neighbour rows of every slot of the events this step bins, at the
+// binning-time positions (team_rows: a team of ROW_TEAM lanes per slot), for
+// the pair kernels of every stage until the next binning.
+constexpr int ROW_TEAM = 16;
+
+template <int D>
+__global__ void __launch_bounds__(256) k_rows(BatchDev b, Params prm, int64_t nslots) {
+  constexpr int ROWS = RowBlock<D>::ROWS;
+  constexpr int PER_BLOCK = 256 / ROW_TEAM;
+  __shared__ int32_t s_lo[PER_BLOCK][ROWS], s_hi[PER_BLOCK][ROWS];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = tid / ROW_TEAM;
+  const int lane = (int)(tid % ROW_TEAM), team = (int)threadIdx.x / ROW_TEAM;
+  // a team lies inside one wave and leaves as a whole
+  if (j >= nslots) return;
+  const int e = b.ev[j];
+  if (e < 0 || !b.evt[e].rebin) return;
+  const EventDev& E = b.evt[e];
+  const int64_t cap = b.cap;
+  const double xa[3] = {row(b.Ys, cap, R_X1, j), row(b.Ys, cap, R_X2, j), D == 3 ? row(b.Ys, cap, R_X3, j) : 0.0};
+  team_rows<D, ROW_TEAM>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
+  rows_keep<D, ROW_TEAM>(b, j, lane, s_lo[team], s_hi[team]);
+}
+
 // sorted -> home (after an initialisation)
 __global__ void __launch_bounds__(256) k_commit(BatchDev b, int64_t nslots, uint32_t rowmask) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -409,6 +440,10 @@ hipError_t launch_bin(const BatchDev& b, const Params& prm, int nevents, int64_t
   const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(512, nslots / (nevents * 64) + 1));
   hipLaunchKernelGGL(k_cellsort, dim3(gx, nevents), dim3(256), 0, s, b, prm.dim);
   hipLaunchKernelGGL(k_permute, dim3(blocks_of(nslots, 256)), dim3(256), 0, s, b, nslots, rowmask);
+  if (prm.dim == 3)
+    hipLaunchKernelGGL(k_rows<3>, dim3(blocks_of(nslots * ROW_TEAM, 256)), dim3(256), 0, s, b, prm, nslots);
+  else
+    hipLaunchKernelGGL(k_rows<2>, dim3(blocks_of(nslots * ROW_TEAM, 256)), dim3(256), 0, s, b, prm, nslots);
   if (marks) (void)hipEventRecord(marks[1], s);
   return hipGetLastError();
 }

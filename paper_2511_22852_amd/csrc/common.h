@@ -112,8 +112,8 @@ struct SourceSet {
 #endif
 constexpr int SUBCELLS = CCAKE_SUBCELLS;
 // the first and last candidate slots of a particle's neighbour rows
-// ((2*SUBCELLS + 1) rows in 2+1D, (2*SUBCELLS + 1)^2 in 3+1D), searched at the
-// first density pass after a binning and reused until the next binning
+// ((2*SUBCELLS + 1) rows in 2+1D, (2*SUBCELLS + 1)^2 in 3+1D), searched by
+// each binning at the binning-time positions and used until the next binning
 constexpr int ROW_CACHE = 2 * (2 * SUBCELLS + 1) * (2 * SUBCELLS + 1);
 
 struct Params {
@@ -152,8 +152,8 @@ struct EventDev {
   uint32_t newton_iters; // total Newton iterations (last stage)
   int32_t rebin;      // this step bins the event (else it keeps its cells and order)
   int32_t need_bin;   // the next step must bin (fresh state)
-  uint32_t bin_serial;// batch-wide serial of this event's last binning (0: none yet)
-  int32_t pad_bs;
+  int32_t tile0;      // first workgroup of the event in the pair kernels' grid
+  int32_t pad_t;
   double disp;        // displacement bound sum(dt max(1, 1/x0)) since the last binning
   // bounding-box accumulators of the next binning: order-preserving integer
   // images of the coordinates (reset to the empty box after every use)
@@ -200,9 +200,7 @@ struct BatchDev {
   int32_t* keys;     // local cell key (sorted order)
   int32_t* perm;     // sorted slot -> home slot
   double* xbin;      // x^1 of each slot at its event's last binning (sorted order)
-  int32_t* rows;     // [ROW_CACHE][cap] row bounds (lo, hi per row), valid for one binning
-  uint32_t* rowstamp;// [cap] bin_serial of the binning the slot's rows belong to (~0: none)
-  uint32_t* serial;  // batch-wide binning counter
+  int32_t* rows;     // [ROW_CACHE][cap] row bounds (lo, hi per row), written by each binning
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

@@ -23,6 +23,10 @@ hipError_t launch_bin_only(const BatchDev& b, int e, hipStream_t s);
 hipError_t launch_commit(const BatchDev& b, int64_t nslots, uint32_t rowmask, hipStream_t s);
 hipError_t launch_pairs(const BatchDev& b, const Params& prm, int e, int64_t n, int64_t* counter, int64_t cap,
                         int32_t* pa, int32_t* pb, hipStream_t s);
+// the pairs the density pass accepts on the state b.Ys through the slots'
+// neighbour rows of the last binning (no binning), original ids
+hipError_t launch_pairs_cached(const BatchDev& b, const Params& prm, int64_t nslots, int64_t* counter,
+                               int64_t cap, int32_t* pa, int32_t* pb, hipStream_t s);
 hipError_t launch_unsort(const BatchDev& b, int e, int64_t n, uint32_t rowmask, double* out, hipStream_t s);
 hipError_t launch_upload(const BatchDev& b, int e, int64_t n, const double* in, int nrows, hipStream_t s);
 hipError_t launch_totals(const BatchDev& b, const Params& prm, int nevents, double* out, hipStream_t s);

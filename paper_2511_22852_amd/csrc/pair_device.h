@@ -1,8 +1,8 @@
 // Per-pair arithmetic of the SPH sums of the pair kernels (one team of lanes
-// per particle, candidates read from global memory, any batch).  Every lane
-// visits its candidates in a fixed order and the lanes are merged with a
-// fixed order (through LDS, lane by lane), so results do not depend on the
-// batch or the launch.
+// per particle, candidates staged in LDS, any batch).  Every lane visits its
+// candidates in a fixed order and the lanes are merged with a fixed order
+// (through LDS, lane by lane), so results do not depend on the batch or the
+// launch.  Rejected candidates enter with a zero kernel weight (no branch).
 // Floating-point contraction is off on the whole pair path and the fused
 // multiply-adds are written out.
 //
@@ -34,28 +34,6 @@ __device__ __forceinline__ double team_sum(double v) {
   return v;
 }
 
-// FP64 team sums through LDS: lane k of the team stores its NV partials at
-// buf[k * NV + v]; after a wavefront barrier (a team lies inside one wave)
-// lane v < NV adds value v of the L lanes in lane order and returns it (the
-// other lanes return 0).  One store and L loads and adds per lane instead of
-// log2(L) dependent cross-lane exchanges per value.
-template <int L, int NV>
-__device__ __forceinline__ double team_sums_lds(double* __restrict__ buf, int lane, const double (&v)[NV]) {
-#pragma clang fp contract(off)
-  static_assert(NV <= L, "one value per lane");
-#pragma unroll
-  for (int q = 0; q < NV; ++q) buf[lane * NV + q] = v[q];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  double acc = 0.0;
-  if (lane < NV) {
-#pragma unroll
-    for (int k = 0; k < L; ++k) acc += buf[k * NV + lane];
-  }
-  return acc;
-}
-
 // ---------------------------------------------------------------------------
 // NS smoothed scalars per neighbour: 0 (specific densities: sigma* only),
 // 1 (s*), 4 (s*, n*_B, n*_S, n*_Q)
@@ -76,21 +54,46 @@ struct DensAcc {
     nnb = 0;
   }
 
-  // one accepted pair at squared distance d2 with the neighbour's scalars v
-  // (S, N_B, N_S, N_Q; the first NS are used)
-  __device__ __forceinline__ void add(double d2, double ih, const double v[4]) {
+  // U candidates at squared distances d2[u] with the neighbours' scalars
+  // v[u] (S, N_B, N_S, N_Q; the first NS are used) in the precision of the
+  // sums; those with ok[u] false (rejected or missing) enter with weight
+  // zero.  FP32: the U terms of each sum are added together first and the
+  // block total is added with compensation, so the error stays below
+  // (U + 1) u sum |terms| + O(n u^2) however many candidates there are
+  // (u = 2^-24).  FP64: plain fused multiply-adds.
+  template <int U, class T>
+  __device__ __forceinline__ void add_block(const bool (&ok)[U], const double (&d2)[U], double ih,
+                                            const T (&v)[U][4]) {
 #pragma clang fp contract(off)
-    ++nnb;
+#pragma unroll
+    for (int u = 0; u < U; ++u) nnb += ok[u] ? 1 : 0;
     if (MIXED) {
-      const float W = spline_wf(fast_sqrtf((float)d2) * (float)ih);
-      ks.add(W);
+      float W[U];
 #pragma unroll
-      for (int q = 0; q < NS; ++q) kv[q].add_prod((float)v[q], W);
+      for (int u = 0; u < U; ++u) {
+        const float w = spline_wf(fast_sqrtf((float)d2[u]) * (float)ih);
+        W[u] = ok[u] ? w : 0.0f;
+      }
+      float ws = W[0];
+#pragma unroll
+      for (int u = 1; u < U; ++u) ws += W[u];
+      ks.add(ws);
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        float ps = (float)v[0][q] * W[0];
+#pragma unroll
+        for (int u = 1; u < U; ++u) ps = fmaf((float)v[u][q], W[u], ps);
+        kv[q].add(ps);
+      }
     } else {
-      const double W = spline_w(sqrt(d2) * ih);
-      ss += W;
 #pragma unroll
-      for (int q = 0; q < NS; ++q) sv[q] = fma(v[q], W, sv[q]);
+      for (int u = 0; u < U; ++u) {
+        const double w = spline_w(sqrt(d2[u]) * ih);
+        const double W = ok[u] ? w : 0.0;
+        ss += W;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) sv[q] = fma((double)v[u][q], W, sv[q]);
+      }
     }
   }
 
@@ -127,63 +130,90 @@ struct GradAcc {
     }
   }
 
-  // one accepted pair: neighbour position xb at squared distance d2 and its
-  // record (p+Pi)/sigma*^2, A^{ji}/sigma*^2 ([j][i]), u, v
-  __device__ __forceinline__ void add(const double xb[3], double d2, RT bpp, const RT bA[3][3], const RT bU[3],
-                                      const RT bV[3]) {
+  // U candidates at positions xb[u] and squared distances d2[u] with their
+  // records r[u] = (p+Pi)/sigma*^2, u^1..u^D, v^1..v^D, A^{ji}/sigma*^2
+  // (j*D + i) in the precision of the sums; a candidate is a pair when
+  // ok[u] (which must exclude the self pair, whose kernel gradient is zero),
+  // otherwise it enters with weight zero.  FP32: the U terms of each sum are
+  // added together before the compensated addition (error below
+  // (U + 1) u sum |terms| + O(n u^2), as for the density sums).
+  template <int U>
+  __device__ __forceinline__ void add_block(const bool (&ok)[U], const double (&xb)[U][3], const double (&d2)[U],
+                                            const RT (*r)[4 * ((1 + 2 * D + (VISC ? D * D : 0) + 3) / 4)]) {
 #pragma clang fp contract(off)
     if (MIXED) {
-      const float d2f = (float)d2;
-      if (!(d2f > 0.0f)) return;  // self pair: grad W = 0
-      const float ir = fast_rsqf(d2f);
-      const float f = spline_dwf(d2f * ir * (float)ih) * ir;
-      float dW[3];
+      float dW[U][3];
 #pragma unroll
-      for (int q = 0; q < D; ++q) dW[q] = (float)(xa[q] - xb[q]) * f;
-      const float pp = (float)aPP + (float)bpp;
+      for (int u = 0; u < U; ++u) {
+        const float d2f = (float)d2[u];
+        const float ir = fast_rsqf(d2f);
+        float f = spline_dwf(d2f * ir * (float)ih) * ir;
+        f = ok[u] ? f : 0.0f;
+#pragma unroll
+        for (int q = 0; q < D; ++q) dW[u][q] = (float)(xa[q] - xb[u][q]) * f;
+      }
+      // forces: (p+Pi) terms and, viscous, G_i sum_j (A_a + A_b)^{ji} d_j W
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        if (VISC) {
-          float vis = 0.f;
+        float acc = 0.f;
 #pragma unroll
-          for (int jj = 0; jj < D; ++jj) vis = fmaf((float)aA[jj][i] + (float)bA[jj][i], dW[jj], vis);
-          kF[i].add(fmaf((float)Gk[i + 1], vis, pp * dW[i]));
-        } else {
-          kF[i].add_prod(pp, dW[i]);
+        for (int u = 0; u < U; ++u) {
+          const float pp = (float)aPP + (float)r[u][0];
+          float term = pp * dW[u][i];
+          if (VISC) {
+            float vis = 0.f;
+#pragma unroll
+            for (int jj = 0; jj < D; ++jj)
+              vis = fmaf((float)aA[jj][i] + (float)r[u][1 + 2 * D + jj * D + i], dW[u][jj], vis);
+            term = fmaf((float)Gk[i + 1], vis, term);
+          }
+          acc = u == 0 ? term : acc + term;
         }
+        kF[i].add(acc);
       }
+      // velocity gradients and divergence (n = 1 differences)
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk)
+#pragma unroll
+        for (int nu = 0; nu < D; ++nu) {
+          float acc = ((float)r[0][1 + nu] - (float)aU[nu]) * dW[0][kk];
+#pragma unroll
+          for (int u = 1; u < U; ++u) acc = fmaf((float)r[u][1 + nu] - (float)aU[nu], dW[u][kk], acc);
+          kdu[kk][nu].add(acc);
+        }
       float dvv = 0.f;
 #pragma unroll
-      for (int kk = 0; kk < D; ++kk) {
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int nu = 0; nu < D; ++nu) kdu[kk][nu].add_prod((float)bU[nu] - (float)aU[nu], dW[kk]);
-        dvv = fmaf((float)bV[kk] - (float)aV[kk], dW[kk], dvv);
-      }
+        for (int kk = 0; kk < D; ++kk) dvv = fmaf((float)r[u][1 + D + kk] - (float)aV[kk], dW[u][kk], dvv);
       kdv.add(dvv);
     } else {
-      const double rr = sqrt(d2);
-      if (!(rr > 0.0)) return;
-      const double f = spline_dw(rr * ih) / rr;
-      double dW[3];
 #pragma unroll
-      for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[q]) * f;
-      const double pp = aPP + (double)bpp;
+      for (int u = 0; u < U; ++u) {
+        const double rr = sqrt(d2[u]);
+        double f = spline_dw(rr * ih) / rr;
+        f = ok[u] ? f : 0.0;
+        double dW[3];
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        if (VISC) {
-          double vis = 0.0;
+        for (int q = 0; q < D; ++q) dW[q] = (xa[q] - xb[u][q]) * f;
+        const double pp = aPP + (double)r[u][0];
 #pragma unroll
-          for (int jj = 0; jj < D; ++jj) vis = fma(aA[jj][i] + (double)bA[jj][i], dW[jj], vis);
-          F[i] += fma(Gk[i + 1], vis, pp * dW[i]);
-        } else {
-          F[i] = fma(pp, dW[i], F[i]);
+        for (int i = 0; i < D; ++i) {
+          if (VISC) {
+            double vis = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < D; ++jj) vis = fma(aA[jj][i] + (double)r[u][1 + 2 * D + jj * D + i], dW[jj], vis);
+            F[i] += fma(Gk[i + 1], vis, pp * dW[i]);
+          } else {
+            F[i] = fma(pp, dW[i], F[i]);
+          }
         }
-      }
 #pragma unroll
-      for (int kk = 0; kk < D; ++kk) {
+        for (int kk = 0; kk < D; ++kk) {
 #pragma unroll
-        for (int nu = 0; nu < D; ++nu) du[kk][nu] = fma((double)bU[nu] - aU[nu], dW[kk], du[kk][nu]);
-        dv = fma((double)bV[kk] - aV[kk], dW[kk], dv);
+          for (int nu = 0; nu < D; ++nu) du[kk][nu] = fma((double)r[u][1 + nu] - aU[nu], dW[kk], du[kk][nu]);
+          dv = fma((double)r[u][1 + D + kk] - aV[kk], dW[kk], dv);
+        }
       }
     }
   }

@@ -140,8 +140,6 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.perm = take(&o, I4 * cap);
   L.xbin = take(&o, D8 * cap);
   L.rows = take(&o, I4 * ROW_CACHE * cap);
-  L.rowstamp = take(&o, I4 * cap);
-  L.serial = take(&o, I4);
   L.cs = take(&o, I4 * (ccap + 1));
   L.cf = take(&o, I4 * (ccap + 1));
   L.evt = take(&o, sizeof(EventDev) * nev);
@@ -172,8 +170,6 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.perm = (int32_t*)(base + L.perm);
   b.xbin = (double*)(base + L.xbin);
   b.rows = (int32_t*)(base + L.rows);
-  b.rowstamp = (uint32_t*)(base + L.rowstamp);
-  b.serial = (uint32_t*)(base + L.serial);
   b.cell_start = (int32_t*)(base + L.cs);
   b.cell_fill = (int32_t*)(base + L.cf);
   b.evt = (EventDev*)(base + L.evt);
@@ -408,9 +404,6 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
   hipError_t he = hipMemcpy(s->b.ev, ev.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (ccap + 1));
   if (he == hipSuccess) he = hipMemset(s->base + L.src, 0, sizeof(SourceSet));
-  // no slot has rows of a binning yet; binnings are numbered from 1
-  if (he == hipSuccess) he = hipMemset(s->b.rowstamp, 0xFF, sizeof(uint32_t) * n);
-  if (he == hipSuccess) he = hipMemset(s->b.serial, 0, sizeof(uint32_t));
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) {
     ccake_destroy(s);
@@ -812,6 +805,27 @@ extern "C" ccake_status ccake_debug_pairs(ccake_sim* s, int64_t cap, int32_t* a,
   s->need_bin = true;
   HIPCHK(s, hipMemsetAsync(counter, 0, sizeof(int64_t), s->stream));
   HIPCHK(s, launch_pairs(s->b, s->prm, 0, s->n, counter, cap, a, b, s->stream));
+  HIPCHK(s, hipMemcpyAsync(npairs, counter, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return CCAKE_OK;
+}
+
+extern "C" ccake_status ccake_debug_pairs_cached(ccake_sim* s, int64_t cap, int32_t* a, int32_t* b,
+                                                int64_t* npairs) {
+  if (!s) return CCAKE_E_ARG;
+  if (!npairs || cap < 0 || (cap > 0 && (!a || !b)))
+    return fail(s, CCAKE_E_ARG, "ccake_debug_pairs_cached: bad arguments");
+  if (!s->initialised) return fail(s, CCAKE_E_STATE, "not initialised");
+  if (s->need_bin) return fail(s, CCAKE_E_STATE, "no binning to reuse: the next step bins first");
+  int64_t* counter = (int64_t*)(s->base + s->L.scratch);
+  // the view of a step that keeps its binning: the home arrays are in the
+  // cell order of the last binning
+  BatchDev v = s->b;
+  v.Ys = v.Y0;
+  v.warms = v.warm;
+  v.ids = v.id;
+  HIPCHK(s, hipMemsetAsync(counter, 0, sizeof(int64_t), s->stream));
+  HIPCHK(s, launch_pairs_cached(v, s->prm, s->n, counter, cap, a, b, s->stream));
   HIPCHK(s, hipMemcpyAsync(npairs, counter, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   return CCAKE_OK;

@@ -216,6 +216,9 @@ static void finish_event(ccake_server* s, int e, ccake_status status) {
   if (he != hipSuccess) res.status = CCAKE_E_HIP;
   else if (res.status == CCAKE_OK && E.nonfinite) res.status = CCAKE_E_NONFINITE;
   else if (res.status == CCAKE_OK && E.noconv) res.status = CCAKE_E_EOS_NOCONV;
+  // a grid that no longer covers the event (coarsened to one cell, or no
+  // finite coordinate) drops candidates: the result is not to be used
+  else if (res.status == CCAKE_OK && E.capacity_err) res.status = CCAKE_E_CAPACITY;
   for (int64_t i = 0; i < r.n; ++i) {
     res.totals[0] += res.state[(size_t)R_S * r.n + i];
     for (int q = 0; q < 3; ++q) res.totals[1 + q] += res.state[(size_t)(R_NB + q) * r.n + i];
@@ -364,9 +367,6 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
   (void)hipMemset(s->b.ev, 0xFF, sizeof(int32_t) * max_particles);
   (void)hipMemset(s->b.evt, 0, sizeof(EventDev) * max_events);
   (void)hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (s->ccap + 1));
-  // no slot has rows of a binning yet; binnings are numbered from 1
-  (void)hipMemset(s->b.rowstamp, 0xFF, sizeof(uint32_t) * max_particles);
-  (void)hipMemset(s->b.serial, 0, sizeof(uint32_t));
   (void)hipDeviceSynchronize();
   s->palloc.init(max_particles);
   s->calloc_.init(s->ccap + max_events);

@@ -13,19 +13,21 @@
 //   k_eom      one thread per particle: local M du/dx0 = F solve, relaxation
 //              rates, Heun update
 //
-// The neighbour loops give each of L consecutive lanes every L-th candidate
-// of the particle's trimmed cell rows and combine the partial sums in a fixed
+// The two pair kernels work on neighbour tiles (tile_device.h): a workgroup
+// takes 256 / L consecutive slots, stages the union of their neighbour rows
+// (positions and the operands of the sums) in LDS with coalesced loads, and
+// each team of L lanes walks its own candidates from there, lane k taking
+// every L-th candidate of the particle's rows, U at a time.  Rejected
+// candidates add zero.  The lanes' partial sums are combined in a fixed
 // order through LDS (lane v adds value v of the team's lanes in lane order),
-// so the result is deterministic.  Each lane
-// takes its candidates U at a time (PairU): the positions of all U are
-// loaded together, then the operands of the accepted ones, so that a lane has
-// several loads in flight across row boundaries instead of one dependent
-// round trip per candidate.  Candidates of particles in the same cell
-// coincide, so the lanes of a wave read the same addresses.  In mixed precision the pair terms are formed and accumulated in
-// FP32 with Kahan compensation per lane, and the lanes' partials are merged in FP64;
-// the pair test itself is always the exact FP64 one.
+// so the result is deterministic and independent of the batch.  In mixed
+// precision the pair terms are formed and accumulated in FP32 with Kahan
+// compensation per lane, and the lanes' partials are merged in FP64; the pair
+// test itself is always the exact FP64 one.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "common.h"
 #include "eom_device.h"
@@ -33,113 +35,405 @@
 #include "kernels.h"
 #include "pair_device.h"
 #include "sph_device.h"
+#include "tile_device.h"
 
 namespace ccake {
 
 // lanes per particle in the pair loops (2D, 3D)
 #ifndef CCAKE_TEAM2
-#define CCAKE_TEAM2 16
+#define CCAKE_TEAM2 8
 #endif
 #ifndef CCAKE_TEAM3
-#define CCAKE_TEAM3 16
+#define CCAKE_TEAM3 8
 #endif
 template <int D>
 struct Team {
   static constexpr int L = D == 2 ? CCAKE_TEAM2 : CCAKE_TEAM3;
-  static constexpr int PER_BLOCK = 256 / L;
+  static constexpr int P = 256 / L;  // particles per workgroup
+  static_assert(L >= 4 && L <= 64 && (L & (L - 1)) == 0, "team of 4 to 64 lanes");
 };
-// candidates per lane in flight in the pair loops (2D, 3D; measured best:
-// the 3D loops are longer and issue-bound, so more loads in flight pay)
+// candidates per lane in flight in the pair loops (2D, 3D)
 #ifndef CCAKE_PAIR_U2
 #define CCAKE_PAIR_U2 2
 #endif
 #ifndef CCAKE_PAIR_U3
-#define CCAKE_PAIR_U3 4
+#define CCAKE_PAIR_U3 2
 #endif
 template <int D>
 struct PairU {
   static constexpr int U = D == 2 ? CCAKE_PAIR_U2 : CCAKE_PAIR_U3;
 };
+// LDS bytes of the staged candidates of a workgroup of the density and the
+// gradient pass (2D, 3D); the chunk size follows from the bytes a candidate
+// takes.  The 2D halos of a workgroup hold about 400 candidates.
+#ifndef CCAKE_DENS_BYTES2
+#define CCAKE_DENS_BYTES2 16384
+#endif
+#ifndef CCAKE_GRAD_BYTES2
+#define CCAKE_GRAD_BYTES2 24576
+#endif
+#ifndef CCAKE_DENS_BYTES3
+#define CCAKE_DENS_BYTES3 24576
+#endif
+#ifndef CCAKE_GRAD_BYTES3
+#define CCAKE_GRAD_BYTES3 32768
+#endif
+template <int D>
+struct TileBytes {
+  static constexpr int DENS = D == 2 ? CCAKE_DENS_BYTES2 : CCAKE_DENS_BYTES3;
+  static constexpr int GRAD = D == 2 ? CCAKE_GRAD_BYTES2 : CCAKE_GRAD_BYTES3;
+};
 
-// Takes this lane's next U candidates from the cursor: slot k[u] and
-// whether it exists (v[u]); missing ones point at the lane's own particle,
-// so every load stays in bounds.
+// four operands of a candidate in LDS: one 16-byte load in FP32, two in FP64
+template <bool MIXED>
+struct Quad;
+template <>
+struct Quad<true> {
+  float4 v;
+  template <class T>
+  __device__ __forceinline__ void put(T a0, T a1, T a2, T a3) {
+    v = make_float4((float)a0, (float)a1, (float)a2, (float)a3);
+  }
+  __device__ __forceinline__ void get(float* o) const {
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <>
+struct Quad<false> {
+  double2 a, b;
+  template <class T>
+  __device__ __forceinline__ void put(T a0, T a1, T a2, T a3) {
+    a = make_double2((double)a0, (double)a1);
+    b = make_double2((double)a2, (double)a3);
+  }
+  __device__ __forceinline__ void get(double* o) const {
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+  }
+};
+
+// LDS halo of a pair kernel: C candidates with their positions (x^1, x^2 as
+// one 16-byte pair, x^3 apart), G quads of operands and, when SLOTS, their
+// slots, C as many as fit in BUDGET bytes (a multiple of 64); the memory is
+// reused for the team sums (NRED values per lane) after the last chunk.
+template <int D, bool MIXED, int G, bool SLOTS, int NRED, int BUDGET>
+struct Halo {
+  static constexpr int PER = 16 + (D == 3 ? 8 : 0) + (int)sizeof(Quad<MIXED>) * G + (SLOTS ? 4 : 0);
+  static constexpr int C = (BUDGET / PER) & ~63;
+  static_assert(C >= 64, "LDS budget below 64 candidates");
+  static constexpr size_t XY = 16 * (size_t)C;
+  static constexpr size_t Z = D == 3 ? 8 * (size_t)C : 0;
+  static constexpr size_t Q = sizeof(Quad<MIXED>) * (size_t)C * G;
+  static constexpr size_t SL = SLOTS ? 4 * (size_t)C : 0;
+  static constexpr size_t DATA = XY + Z + Q + SL;
+  static constexpr size_t RED = 8 * (size_t)256 * NRED;
+  static constexpr size_t BYTES = DATA > RED ? DATA : RED;
+  char* m;
+  __device__ __forceinline__ double2* xy() const { return (double2*)m; }
+  __device__ __forceinline__ double* z() const { return (double*)(m + XY); }
+  __device__ __forceinline__ Quad<MIXED>* q(int g) const { return (Quad<MIXED>*)(m + XY + Z) + (size_t)g * C; }
+  __device__ __forceinline__ int32_t* slot() const { return (int32_t*)(m + XY + Z + Q); }
+  __device__ __forceinline__ double* red() const { return (double*)m; }
+};
+
+// Cooperative load of the halo indices [c0, c1) into the LDS halo: thread
+// i takes indices c0 + i, c0 + i + 256, ...; positions from the state Y,
+// operands through operands(slot, quads) (G quads in the precision of the
+// sums).
+template <int D, bool MIXED, int G, bool SLOTS, int NRED, int BUDGET, int P, class F>
+__device__ __forceinline__ void halo_load(const Halo<D, MIXED, G, SLOTS, NRED, BUDGET>& H, const TileShared<D, P>& S,
+                                          const double* __restrict__ Y, int64_t cap, int32_t c0, int32_t c1,
+                                          F&& operands) {
+  int32_t x = c0 + (int32_t)threadIdx.x;
+  if (x >= c1) return;
+  int e = tile_entry(S, x);
+  for (; x < c1; x += 256) {
+    const int32_t sl = tile_slot(S, x, e);
+    const int32_t i = x - c0;
+    H.xy()[i] = make_double2(Y[(int64_t)R_X1 * cap + sl], Y[(int64_t)R_X2 * cap + sl]);
+    if (D == 3) H.z()[i] = Y[(int64_t)R_X3 * cap + sl];
+    operands(sl, &H.q(0)[i], (size_t)H.C);
+    if (SLOTS) H.slot()[i] = sl;
+  }
+}
+
+// Debug export of the pairs a pass accepts (original ids), or none.
+struct PairExport {
+  int64_t* counter;  // nullptr: no export
+  int64_t cap;
+  int32_t* a;
+  int32_t* b;
+};
+
+// Takes this lane's next U candidates from the cursor (chunk-local LDS
+// indices); missing ones point at index 0, a loaded candidate, and are
+// flagged invalid.
 template <int U, class Cursor>
-__device__ __forceinline__ void take(Cursor& cur, int32_t self, int32_t k[U], bool v[U]) {
+__device__ __forceinline__ void take(Cursor& cur, int32_t k[U], bool v[U]) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     v[u] = cur.valid();
-    k[u] = self;
+    k[u] = 0;
     if (v[u]) k[u] = cur.next();
   }
 }
 
 // ---------------------------------------------------------------------------
-// NS: smoothed scalars per neighbour (0 specific densities, 1 s*, 4 s* and n*)
-template <int D, bool MIXED, int NS>
+// NS: smoothed scalars per neighbour (0 specific densities, 1 s*, 4 s* and n*);
+// DBG: export the accepted pairs
+template <int D, bool MIXED, int NS, bool DBG>
 __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const double* __restrict__ Y,
-                                                 int64_t nslots) {
-  constexpr int L = Team<D>::L;
+                                                 PairExport px) {
+  constexpr int L = Team<D>::L, P = Team<D>::P;
   constexpr int ROWS = RowBlock<D>::ROWS;
-  __shared__ int32_t s_lo[Team<D>::PER_BLOCK][ROWS], s_hi[Team<D>::PER_BLOCK][ROWS];
-  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t j = tid / L;
-  const int lane = (int)(tid % L);
-  if (j >= nslots) return;
-  const int e = b.ev[j];
-  if (e < 0) return;
-  const EventDev& E = b.evt[e];
+  constexpr int G = NS > 0 ? 1 : 0;
+  using RT = typename std::conditional<MIXED, float, double>::type;
+  using HaloT = Halo<D, MIXED, G, DBG, 6, TileBytes<D>::DENS>;
+  constexpr int C = HaloT::C;
+  __shared__ TileShared<D, P> S;
+  __shared__ __align__(16) char s_mem[HaloT::BYTES];
+  const HaloT H{s_mem};
   const int64_t cap = b.cap;
+  int ev0;
+  int64_t j0, jend;
+  if (!tile_targets<P>(b, xcd_block(blockIdx.x, gridDim.x), ev0, j0, jend)) return;  // whole workgroup
+  const int32_t total = tile_setup<D, L, P>(b, j0, jend, S);
+  const int t = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;
+  const int64_t j = j0 + t;
+  const bool have = S.seg[t] >= 0;
+  (void)ev0;
   const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
-  const double xa[3] = {row(Y, cap, R_X1, j), row(Y, cap, R_X2, j), D == 3 ? row(Y, cap, R_X3, j) : 0.0};
-  const int team = (int)threadIdx.x / L;
-  // rows found at the first pass after a binning, kept until the next
-  // binning: a pair within 2h now was within 2h + skin then, because the
-  // binning is redone before twice the displacement bound exceeds the skin
-  if (b.rowstamp[j] == E.bin_serial) {
-    rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
-  } else {
-    team_rows<D, L>(b, E, b.keys[j], xa, prm.cell_edge, lane, s_lo[team], s_hi[team]);
-    rows_keep<D, L>(b, j, lane, s_lo[team], s_hi[team]);
-    if (lane == 0) b.rowstamp[j] = E.bin_serial;
+  double xa[3] = {0.0, 0.0, 0.0};
+  if (have) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) xa[k] = row(Y, cap, R_X1 + k, j);
   }
-  RowCursor<L, ROWS> cur;
-  cur.start(s_lo[team], s_hi[team], lane);
   DensAcc<MIXED, NS> A;
   A.init();
-  const int32_t self = (int32_t)j;
-  constexpr int PAIR_U = PairU<D>::U;
-  for (;;) {
-    int32_t k[PAIR_U];
-    bool v[PAIR_U];
-    take<PAIR_U>(cur, self, k, v);
-    if (!v[0]) break;
-    double d2[PAIR_U];
-    bool ok[PAIR_U];
+  TileCursor<L, ROWS> cur;
+  cur.start(S.lo[t], S.hi[t], lane);
+  constexpr int U = PairU<D>::U;
+  for (int32_t c0 = 0; c0 < total; c0 += C) {
+    const int32_t c1 = total - c0 < C ? total : c0 + C;
+    halo_load(H, S, Y, cap, c0, c1, [&](int32_t sl, Quad<MIXED>* q, size_t) {
+      if (NS == 4)
+        q->put(row(Y, cap, R_S, sl), row(Y, cap, R_NB, sl), row(Y, cap, R_NS, sl), row(Y, cap, R_NQ, sl));
+      else if (NS == 1)
+        q->put(row(Y, cap, R_S, sl), 0.0, 0.0, 0.0);
+    });
+    __syncthreads();
+    cur.chunk(c0, c1);
+    for (;;) {
+      int32_t k[U];
+      bool v[U];
+      take<U>(cur, k, v);
+      if (!v[0]) break;
+      double d2[U];
+      bool ok[U];
 #pragma unroll
-    for (int u = 0; u < PAIR_U; ++u) {
-      const double xb[3] = {row(Y, cap, R_X1, k[u]), row(Y, cap, R_X2, k[u]),
-                            D == 3 ? row(Y, cap, R_X3, k[u]) : 0.0};
-      d2[u] = dist2<D>(xa, xb);
-      ok[u] = v[u] && d2[u] < r2max;
+      for (int u = 0; u < U; ++u) {
+        const double2 p = H.xy()[k[u]];
+        const double xb[3] = {p.x, p.y, D == 3 ? H.z()[k[u]] : 0.0};
+        d2[u] = dist2<D>(xa, xb);
+        ok[u] = v[u] && d2[u] < r2max;
+      }
+      RT sc[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        sc[u][0] = sc[u][1] = sc[u][2] = sc[u][3] = RT(0);
+        if (G) H.q(0)[k[u]].get(sc[u]);
+      }
+      A.template add_block<U>(ok, d2, ih, sc);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (DBG && ok[u]) {
+          const int64_t at = (int64_t)atomicAdd((unsigned long long*)px.counter, 1ull);
+          if (at < px.cap) {
+            px.a[at] = b.ids[j];
+            px.b[at] = b.ids[H.slot()[k[u]]];
+          }
+        }
+      }
+      if (!v[U - 1]) break;
     }
-#pragma unroll
-    for (int u = 0; u < PAIR_U; ++u) {
-      const int32_t m = ok[u] ? k[u] : self;
-      double sc[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sc[q] = q < NS ? row(Y, cap, R_S + q, m) : 0.0;
-      if (ok[u]) A.add(d2[u], ih, sc);
-    }
-    if (!v[PAIR_U - 1]) break;
+    __syncthreads();
   }
-  // lane v < 6 forms row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
-  __shared__ double s_red[Team<D>::PER_BLOCK][L * 6];
-  double part[6];
+  // lanes v < 6 form row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
+  double part[6], tot[(6 + L - 1) / L];
   A.partials(part);
-  const double tot = team_sums_lds<L, 6>(s_red[team], lane, part);
-  if (lane < 6) b.dsum[(int64_t)(DS_SIG + lane) * b.cap + j] = lane == 5 ? tot : tot * sigma_d<D>(prm.h);
+  team_sums_lds_n<L, 6>(H.red() + (size_t)t * L * 6, lane, part, tot);
+  if (have) {
+#pragma unroll
+    for (int q = 0; q < (6 + L - 1) / L; ++q) {
+      const int v = lane + q * L;
+      if (v < 6) b.dsum[(int64_t)(DS_SIG + v) * cap + j] = v == 5 ? tot[q] : tot[q] * sigma_d<D>(prm.h);
+    }
+  }
 }
+
+// own record and geometry of particle j for the gradient sums
+template <int D, bool VISC, bool MIXED>
+__device__ __forceinline__ void grad_setup(const BatchDev& b, const Params& prm, const double* __restrict__ Y,
+                                           double t, int64_t j, GradAcc<D, VISC, MIXED>& A) {
+  const int64_t cap = b.cap;
+  const double G3 = metric_G3(prm, t);
+  A.Gk[0] = 0.0;
+  A.Gk[1] = 1.0;
+  A.Gk[2] = 1.0;
+  A.Gk[3] = G3;
+  A.ih = 1.0 / prm.h;
+  A.xa[0] = row(Y, cap, R_X1, j);
+  A.xa[1] = row(Y, cap, R_X2, j);
+  A.xa[2] = D == 3 ? row(Y, cap, R_X3, j) : 0.0;
+  auto recv = [&](int q) -> double {
+    return MIXED ? (double)b.recf[(int64_t)q * cap + j] : b.rec[(int64_t)q * cap + j];
+  };
+  A.aPP = recv(Q_PP);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A.aU[k] = k < D ? recv(Q_U1 + k) : 0.0;
+    A.aV[k] = k < D ? recv(Q_V1 + k) : 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) A.aA[k][i] = (VISC && k < D && i < D) ? recv(Q_A11 + k * 3 + i) : 0.0;
+  }
+  A.init();
+}
+
+// neighbour record of the gradient sums as staged in LDS: (p+Pi)/sigma*^2,
+// u^1..u^D, v^1..v^D and, when viscous, A^{ji}/sigma*^2 at j*D + i
+template <int D, bool VISC>
+struct GradRec {
+  static constexpr int N = 1 + 2 * D + (VISC ? D * D : 0);
+  static constexpr int G = (N + 3) / 4;
+  __device__ __forceinline__ static int source(int q) {  // its row of the pass-1 record
+    return q == 0 ? Q_PP : q <= D ? Q_U1 + q - 1 : q <= 2 * D ? Q_V1 + q - 1 - D
+                                                              : Q_A11 + ((q - 1 - 2 * D) / D) * 3 + (q - 1 - 2 * D) % D;
+  }
+};
+
+// DIFF: also the BSQ diffusion sums (DiffAcc) over the same accepted pairs
+// (1: without, 2: with the bulk-pressure gradient); their FP64 records are
+// read from global memory by slot
+template <int D, bool VISC, bool MIXED, int DIFF>
+__global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage) {
+  constexpr int L = Team<D>::L, P = Team<D>::P;
+  constexpr int ROWS = RowBlock<D>::ROWS;
+  using GA = GradAcc<D, VISC, MIXED>;
+  using RT = typename GA::RT;
+  using GR = GradRec<D, VISC>;
+  constexpr int NP = GA::NP;
+  using HaloT = Halo<D, MIXED, GR::G, DIFF != 0, NP, TileBytes<D>::GRAD>;
+  constexpr int C = HaloT::C;
+  __shared__ TileShared<D, P> S;
+  __shared__ __align__(16) char s_mem[HaloT::BYTES];
+  const HaloT H{s_mem};
+  const int64_t cap = b.cap;
+  int ev0;
+  int64_t j0, jend;
+  if (!tile_targets<P>(b, xcd_block(blockIdx.x, gridDim.x), ev0, j0, jend)) return;  // whole workgroup
+  const int32_t total = tile_setup<D, L, P>(b, j0, jend, S);
+  const int t = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;
+  const int64_t j = j0 + t;
+  const bool have = S.seg[t] >= 0;
+  const double r2max = (2.0 * prm.h) * (2.0 * prm.h);
+  GA A;
+  DiffAcc<D, DIFF == 2> DA;
+  if (have) {
+    const EventDev& E = b.evt[ev0];
+    grad_setup<D, VISC, MIXED>(b, prm, Y, E.t + stage * E.dt, j, A);
+    if (DIFF) DA.init(b.drec, cap, j);
+  } else {
+    A.xa[0] = A.xa[1] = A.xa[2] = 0.0;
+    A.ih = 1.0;
+    A.init();
+    if (DIFF) DA.init(b.drec, cap, j0);
+  }
+  TileCursor<L, ROWS> cur;
+  cur.start(S.lo[t], S.hi[t], lane);
+  constexpr int U = PairU<D>::U;
+  for (int32_t c0 = 0; c0 < total; c0 += C) {
+    const int32_t c1 = total - c0 < C ? total : c0 + C;
+    halo_load(H, S, Y, cap, c0, c1, [&](int32_t sl, Quad<MIXED>* q, size_t stride) {
+      const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
+      auto op = [&](int i) -> RT { return i < GR::N ? rb[(int64_t)GR::source(i) * cap + sl] : RT(0); };
+#pragma unroll
+      for (int g = 0; g < GR::G; ++g) q[g * stride].put(op(4 * g), op(4 * g + 1), op(4 * g + 2), op(4 * g + 3));
+    });
+    __syncthreads();
+    cur.chunk(c0, c1);
+    for (;;) {
+      int32_t k[U];
+      bool v[U];
+      take<U>(cur, k, v);
+      if (!v[0]) break;
+      double xb[U][3], d2[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double2 p = H.xy()[k[u]];
+        xb[u][0] = p.x;
+        xb[u][1] = p.y;
+        xb[u][2] = D == 3 ? H.z()[k[u]] : 0.0;
+        d2[u] = dist2<D>(A.xa, xb[u]);
+        ok[u] = v[u] && d2[u] < r2max && d2[u] > 0.0;
+      }
+      RT r[U][4 * GR::G];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int g = 0; g < GR::G; ++g) H.q(g)[k[u]].get(r[u] + 4 * g);
+      A.template add_block<U>(ok, xb, d2, r);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (DIFF && ok[u]) {
+          double ab[3], Fb[3][3], Pb = 0.0;
+          DiffAcc<D, DIFF == 2>::load(b.drec, cap, H.slot()[k[u]], ab, Fb, Pb);
+          DA.add(A.xa, xb[u], d2[u], A.ih, ab, Fb, Pb);
+        }
+      }
+      if (!v[U - 1]) break;
+    }
+    __syncthreads();
+  }
+  // lane v forms gradient sums v, v + L, ...: F_i, d_k u^j (row-major), div v
+  {
+    constexpr int NQ = (NP + L - 1) / L;
+    double part[NP], tot[NQ];
+    A.partials(part);
+    team_sums_lds_n<L, NP>(H.red() + (size_t)t * L * NP, lane, part, tot);
+    if (have) {
+      const double fsd = sigma_d<D>(prm.h) / prm.h;
+      const double isg = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int v = lane + q * L;
+        if (v >= NP) continue;
+        int rw;
+        double scale = isg;
+        if (v < D) {
+          rw = GS_F1 + v;
+          scale = fsd;
+        } else if (v < NP - 1) {
+          rw = GS_DU11 + ((v - D) / D) * 3 + (v - D) % D;
+        } else {
+          rw = GS_DIVV;
+        }
+        b.gsum[(int64_t)rw * cap + j] = tot[q] * scale;
+      }
+    }
+  }
+  if (DIFF) DA.template reduce<L>();
+  if (DIFF && have && lane == 0) {
+    const double fsd = sigma_d<D>(prm.h) / prm.h;
+    DA.write(b.gsum, cap, j, fsd, fsd / b.th[(int64_t)T_SIGSTAR * cap + j]);
+  }
+}
+
 
 // ---------------------------------------------------------------------------
 template <int D, bool VISC, bool MIXED, int NQ>
@@ -315,132 +609,6 @@ __global__ void __launch_bounds__(128) k_eos(BatchDev b, Params prm, EosDev eos,
   wave_count_eos(b.evt, e, c_backup, c_iters, c_noconv);
 }
 
-// own record and geometry of particle j for the gradient sums
-template <int D, bool VISC, bool MIXED>
-__device__ __forceinline__ void grad_setup(const BatchDev& b, const Params& prm, const double* __restrict__ Y,
-                                           double t, int64_t j, GradAcc<D, VISC, MIXED>& A) {
-  const int64_t cap = b.cap;
-  const double G3 = metric_G3(prm, t);
-  A.Gk[0] = 0.0;
-  A.Gk[1] = 1.0;
-  A.Gk[2] = 1.0;
-  A.Gk[3] = G3;
-  A.ih = 1.0 / prm.h;
-  A.xa[0] = row(Y, cap, R_X1, j);
-  A.xa[1] = row(Y, cap, R_X2, j);
-  A.xa[2] = D == 3 ? row(Y, cap, R_X3, j) : 0.0;
-  auto recv = [&](int q) -> double {
-    return MIXED ? (double)b.recf[(int64_t)q * cap + j] : b.rec[(int64_t)q * cap + j];
-  };
-  A.aPP = recv(Q_PP);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    A.aU[k] = k < D ? recv(Q_U1 + k) : 0.0;
-    A.aV[k] = k < D ? recv(Q_V1 + k) : 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) A.aA[k][i] = (VISC && k < D && i < D) ? recv(Q_A11 + k * 3 + i) : 0.0;
-  }
-  A.init();
-}
-
-// DIFF: also the BSQ diffusion sums (DiffAcc) over the same accepted pairs
-template <int D, bool VISC, bool MIXED, int DIFF>
-__global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
-                                              int64_t nslots) {
-  constexpr int L = Team<D>::L;
-  constexpr int ROWS = RowBlock<D>::ROWS;
-  using RT = typename GradAcc<D, VISC, MIXED>::RT;
-  __shared__ int32_t s_lo[Team<D>::PER_BLOCK][ROWS], s_hi[Team<D>::PER_BLOCK][ROWS];
-  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  const int64_t j = tid / L;
-  const int lane = (int)(tid % L);
-  if (j >= nslots) return;
-  const int e = b.ev[j];
-  if (e < 0) return;
-  const EventDev& E = b.evt[e];
-  const int64_t cap = b.cap;
-  const double r2max = (2.0 * prm.h) * (2.0 * prm.h);
-  GradAcc<D, VISC, MIXED> A;
-  grad_setup<D, VISC, MIXED>(b, prm, Y, E.t + stage * E.dt, j, A);
-  DiffAcc<D, DIFF == 2> DA;
-  if (DIFF) DA.init(b.drec, cap, j);
-  const int team = (int)threadIdx.x / L;
-  // the rows the density pass of this stage used for the same particle
-  rows_load<D, L>(b, j, lane, s_lo[team], s_hi[team]);
-  RowCursor<L, ROWS> cur;
-  cur.start(s_lo[team], s_hi[team], lane);
-  const RT* rb = MIXED ? (const RT*)b.recf : (const RT*)b.rec;
-  const int32_t self = (int32_t)j;
-  constexpr int PAIR_U = PairU<D>::U;
-  for (;;) {
-    int32_t k[PAIR_U];
-    bool v[PAIR_U];
-    take<PAIR_U>(cur, self, k, v);
-    if (!v[0]) break;
-    double xb[PAIR_U][3], d2[PAIR_U];
-    bool ok[PAIR_U];
-#pragma unroll
-    for (int u = 0; u < PAIR_U; ++u) {
-      xb[u][0] = row(Y, cap, R_X1, k[u]);
-      xb[u][1] = row(Y, cap, R_X2, k[u]);
-      xb[u][2] = D == 3 ? row(Y, cap, R_X3, k[u]) : 0.0;
-      d2[u] = dist2<D>(A.xa, xb[u]);
-      ok[u] = v[u] && d2[u] < r2max;
-    }
-#pragma unroll
-    for (int u = 0; u < PAIR_U; ++u) {
-      const int32_t m = ok[u] ? k[u] : self;
-      RT bA[3][3], bU[3], bV[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        bU[q] = q < D ? rb[(int64_t)(Q_U1 + q) * cap + m] : RT(0);
-        bV[q] = q < D ? rb[(int64_t)(Q_V1 + q) * cap + m] : RT(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-          bA[q][i] = (VISC && q < D && i < D) ? rb[(int64_t)(Q_A11 + q * 3 + i) * cap + m] : RT(0);
-      }
-      const RT bpp = rb[(int64_t)Q_PP * cap + m];
-      double ab[3], Fb[3][3], Pb = 0.0;
-      if (DIFF) DiffAcc<D, DIFF == 2>::load(b.drec, cap, m, ab, Fb, Pb);
-      if (ok[u]) {
-        A.add(xb[u], d2[u], bpp, bA, bU, bV);
-        if (DIFF) DA.add(A.xa, xb[u], d2[u], A.ih, ab, Fb, Pb);
-      }
-    }
-    if (!v[PAIR_U - 1]) break;
-  }
-  {
-    // lane v < NP forms gradient sum v: F_i, d_k u^j (row-major), div v
-    constexpr int NP = GradAcc<D, VISC, MIXED>::NP;
-    __shared__ double s_red[Team<D>::PER_BLOCK][L * NP];
-    double part[NP];
-    A.partials(part);
-    const double tot = team_sums_lds<L, NP>(s_red[team], lane, part);
-    if (lane < NP) {
-      const double fsd = sigma_d<D>(prm.h) / prm.h;
-      int row;
-      double scale = fsd;
-      if (lane < D) {
-        row = GS_F1 + lane;
-      } else if (lane < NP - 1) {
-        const int kk = (lane - D) / D, nu = (lane - D) % D;
-        row = GS_DU11 + kk * 3 + nu;
-        scale = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
-      } else {
-        row = GS_DIVV;
-        scale = fsd / b.th[(int64_t)T_SIGSTAR * cap + j];
-      }
-      b.gsum[(int64_t)row * cap + j] = tot * scale;
-    }
-  }
-  if (DIFF) DA.template reduce<L>();
-  if (lane == 0) {
-    if (DIFF) {
-      const double fsd = sigma_d<D>(prm.h) / prm.h;
-      DA.write(b.gsum, cap, j, fsd, fsd / b.th[(int64_t)T_SIGSTAR * cap + j]);
-    }
-  }
-}
 
 // Spatial gradient of the energy density for the freeze-out surface
 // ("Freeze-out hypersurface construction"), n = 1 difference form like
@@ -754,6 +922,43 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
 // ---------------------------------------------------------------------------
 static inline unsigned nblocks(int64_t threads, int bs) { return (unsigned)((threads + bs - 1) / bs); }
 
+// Workgroups of the pair kernels: ceil(n / P) per event, at most one more
+// per event than the slots need; surplus workgroups leave at once.
+static inline unsigned pair_blocks(const BatchDev& b, int64_t nslots, int P) {
+  return nblocks(nslots, P) + (b.max_events > 1 ? (unsigned)b.max_events : 0u);
+}
+
+// First workgroup of every event in the pair kernels' grid (ceil(n / P)
+// workgroups per active event, none for the others): one workgroup scans the
+// event table.  A single simulation keeps tile0 = 0 and needs no scan.
+__global__ void __launch_bounds__(256) k_tiles(BatchDev b, int P) {
+  __shared__ int32_t s_w[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int32_t run = 0;
+  for (int base = 0; base < b.max_events; base += 256) {
+    const int m = base + tid;
+    int32_t nt = 0;
+    if (m < b.max_events && b.evt[m].active) nt = (b.evt[m].n + P - 1) / P;
+    int32_t inc = nt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      before += a < w ? s_w[a] : 0;
+      total += s_w[a];
+    }
+    if (m < b.max_events) b.evt[m].tile0 = run + before + inc - nt;
+    run += total;
+    __syncthreads();
+  }
+}
+
 // A stage kernel launch.  With profiling events (ev = {start, stop}) the
 // dispatch itself records them, so a group's time is its kernel's execution
 // without the gaps between launches.
@@ -771,18 +976,18 @@ template <int D, bool VISC, bool MIXED>
 static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, const double* Y,
                     int stage, int mode, double* fout, double* aux, bool rates, hipStream_t s,
                     const hipEvent_t* mk) {
-  constexpr int L = Team<D>::L;
-  const unsigned gt = nblocks(nslots * L, 256), gp = nblocks(nslots, 128);
+  const unsigned gt = pair_blocks(b, nslots, Team<D>::P), gp = nblocks(nslots, 128);
+  const PairExport none{nullptr, 0, nullptr, nullptr};
   const hipEvent_t* ed = mk ? mk + 0 : nullptr;
   const hipEvent_t* ee = mk ? mk + 2 : nullptr;
   const hipEvent_t* eg = mk ? mk + 4 : nullptr;
   const hipEvent_t* em = mk ? mk + 6 : nullptr;
   if (prm.density_mode != 0)
-    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 0>), dim3(gt), dim3(256), b, prm, Y, nslots);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 0, false>), dim3(gt), dim3(256), b, prm, Y, none);
   else if (prm.ncharge)
-    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 4>), dim3(gt), dim3(256), b, prm, Y, nslots);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 4, false>), dim3(gt), dim3(256), b, prm, Y, none);
   else
-    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 1>), dim3(gt), dim3(256), b, prm, Y, nslots);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 1, false>), dim3(gt), dim3(256), b, prm, Y, none);
   if (prm.ncharge)
     CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 3>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux);
   else
@@ -790,11 +995,11 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
   if (!rates) return;
   // diffusion sums: 1 without, 2 with the bulk-pressure gradient
   if (prm.diffusion && (prm.d_JPi[0] != 0.0 || prm.d_JPi[1] != 0.0 || prm.d_JPi[2] != 0.0))
-    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 2>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 2>), dim3(gt), dim3(256), b, prm, Y, stage);
   else if (prm.diffusion)
-    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 1>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 1>), dim3(gt), dim3(256), b, prm, Y, stage);
   else
-    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 0>), dim3(gt), dim3(256), b, prm, Y, stage, nslots);
+    CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 0>), dim3(gt), dim3(256), b, prm, Y, stage);
   // diagnostic evaluations only (never profiled)
   if (aux) hipLaunchKernelGGL((k_fo_grad<D>), dim3(gp), dim3(128), 0, s, b, prm, Y, nslots);
   CCAKE_STAGE_LAUNCH(em, (k_eom<D, VISC>), dim3(gp), dim3(128), b, prm, Y, stage, mode, nslots, fout, aux);
@@ -803,12 +1008,40 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
 template <int D, bool VISC, bool MIXED>
 static void passes_t(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, int which,
                      double* fout, double* aux, hipStream_t s, const hipEvent_t* marks) {
+  if (b.max_events > 1) hipLaunchKernelGGL(k_tiles, dim3(1), dim3(256), 0, s, b, Team<D>::P);
   if (which == 0) {
     stage_t<D, VISC, MIXED>(b, prm, eos, nslots, b.Ys, 0, 0, nullptr, nullptr, true, s, marks);
     stage_t<D, VISC, MIXED>(b, prm, eos, nslots, b.Y1, 1, 1, nullptr, nullptr, true, s, marks ? marks + 8 : nullptr);
   } else {
     stage_t<D, VISC, MIXED>(b, prm, eos, nslots, b.Ys, 0, 2, fout, aux, fout != nullptr, s, nullptr);
   }
+}
+
+template <int D, bool MIXED>
+static void pairs_cached_t(const BatchDev& b, const Params& prm, int64_t nslots, const PairExport& px,
+                           hipStream_t s) {
+  if (b.max_events > 1) hipLaunchKernelGGL(k_tiles, dim3(1), dim3(256), 0, s, b, Team<D>::P);
+  const dim3 grid(pair_blocks(b, nslots, Team<D>::P));
+  if (prm.density_mode != 0)
+    hipLaunchKernelGGL((k_density<D, MIXED, 0, true>), grid, dim3(256), 0, s, b, prm, b.Ys, px);
+  else if (prm.ncharge)
+    hipLaunchKernelGGL((k_density<D, MIXED, 4, true>), grid, dim3(256), 0, s, b, prm, b.Ys, px);
+  else
+    hipLaunchKernelGGL((k_density<D, MIXED, 1, true>), grid, dim3(256), 0, s, b, prm, b.Ys, px);
+}
+
+hipError_t launch_pairs_cached(const BatchDev& b, const Params& prm, int64_t nslots, int64_t* counter,
+                               int64_t cap, int32_t* pa, int32_t* pb, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  const PairExport px{counter, cap, pa, pb};
+  const int key = (prm.dim == 3 ? 2 : 0) + (prm.mixed ? 1 : 0);
+  switch (key) {
+    case 0: pairs_cached_t<2, false>(b, prm, nslots, px, s); break;
+    case 1: pairs_cached_t<2, true>(b, prm, nslots, px, s); break;
+    case 2: pairs_cached_t<3, false>(b, prm, nslots, px, s); break;
+    case 3: pairs_cached_t<3, true>(b, prm, nslots, px, s); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_passes(const BatchDev& b, const Params& prm, const EosDev& eos, int64_t nslots, int which,

@@ -65,6 +65,66 @@ def test_pairs_bit_exact(B, O, name, build):
     assert np.array_equal(ga, oa) and np.array_equal(gb, ob)
 
 
+def relativistic_cloud(side=30, dx=0.1, seed=21):
+    """A lattice whose particles move at 0.8 - 0.95 c in random directions:
+    pairs close at nearly twice that rate, the tight case of the binning
+    skin's displacement bound."""
+    xi = I.lattice((side, side), dx, -0.5 * dx * (side - 1))
+    n = xi.shape[1]
+    rng = np.random.default_rng(seed)
+    speed = rng.uniform(0.8, 0.95, n)
+    phi = rng.uniform(0.0, 2 * np.pi, n)
+    gam = 1.0 / np.sqrt(1.0 - speed ** 2)
+    u = np.stack([gam * speed * np.cos(phi), gam * speed * np.sin(phi)])
+    dens = np.zeros((4, n))
+    dens[0] = 20.0 + 5.0 * rng.random(n)
+    return xi, u, dens
+
+
+def cached_case(B, O, name):
+    """(sim after its steps, oracle params): the state sits at the end of a
+    binning interval (the last step that reuses the binning's rows)."""
+    if name == "lumpy40k_skin025":
+        w = I.lumpy_2d_workload()
+        prm, oe, cfg, ge = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", table_size="full", h=w.h,
+                                skin=0.25 * w.h, precision=B.MIXED)
+        sim = B.Sim(cfg, ge, w.n)
+        sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+        steps = 6  # one binning step and five that keep its rows (skin 0.06 fm, dt 0.005 fm)
+    elif name == "relativistic2d":
+        xi, u, dens = relativistic_cloud()
+        prm, oe, cfg, ge = make(O, B, dim=2, hyperbolic=False, h=0.3, skin=0.25 * 0.3)
+        sim = B.Sim(cfg, ge, xi.shape[1])
+        y = O.init(prm, oe, 0.0, xi, u, 0, dens)
+        sim.set_state(0.0, y)
+        steps = 7  # skin 0.075 fm: one binning step and six that keep it
+    else:  # lumpy3d_skin025
+        w = lumpy3d_small()
+        prm, oe, cfg, ge = make(O, B, dim=3, viscous=True, ncharge=3, eos="table", h=w.h, skin=0.25 * w.h,
+                                precision=B.MIXED)
+        sim = B.Sim(cfg, ge, w.n)
+        sim.init_particles(w.t0, w.xi, w.u, w.dens_kind, w.dens)
+        steps = 2  # 3+1D near tau0 moves by up to dt / tau per step: one binning, one reuse
+    sim.step(0.005, steps)
+    sim.check()
+    return sim, prm
+
+
+@pytest.mark.parametrize("name", ["lumpy40k_skin025", "relativistic2d", "lumpy3d_skin025"])
+def test_pairs_cached_bit_exact(B, O, name):
+    """The pairs the density kernel itself accepts between binnings (neighbour
+    tiles over the rows the last binning cut, the FP64 pair test at the
+    current positions), exported by that kernel, against the oracle's pair
+    set at the same positions, bit for bit."""
+    sim, prm = cached_case(B, O, name)
+    y = sim.get_state()
+    ga, gb = sim.pairs(cached=True)
+    oa, ob = O.pairs(prm, y)
+    assert ga.size == oa.size
+    assert np.array_equal(ga, oa) and np.array_equal(gb, ob)
+    sim.close()
+
+
 # ------------------------------------------------------------- rates -------
 def lumpy_small(side=48, rhoB=0.05, rhoQ=0.02, seed=1):
     return I.lumpy_2d_workload(n_side=side, seed=seed, n_hot=10, radius=1.0, rhoB=rhoB, rhoQ=rhoQ)
@@ -255,16 +315,9 @@ def test_cached_rows_at_relativistic_speeds(B, O):
     random directions close pairs at nearly twice that rate, the tight case
     of the bound: over three binning intervals (skin 0.25 h) the GPU state
     must follow the oracle's (which searches all pairs at every stage)."""
-    side, dx, h = 30, 0.1, 0.3
-    xi = I.lattice((side, side), dx, -0.5 * dx * (side - 1))
+    h = 0.3
+    xi, u, dens = relativistic_cloud()
     n = xi.shape[1]
-    rng = np.random.default_rng(21)
-    speed = rng.uniform(0.8, 0.95, n)
-    phi = rng.uniform(0.0, 2 * np.pi, n)
-    gam = 1.0 / np.sqrt(1.0 - speed ** 2)
-    u = np.stack([gam * speed * np.cos(phi), gam * speed * np.sin(phi)])
-    dens = np.zeros((4, n))
-    dens[0] = 20.0 + 5.0 * rng.random(n)
     prm, oe, cfg, ge = make(O, B, dim=2, hyperbolic=False, h=h, skin=0.25 * h)
     y = O.init(prm, oe, 0.0, xi, u, 0, dens)
     nsteps = 18

@@ -127,3 +127,68 @@ def test_bad_event_rejected_others_unaffected(B, eos):
     assert r["ticket"] == t_ok and r["status"] == 0
     assert np.array_equal(r["state"], alone(B, cfg, eos, w, 12))
     srv.close()
+
+
+@pytest.fixture(scope="module")
+def O(oracle_mod):
+    return oracle_mod
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_served_events_match_oracle(B, O, eos, precision):
+    """Events served in the mix against the FP64 oracle run of each event:
+    FP64 within the trajectory bar (1e-9 normwise per state row), mixed
+    precision within relative L2 1e-4 on e and n_B (the oracle's EoS applied
+    to the served state)."""
+    from cases import make, rel_inf, rel_l2
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=0.24, precision=precision, **TR)
+    prm, oe, _, _ = make(O, B, dim=2, viscous=True, ncharge=3, eos="table", h=0.24)
+    evs = events(5, seed=3)
+    steps = [30 + 7 * i for i in range(len(evs))]
+    srv = B.Server(cfg, eos, budget_bytes=2 << 30, max_particles=200000, max_events=8, dt=0.005)
+    for i, (w, s) in enumerate(zip(evs, steps)):
+        srv.submit(w.t0, w.t0 + s * w.dt, w.xi, w.u, w.dens_kind, w.dens, tag=i)
+    srv.drain()
+    res = srv.poll(64)
+    srv.close()
+    assert len(res) == len(evs)
+    for r in res:
+        i = r["tag"]
+        w = evs[i]
+        assert r["status"] == 0 and r["steps"] == steps[i]
+        y0 = O.init(prm, oe, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+        t, yo, _ = O.evolve(prm, oe, w.t0, w.dt, steps[i], y0)
+        yg = r["state"]
+        if precision == 0:
+            for row in (O.V_X1, O.V_X2, O.V_U1, O.V_U2, O.V_S, O.V_B, O.V_P11, O.V_P12, O.V_P33):
+                assert rel_inf(yg[row], yo[row]) <= 1e-9, (i, row, rel_inf(yg[row], yo[row]))
+        else:
+            _, aux_o, _ = O.rhs(prm, oe, t, yo)
+            _, aux_g, _ = O.rhs(prm, oe, t, yg)
+            assert rel_l2(aux_g[O.A_E], aux_o[O.A_E]) <= 1e-4, i
+            assert rel_l2(aux_g[O.A_NB], aux_o[O.A_NB]) <= 1e-4, i
+
+
+def test_capacity_fallback_reported(B, eos):
+    """An event spread so wide that no cell grid within the event's cell
+    capacity covers it (the grid falls back to a single cell around the
+    whole event) is flagged with CCAKE_E_CAPACITY, in the server and in a
+    single simulation, while an ordinary event in the same mix is unaffected."""
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=0.24, precision=1, **TR)
+    w = I.lumpy_2d_workload(n_side=6, seed=4, n_hot=2, radius=0.3)
+    wide = w.xi * 1e9  # 4e8 fm across: more cells than 4n + 8192 even after coarsening
+    ok = I.lumpy_2d_workload(n_side=20, seed=9, n_hot=3, radius=0.5)
+    srv = B.Server(cfg, eos, budget_bytes=1 << 30, max_particles=50000, max_events=4, dt=0.005)
+    t_bad = srv.submit(w.t0, w.t0 + 3 * w.dt, wide, w.u, w.dens_kind, w.dens)
+    t_ok = srv.submit(ok.t0, ok.t0 + 12 * ok.dt, ok.xi, ok.u, ok.dens_kind, ok.dens)
+    srv.drain()
+    res = {r["ticket"]: r for r in srv.poll(8)}
+    srv.close()
+    assert res[t_bad]["status"] == B.E_CAPACITY
+    assert res[t_ok]["status"] == 0
+    assert np.array_equal(res[t_ok]["state"], alone(B, cfg, eos, ok, 12))
+    sim = B.Sim(cfg, eos, w.n)
+    with pytest.raises(B.CcakeError) as e:
+        sim.init_particles(w.t0, wide, w.u, w.dens_kind, w.dens)
+    assert e.value.status == B.E_CAPACITY
+    sim.close()
