@@ -188,6 +188,17 @@ ccake_status ccake_eos_destroy(ccake_eos* eos);
 ccake_status ccake_eos_invert(ccake_eos* eos, int32_t mode, int32_t ncharge, int64_t n, const double* in,
                               double* out, int32_t* in_table, void* stream);
 
+/* Allocation-free form of ccake_eos_invert, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors.  Its only
+ * scratch, the count of failed inversions, lives in a 256-byte device array
+ * of the library that every call on a device shares (its size does not depend
+ * on n, so no n is too large for it); calls that overlap on one device race
+ * on that count.  Allocates nothing (no hipMalloc, no pinned memory); clears
+ * the count with a kernel; synchronises the stream like ccake_eos_invert.     */
+ccake_status ccake_eos_invert_noalloc(ccake_eos* eos, int32_t mode, int32_t ncharge, int64_t n, const double* in,
+                                      double* out, int32_t* in_table, void* stream);
+
 /* Offline inverter ("EoS inverter", offline option): the thermodynamics are
  * converted once onto a fixed grid in the hydrodynamic variables, and the
  * stages then interpolate instead of root-finding.  The s nodes are evenly

@@ -36,7 +36,7 @@ KAPPA_T2_BSQ = ((0.0482, -0.0482, 0.0), (-0.0482, 0.1447, 0.0147), (0.0, 0.0147,
 
 EXPORTS = [
     "ccake_eos_create_conformal", "ccake_eos_create_gas", "ccake_eos_create_table",
-    "ccake_eos_destroy", "ccake_eos_invert", "ccake_eos_build_inverted",
+    "ccake_eos_destroy", "ccake_eos_invert", "ccake_eos_invert_noalloc", "ccake_eos_build_inverted",
     "ccake_eos_offline_eval",
     "ccake_workspace_bytes", "ccake_create",
     "ccake_init_particles", "ccake_set_state", "ccake_get_state", "ccake_time", "ccake_step",
@@ -134,6 +134,7 @@ def lib():
             "ccake_eos_create_table": [ctypes.POINTER(vp), ip, dp, dp, dp, i32, dbl],
             "ccake_eos_destroy": [vp],
             "ccake_eos_invert": [vp, i32, i32, i64, vp, vp, vp, vp],
+            "ccake_eos_invert_noalloc": [vp, i32, i32, i64, vp, vp, vp, vp],
             "ccake_eos_build_inverted": [vp, ctypes.POINTER(InvGrid), vp],
             "ccake_eos_offline_eval": [vp, i32, i64, vp, vp, vp, vp],
             "ccake_workspace_bytes": [ctypes.POINTER(Config), i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -240,15 +241,16 @@ class Eos:
                                             max_iter, tol), what="eos_create_table")
         return cls(h)
 
-    def invert(self, mode, ncharge, x4, device="cuda:0"):
-        """(s or e, nB, nS, nQ) [4, n] -> (T, muB, muS, muQ) [4, n] and the in-table flags."""
+    def invert(self, mode, ncharge, x4, device="cuda:0", noalloc=False):
+        """(s or e, nB, nS, nQ) [4, n] -> (T, muB, muS, muQ) [4, n] and the
+        in-table flags; noalloc: through ccake_eos_invert_noalloc."""
         import torch
         x = torch.as_tensor(_f64(x4), device=device).contiguous()
         n = x.shape[1]
         out = torch.empty_like(x)
         it = torch.empty(n, dtype=torch.int32, device=device)
         stream = torch.cuda.current_stream(device)
-        fn = lib().ccake_eos_invert
+        fn = lib().ccake_eos_invert_noalloc if noalloc else lib().ccake_eos_invert
         _check(fn(self.h, mode, ncharge, n, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                   ctypes.c_void_p(it.data_ptr()), ctypes.c_void_p(stream.cuda_stream)), self.h)
         return out.cpu().numpy(), it.cpu().numpy()

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libccake_hip.so")
 DRIVER = os.path.join(PKG, "ccake_bench")
-SOURCES = ["binning.hip", "stage.hip", "kernels.hip", "runtime.cpp", "server.cpp"]
+SOURCES = ["binning.hip", "stage.hip", "kernels.hip", "runtime.cpp", "server.cpp", "noalloc.hip"]
 ARCH = os.environ.get("CCAKE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
