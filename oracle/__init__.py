@@ -389,3 +389,69 @@ def evolve(prm: Params, eos: Eos, t0: float, dt: float, nsteps: int, y):
             raise RuntimeError(f"oracle: {bad} EoS inversions did not converge at t={t}")
         t += dt
     return t, y, aux
+
+
+# ---------------------------------------------------------------------------
+# Constant-energy-density freeze-out surface ("Freeze-out hypersurface
+# construction", eq. efo_surface and eq. fonormal), as a record per particle.
+# Reading: a particle crosses e = e_fo in the step [t_{k-1}, t_k] in which its
+# energy density, evaluated at the step starts, falls from >= e_fo to < e_fo
+# (particles already below e_fo at the first evaluation never cross).  Its
+# record holds the crossing time t_fo from linear interpolation of e in x^0
+# between the two evaluations, its position moved back from t_k to t_fo
+# along its velocity (dx^i/dx^0 = u^i / u^0), and u^i, T, mu_q and the surface
+# element d sigma_mu (eq. fonormal with the SPH gradient of e and the time
+# derivative from the energy equation, the oracle's A_DSIG rows) at t_k.
+FO_ID, FO_T, FO_X1, FO_X2, FO_X3, FO_U1, FO_U2, FO_U3, FO_T_, FO_MUB, FO_MUS, FO_MUQ, \
+    FO_DS0, FO_DS1, FO_DS2, FO_DS3 = range(16)
+FO_NCOL = 16
+
+
+def freezeout_records(prm: Params, t_prev, t, e_prev, y, aux, frozen, e_fo):
+    """Records (rows of FO_NCOL values) of the particles that cross e_fo
+    between an evaluation at t_prev (energy densities e_prev) and one at t
+    (state y, diagnostics aux); frozen marks the particles already recorded
+    and is updated in place."""
+    e = aux[A_E]
+    cross = (~frozen) & (e_prev >= e_fo) & (e < e_fo)
+    dim = prm.dim
+    gam = aux[A_GAMMA]
+    recs = np.zeros((int(cross.sum()), FO_NCOL))
+    for r, i in enumerate(np.flatnonzero(cross)):
+        tfo = t - (t - t_prev) * (e_fo - e[i]) / (e_prev[i] - e[i])
+        recs[r, FO_ID] = i
+        recs[r, FO_T] = tfo
+        for k in range(dim):
+            recs[r, FO_X1 + k] = y[V_X1 + k, i] - (t - tfo) * y[V_U1 + k, i] / gam[i]
+            recs[r, FO_U1 + k] = y[V_U1 + k, i]
+        recs[r, FO_T_] = aux[A_T, i]
+        for q in range(3):
+            recs[r, FO_MUB + q] = aux[A_MUB + q, i]
+        for m in range(4):
+            recs[r, FO_DS0 + m] = aux[A_DSIG0 + m, i]
+    frozen |= cross
+    return recs
+
+
+def evolve_freezeout(prm: Params, eos: Eos, t0: float, dt: float, nsteps: int, y, e_fo: float):
+    """nsteps Heun steps from (t0, y), evaluating the diagnostics at every
+    step start t_0 .. t_{nsteps-1} and recording the freeze-out crossings
+    between consecutive step starts; returns (t, y, records sorted by
+    particle)."""
+    n = y.shape[1]
+    frozen = np.zeros(n, dtype=bool)
+    t, e_prev, t_prev = t0, None, None
+    out = []
+    for _ in range(nsteps):
+        _, aux, bad = rhs(prm, eos, t, y)
+        if bad:
+            raise RuntimeError(f"oracle: {bad} EoS inversions did not converge at t={t}")
+        if e_prev is not None:
+            out.append(freezeout_records(prm, t_prev, t, e_prev, y, aux, frozen, e_fo))
+        e_prev, t_prev = aux[A_E].copy(), t
+        y, _, bad = heun_step(prm, eos, t, dt, y)
+        if bad:
+            raise RuntimeError(f"oracle: {bad} EoS inversions did not converge at t={t}")
+        t += dt
+    recs = np.concatenate(out) if out else np.zeros((0, FO_NCOL))
+    return t, y, recs[np.argsort(recs[:, FO_ID], kind="stable")]

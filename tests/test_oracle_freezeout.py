@@ -13,6 +13,11 @@ d sigma_mu = n_mu / (sigma |u^mu n_mu|) (m = 1).
   orthogonal to u, so d sigma = 0;
 * everywhere: |u^mu d sigma_mu| sigma = 1 and g^{mu nu} d sigma_mu d sigma_nu
   = +-|d sigma|^2 with n a unit vector.
+
+And of the surface built from them (eq. efo_surface): each particle's
+crossing of e = e_fo between step starts, in Bjorken flow (closed-form
+crossing time) and in Gubser flow (closed-form energy density at the
+crossings and closed-form normals, converging under refinement).
 """
 import numpy as np
 
@@ -105,3 +110,86 @@ def test_normalisation_everywhere(oracle_mod):
     want = -np.sqrt(np.abs(dsds)) * dede / np.sqrt(np.abs(dede))
     assert np.allclose(dsde[have], want[have], rtol=1e-10, atol=0)
     assert (dede[have] > 0).any() and (dede[have] < 0).any()   # timelike and spacelike normals
+
+
+# ---------------------------------------------------------------------------
+# The surface itself: crossings of e = e_fo between step starts
+# ---------------------------------------------------------------------------
+def test_surface_bjorken_crossing_time(oracle_mod):
+    """Ideal conformal Bjorken flow (uniform lattice at rest in Milne
+    coordinates): e = e0 (tau0 / tau)^(4/3), so every interior particle
+    crosses e_fo once, at tau_fo = tau0 (e0 / e_fo)^(3/4); its surface
+    element is d sigma_mu = (tau / sigma*, 0, 0, 0) at the recording step."""
+    O = oracle_mod
+    side, dx, h, e0, dt = 31, 0.1, 0.15, 20.0, 0.01
+    xi = I.lattice((side, side), dx, -0.5 * dx * (side - 1))
+    n = xi.shape[1]
+    prm = O.params(dim=2, hyperbolic=True, viscous=False, ncharge=0, h=h, use_cells=1)
+    eos = O.eos_conformal(11.0)
+    dens = np.zeros((4, n))
+    dens[0] = e0
+    y = O.init(prm, eos, 1.0, xi, np.zeros_like(xi), 1, dens)
+    _, aux0, _ = O.rhs(prm, eos, 1.0, y)
+    e_fo = e0 * 1.2 ** (-4.0 / 3.0)  # tau_fo = 1.2 fm
+    _, _, recs = O.evolve_freezeout(prm, eos, 1.0, dt, 30, y, e_fo)
+    ids = recs[:, O.FO_ID].astype(int)
+    assert np.all(np.diff(ids) > 0)  # one record per particle at most
+    inner = np.abs(xi).max(axis=0) < 0.5 * dx * (side - 1) - 4 * h
+    m = inner[ids]
+    assert m.sum() == inner.sum()
+    tfo = recs[m, O.FO_T]
+    assert np.abs(tfo / 1.2 - 1.0).max() < 2e-3  # measured 7e-4 (Heun and interpolation errors)
+    # deep inside, where the rarefaction from the lattice edges has hardly
+    # arrived, the medium stays at rest and sigma* changes by ~1e-8
+    deep = (np.abs(xi).max(axis=0) < 0.45)[ids]
+    tfo = recs[deep, O.FO_T]
+    tk = 1.0 + np.ceil((tfo - 1.0) / dt - 1e-9) * dt  # the evaluation that saw e < e_fo
+    sstar = aux0[O.A_SIGSTAR, ids[deep]]
+    assert deep.sum() >= 64
+    assert np.abs(recs[deep, O.FO_DS0] * sstar / tk - 1.0).max() < 1e-6  # sigma* drifts by ~1e-8
+    for r in (O.FO_DS1, O.FO_DS2, O.FO_DS3, O.FO_U1, O.FO_U2):
+        assert np.abs(recs[deep, r]).max() < 1e-5 * recs[deep, O.FO_DS0].max()
+    assert np.abs(recs[deep, O.FO_X1] - xi[0, ids[deep]]).max() < 1e-9
+    assert np.abs(recs[deep, O.FO_X2] - xi[1, ids[deep]]).max() < 1e-9
+    # the temperature of the recording step, just below the freeze-out value
+    T_fo = (e_fo / 11.0) ** 0.25
+    assert np.all(recs[deep, O.FO_T_] < T_fo) and np.all(recs[deep, O.FO_T_] > 0.99 * T_fo)
+
+
+def gubser_surface_errors(O, n_side, spacing, h, dt, e_fo):
+    w = I.gubser_workload(n_side=n_side, spacing=spacing, h=h, dt=dt)
+    prm = O.params(dim=2, hyperbolic=True, viscous=False, ncharge=0, h=w.h, use_cells=1)
+    eos = O.eos_conformal(11.0)
+    y = O.init(prm, eos, w.t0, w.xi, w.u, w.dens_kind, w.dens)
+    _, _, recs = O.evolve_freezeout(prm, eos, w.t0, w.dt, w.nsteps, y, e_fo)
+    tf, x, yy = recs[:, O.FO_T], recs[:, O.FO_X1], recs[:, O.FO_X2]
+    # the closed-form energy density at the recorded crossings
+    e_dev = I.gubser_ideal(tf, x, yy)[0] / e_fo - 1.0
+    # the closed-form normal: -d_mu e (finite differences of the closed form
+    # in tau and along r), compared as the angle of (n_tau, n_r)
+    r = np.hypot(x, yy)
+    rs = np.where(r > 0, r, 1.0)
+    d = 1e-6
+    de_t = (I.gubser_ideal(tf + d, x, yy)[0] - I.gubser_ideal(tf - d, x, yy)[0]) / (2 * d)
+    de_r = (I.gubser_ideal(tf, x * (1 + d / rs), yy * (1 + d / rs))[0]
+            - I.gubser_ideal(tf, x * (1 - d / rs), yy * (1 - d / rs))[0]) / (2 * d)
+    ds_r = (recs[:, O.FO_DS1] * x + recs[:, O.FO_DS2] * yy) / rs
+    ang = np.arctan2(ds_r, recs[:, O.FO_DS0]) - np.arctan2(-de_r, -de_t)
+    sel = r < 2.5  # away from the lattice edge
+    rms = lambda a: float(np.sqrt(np.mean(a[sel] ** 2)))
+    return len(recs), rms(e_dev), float(np.abs(e_dev).max()), rms(ang)
+
+
+def test_surface_gubser_closed_form_and_convergence(oracle_mod):
+    """Ideal Gubser flow ("Code validation"), e_fo = e_G(tau = 1.5 fm, r = 0):
+    the closed-form energy density at the recorded crossing points equals
+    e_fo, and the recorded surface normals point along the closed form's
+    -d_mu e, up to the SPH error; both errors fall by more than 2x when h,
+    the spacing and dt are halved (measured: rms e 2.7% -> 0.85%, rms angle
+    0.081 -> 0.021 rad)."""
+    O = oracle_mod
+    e_fo = float(I.gubser_ideal(1.5, np.zeros(1), np.zeros(1))[0][0])
+    n1, e1, emax1, a1 = gubser_surface_errors(O, 51, 0.2, 0.3, 0.005, e_fo)
+    assert n1 > 200 and e1 < 0.04 and emax1 < 0.06 and a1 < 0.12
+    n2, e2, emax2, a2 = gubser_surface_errors(O, 101, 0.1, 0.15, 0.0025, e_fo)
+    assert n2 > 3 * n1 and e2 < 0.5 * e1 and a2 < 0.5 * a1
