@@ -345,6 +345,36 @@ ccake_status ccake_debug_pairs(ccake_sim* sim, int64_t cap, int32_t* a, int32_t*
  * first (right after initialisation or a state upload).  Synchronises.      */
 ccake_status ccake_debug_pairs_cached(ccake_sim* sim, int64_t cap, int32_t* a, int32_t* b, int64_t* npairs);
 
+/* Freeze-out hypersurface ("Freeze-out hypersurface construction", eq.
+ * efo_surface and eq. fonormal).  With e_fo > 0 every step looks, at its
+ * start x^0 = t_k, for the particles whose energy density fell below e_fo
+ * since the previous step start (e(t_{k-1}) >= e_fo > e(t_k)), each particle
+ * once.  A crossing particle gets one record of CCAKE_FO_NCOL doubles:
+ *   ID        caller index of the particle (as a double)
+ *   T         x^0 of the crossing, t_k - (t_k - t_{k-1}) (e_fo - e_k) / (e_{k-1} - e_k)
+ *   X1..X3    position moved back to that x^0 along dx^i/dx^0 = u^i/u^0
+ *   U1..U3    u^i at t_k
+ *   TEMP, MUB, MUS, MUQ   T and mu_q at t_k (fm^-1)
+ *   DS0..DS3  d sigma_mu at t_k as in CCAKE_AUX_DSIG0..3
+ * (unused spatial components zero).  The step start's energy densities come
+ * from the step's own first stage, so the surface costs no extra evaluation.
+ * ccake_set_freezeout(e_fo) (0 switches the surface off) forgets the records
+ * and every particle's history; so do ccake_init_particles and
+ * ccake_set_state.  Synchronises.  CCAKE_E_ARG for a negative or non-finite
+ * e_fo.                                                                       */
+enum {
+  CCAKE_FO_ID = 0, CCAKE_FO_T, CCAKE_FO_X1, CCAKE_FO_X2, CCAKE_FO_X3, CCAKE_FO_U1, CCAKE_FO_U2,
+  CCAKE_FO_U3, CCAKE_FO_TEMP, CCAKE_FO_MUB, CCAKE_FO_MUS, CCAKE_FO_MUQ, CCAKE_FO_DS0, CCAKE_FO_DS1,
+  CCAKE_FO_DS2, CCAKE_FO_DS3,
+  CCAKE_FO_NCOL
+};
+ccake_status ccake_set_freezeout(ccake_sim* sim, double e_fo);
+
+/* The records found so far, in the order found (not sorted by particle):
+ * count gets their number (at most n) and out [count][CCAKE_FO_NCOL] (host
+ * or device per mem) the first min(count, cap) of them.  Synchronises.       */
+ccake_status ccake_freezeout_records(ccake_sim* sim, int64_t cap, double* out, int64_t* count, int32_t mem);
+
 ccake_status ccake_destroy(ccake_sim* sim);
 
 /* ------------------------------------------------------------ serving ---- */

@@ -33,6 +33,9 @@ KAPPA_T2_BSQ = ((0.0482, -0.0482, 0.0), (-0.0482, 0.1447, 0.0147), (0.0, 0.0147,
  AUX_CS2, AUX_INTABLE, AUX_GAMMA, AUX_THETA, AUX_NNB, AUX_F1, AUX_F2, AUX_F3, AUX_NEWTON,
  AUX_EOS_EVALS, AUX_KN_SHEAR, AUX_REINV_SHEAR, AUX_KN_BULK, AUX_REINV_BULK, AUX_DE0, AUX_DE1, AUX_DE2,
  AUX_DE3, AUX_DSIG0, AUX_DSIG1, AUX_DSIG2, AUX_DSIG3) = range(NAUX)
+FO_NCOL = 16
+(FO_ID, FO_T, FO_X1, FO_X2, FO_X3, FO_U1, FO_U2, FO_U3, FO_TEMP, FO_MUB, FO_MUS, FO_MUQ,
+ FO_DS0, FO_DS1, FO_DS2, FO_DS3) = range(FO_NCOL)
 
 EXPORTS = [
     "ccake_eos_create_conformal", "ccake_eos_create_gas", "ccake_eos_create_table",
@@ -41,7 +44,7 @@ EXPORTS = [
     "ccake_workspace_bytes", "ccake_create",
     "ccake_init_particles", "ccake_set_state", "ccake_get_state", "ccake_time", "ccake_step",
     "ccake_check", "ccake_set_sources", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
-    "ccake_debug_pairs_cached",
+    "ccake_debug_pairs_cached", "ccake_set_freezeout", "ccake_freezeout_records",
     "ccake_destroy", "ccake_server_create", "ccake_server_submit", "ccake_server_poll",
     "ccake_server_drain", "ccake_server_release", "ccake_server_stats", "ccake_server_destroy",
     "ccake_last_error",
@@ -153,6 +156,8 @@ def lib():
             "ccake_totals": [vp, dp, ctypes.POINTER(Counters)],
             "ccake_debug_pairs": [vp, i64, vp, vp, ctypes.POINTER(i64)],
             "ccake_debug_pairs_cached": [vp, i64, vp, vp, ctypes.POINTER(i64)],
+            "ccake_set_freezeout": [vp, dbl],
+            "ccake_freezeout_records": [vp, i64, vp, ctypes.POINTER(i64), i32],
             "ccake_destroy": [vp],
             "ccake_server_create": [ctypes.POINTER(vp), ctypes.POINTER(Config), vp, ctypes.c_size_t, i64, i32,
                                     dbl, vp],
@@ -407,6 +412,21 @@ class Sim:
         b = b[:cnt.value].cpu().numpy().astype(np.int64)
         order = np.lexsort((b, a))
         return a[order], b[order]
+
+    def set_freezeout(self, e_fo):
+        """Freeze-out surface at energy density e_fo (fm^-4; 0: off); forgets
+        the records so far (ccake_set_freezeout)."""
+        _check(lib().ccake_set_freezeout(self.h, float(e_fo)), self.h)
+
+    def freezeout_records(self):
+        """Records [count][FO_NCOL] (ccake_freezeout_records), sorted by
+        particle."""
+        cnt = ctypes.c_int64()
+        _check(lib().ccake_freezeout_records(self.h, 0, None, ctypes.byref(cnt), HOST), self.h)
+        out = np.empty((max(cnt.value, 1), FO_NCOL))
+        _check(lib().ccake_freezeout_records(self.h, cnt.value, _ptr(out), ctypes.byref(cnt), HOST), self.h)
+        out = out[:cnt.value]
+        return out[np.argsort(out[:, FO_ID], kind="stable")]
 
     def close(self):
         if getattr(self, "h", None):

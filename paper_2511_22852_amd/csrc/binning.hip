@@ -115,7 +115,7 @@ __global__ void k_grid(BatchDev b, Params prm, int dim) {
     for (int k = 0; k < 3; ++k) lo[k] = hi[k] = 0.0;
     if (E->n > 0) E->capacity_err += 1;  // every coordinate non-finite
   }
-  double edge = prm.cell_edge / SUBCELLS;
+  double edge = prm.cell_edge / subcells(dim);
   int64_t nc[3] = {1, 1, 1};
   bool fits = false;
   // coarsen the grid (never below the cutoff) until it fits the capacity;
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(256) k_scatter(BatchDev b, int64_t nslots) {
 }
 
 // one wave per cell: the rank of each member is the number of members with a
-// smaller original id (ids are unique within an event)
+// smaller (x^1 at binning, original id) key (ids are unique within an event)
 constexpr int SORT_CAP = 1024;  // members per cell held in LDS by one wave
 // sort key inside a cell: binning-time x^1 (total order on the bits), then id
 struct CellKey {
@@ -316,18 +316,24 @@ __global__ void __launch_bounds__(256) k_cellsort(BatchDev b, int dim) {
         b.perm[s + rank] = s_p[w][k];
       }
       __builtin_amdgcn_wave_barrier();
-    } else if (lane == 0) {
-      // oversized cell (degenerate grid): insertion sort by one lane
-      for (int32_t i = s + 1; i < s + m; ++i) {
-        const int32_t p = b.perm[i];
-        const CellKey pk = cell_key(b, p);
-        int32_t j = i - 1;
-        while (j >= s && pk < cell_key(b, b.perm[j])) {
-          b.perm[j + 1] = b.perm[j];
-          --j;
-        }
-        b.perm[j + 1] = p;
+    } else if (!E.nonfinite) {
+      // oversized cell (a degenerate grid): the lanes rank the members
+      // against all others in global memory (m^2 / 64 comparisons per lane)
+      // into the sorted-key array, which is free until the gather, then
+      // copy back.  An event already flagged non-finite is left unsorted:
+      // its results are void, and its positions may all share one cell.
+      for (int k = lane; k < m; k += 64) {
+        const int32_t p = b.perm[s + k];
+        const CellKey mine = cell_key(b, p);
+        int rank = 0;
+        for (int q = 0; q < m; ++q) rank += cell_key(b, b.perm[s + q]) < mine ? 1 : 0;
+        b.keys[s + rank] = p;
       }
+      __threadfence();
+      __builtin_amdgcn_wave_barrier();
+      for (int k = lane; k < m; k += 64) b.perm[s + k] = b.keys[s + k];
+      __threadfence();
+      __builtin_amdgcn_wave_barrier();
     }
   }
 }

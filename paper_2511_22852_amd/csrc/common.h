@@ -44,10 +44,19 @@ enum Rec { Q_PP, Q_A11, Q_A12, Q_A13, Q_A21, Q_A22, Q_A23, Q_A31, Q_A32, Q_A33,
 // alpha_q = mu_q/T and F^k_q/sigma*^2 with F = J - v J^0 (row QD_FB1 + 3q + k-1), and Pi
 enum DRec { QD_AB, QD_AS, QD_AQ, QD_FB1, QD_FB2, QD_FB3, QD_FS1, QD_FS2, QD_FS3, QD_FQ1, QD_FQ2, QD_FQ3, QD_PI, NDREC };
 
-// warm-start record of the EoS inversion (carried with the particle): the
-// last root of the analytic backup EoS and, when the table answered, the last
-// root of the table interpolant (W_TT = 0 when there is none)
-enum Warm { W_GT, W_GMUB, W_GMUS, W_GMUQ, W_TT, W_TMUB, W_TMUS, W_TMUQ, NWARM };
+// record carried with the particle from step to step: the warm start of the
+// EoS inversion (the last root of the analytic backup EoS and, when the table
+// answered, the last root of the table interpolant; W_TT = 0 when there is
+// none), then the freeze-out bookkeeping (the energy density at the last step
+// start, and 1 once the particle has crossed e_fo)
+enum Warm { W_GT, W_GMUB, W_GMUS, W_GMUQ, W_TT, W_TMUB, W_TMUS, W_TMUQ, NWARM_EOS,
+            W_EPREV = NWARM_EOS, W_FROZEN, NWARM };
+
+// freeze-out surface record ("Freeze-out hypersurface construction"): original
+// id, crossing time, position at the crossing, u^i, T, mu_q and d sigma_mu at
+// the recording step
+enum FoCol { FO_ID, FO_T, FO_X1, FO_X2, FO_X3, FO_U1, FO_U2, FO_U3, FO_TEMP, FO_MUB, FO_MUS, FO_MUQ,
+             FO_DS0, FO_DS1, FO_DS2, FO_DS3, FO_NCOL };
 
 // density sums of a particle (lab frame, kernel normalisation applied) and its neighbour count
 enum DSum { DS_SIG, DS_S, DS_NB, DS_NS, DS_NQ, DS_NNB, NDSUM };
@@ -105,16 +114,23 @@ struct SourceSet {
   SourceDev s[MAX_SOURCES];
 };
 
-// cells per kernel support along an axis: the grid cell edge is
-// (2h + skin) / SUBCELLS and a particle's candidates lie within SUBCELLS cells
-#ifndef CCAKE_SUBCELLS
-#define CCAKE_SUBCELLS 2
+// cells per kernel support along an axis (2+1D, 3+1D): the grid cell edge is
+// (2h + skin) / subcells and a particle's candidates lie within subcells
+// cells per axis; finer cells cut the candidate rows closer to the ball
+#ifndef CCAKE_SUBCELLS2
+#define CCAKE_SUBCELLS2 2
 #endif
-constexpr int SUBCELLS = CCAKE_SUBCELLS;
+#ifndef CCAKE_SUBCELLS3
+#define CCAKE_SUBCELLS3 2
+#endif
+__host__ __device__ constexpr int subcells(int dim) { return dim == 3 ? CCAKE_SUBCELLS3 : CCAKE_SUBCELLS2; }
+__host__ __device__ constexpr int row_count(int dim) {
+  return dim == 3 ? (2 * subcells(3) + 1) * (2 * subcells(3) + 1) : 2 * subcells(2) + 1;
+}
 // the first and last candidate slots of a particle's neighbour rows
-// ((2*SUBCELLS + 1) rows in 2+1D, (2*SUBCELLS + 1)^2 in 3+1D), searched by
-// each binning at the binning-time positions and used until the next binning
-constexpr int ROW_CACHE = 2 * (2 * SUBCELLS + 1) * (2 * SUBCELLS + 1);
+// (row_count(dim) rows), searched by each binning at the binning-time
+// positions and used until the next binning
+constexpr int ROW_CACHE = 2 * (row_count(3) > row_count(2) ? row_count(3) : row_count(2));
 
 struct Params {
   int32_t dim, hyperbolic, viscous, ncharge, density_mode, mixed;
@@ -129,6 +145,7 @@ struct Params {
   double c_pisig;     // coefficient of the ADNH shear term pi_lambda^<i sigma^j>lambda
   double d_JPi[3];    // delta_JPi^q / beta: currents coupled to nabla Pi (diffusion)
   double cell_edge;   // >= 2h + skin
+  double e_fo;        // freeze-out energy density (fm^-4); 0: no surface
   const SourceSet* src = nullptr;  // external sources (device), or none
 };
 
@@ -143,6 +160,7 @@ struct EventDev {
   double lo[3];       // grid origin (this step)
   double edge;        // cell edge (this step, >= cell_edge)
   double t;           // current x^0
+  double t_prev;      // x^0 at the start of the previous step
   double dt;          // step size
   uint32_t nonfinite; // count of non-finite state updates (sticky)
   uint32_t noconv;    // count of EoS inversions that failed (sticky)
@@ -201,6 +219,10 @@ struct BatchDev {
   int32_t* perm;     // sorted slot -> home slot
   double* xbin;      // x^1 of each slot at its event's last binning (sorted order)
   int32_t* rows;     // [ROW_CACHE][cap] row bounds (lo, hi per row), written by each binning
+  double* fo_rec;    // [cap][FO_NCOL] freeze-out records, in the order found
+  int32_t* fo_slot;  // [cap] sorted slot of each record's particle (step of its crossing)
+  int32_t* fo_mark;  // [cap] per sorted slot: record found in this step's first stage, or -1
+  uint32_t* fo_ctr;  // [2] records so far, records before this step
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

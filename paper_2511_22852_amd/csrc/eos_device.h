@@ -383,7 +383,7 @@ __device__ __forceinline__ bool finite4(const double* x) {
 // if its root lies inside the table axes the table interpolant is solved and
 // accepted when it converges inside; otherwise the gas is the backup.
 // Conformal: closed form.
-// Warm start (warm[NWARM] or null): the gas solve starts from the last gas
+// Warm start (warm[NWARM_EOS] or null): the gas solve starts from the last gas
 // root; the table solve starts from the last table root moved by the change
 // of the gas root since then (the two roots differ by the interpolation
 // error, which varies slowly), else from the gas root.  Both solves converge

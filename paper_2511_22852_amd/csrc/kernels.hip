@@ -14,6 +14,7 @@ namespace ccake {
 __global__ void k_advance(BatchDev b) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= b.max_events || !b.evt[e].active) return;
+  b.evt[e].t_prev = b.evt[e].t;
   b.evt[e].t += b.evt[e].dt;
 }
 

@@ -3,6 +3,7 @@
 // loop lives in server.cpp and drives the same launchers with many events.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -85,6 +86,7 @@ Params to_params(const ccake_config& c) {
   p.c_pisig = c.viscous ? c.c_pisig : 0.0;
   for (int q = 0; q < 3; ++q) p.d_JPi[q] = (c.diffusion && c.viscous) ? c.d_JPi[q] : 0.0;
   p.cell_edge = 2.0 * c.h + c.skin;
+  p.e_fo = 0.0;
   return p;
 }
 
@@ -140,6 +142,10 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.perm = take(&o, I4 * cap);
   L.xbin = take(&o, D8 * cap);
   L.rows = take(&o, I4 * ROW_CACHE * cap);
+  L.fo_rec = take(&o, D8 * FO_NCOL * cap);
+  L.fo_slot = take(&o, I4 * cap);
+  L.fo_mark = take(&o, I4 * cap);
+  L.fo_ctr = take(&o, I4 * 2);
   L.cs = take(&o, I4 * (ccap + 1));
   L.cf = take(&o, I4 * (ccap + 1));
   L.evt = take(&o, sizeof(EventDev) * nev);
@@ -170,6 +176,10 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.perm = (int32_t*)(base + L.perm);
   b.xbin = (double*)(base + L.xbin);
   b.rows = (int32_t*)(base + L.rows);
+  b.fo_rec = (double*)(base + L.fo_rec);
+  b.fo_slot = (int32_t*)(base + L.fo_slot);
+  b.fo_mark = (int32_t*)(base + L.fo_mark);
+  b.fo_ctr = (uint32_t*)(base + L.fo_ctr);
   b.cell_start = (int32_t*)(base + L.cs);
   b.cell_fill = (int32_t*)(base + L.cf);
   b.evt = (EventDev*)(base + L.evt);
@@ -404,6 +414,9 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
   hipError_t he = hipMemcpy(s->b.ev, ev.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (ccap + 1));
   if (he == hipSuccess) he = hipMemset(s->base + L.src, 0, sizeof(SourceSet));
+  // no freeze-out record yet; no slot marked
+  if (he == hipSuccess) he = hipMemset(s->b.fo_mark, 0xFF, sizeof(int32_t) * n);
+  if (he == hipSuccess) he = hipMemset(s->b.fo_ctr, 0, 2 * sizeof(uint32_t));
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) {
     ccake_destroy(s);
@@ -465,6 +478,8 @@ static ccake_status stage_out(ccake_sim* s, double* dst, const double* src, size
   return CCAKE_OK;
 }
 
+static ccake_status reset_surface(ccake_sim* s);
+
 extern "C" ccake_status ccake_init_particles(ccake_sim* s, double t0, const double* xi, const double* u,
                                              int32_t dens_kind, const double* dens, int32_t mem) {
   if (!s) return CCAKE_E_ARG;
@@ -500,6 +515,8 @@ extern "C" ccake_status ccake_init_particles(ccake_sim* s, double t0, const doub
   HIPCHK(s, launch_bin(s->b, s->prm, 1, n, n, 0x1FFFFu, s->stream));
   HIPCHK(s, launch_init(s->b, s->prm, s->eos, dens_kind, s->b.rec, n, s->stream));
   HIPCHK(s, launch_commit(s->b, n, 0x1FFFFu, s->stream));
+  st = reset_surface(s);
+  if (st) return st;
   st = fetch_event(s);
   if (st) return st;
   s->t = t0;
@@ -516,7 +533,8 @@ extern "C" ccake_status ccake_set_state(ccake_sim* s, double t, const double* y,
   st = stage_in(s, s->b.Y1, y, (size_t)NROW * s->n, mem);
   if (st) return st;
   HIPCHK(s, launch_upload(s->b, 0, s->n, s->b.Y1, NROW, s->stream));
-  HIPCHK(s, hipStreamSynchronize(s->stream));
+  st = reset_surface(s);
+  if (st) return st;
   s->t = t;
   s->initialised = true;
   s->need_bin = true;
@@ -828,6 +846,53 @@ extern "C" ccake_status ccake_debug_pairs_cached(ccake_sim* s, int64_t cap, int3
   HIPCHK(s, launch_pairs_cached(v, s->prm, s->n, counter, cap, a, b, s->stream));
   HIPCHK(s, hipMemcpyAsync(npairs, counter, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  return CCAKE_OK;
+}
+
+static_assert(CCAKE_FO_NCOL == FO_NCOL && CCAKE_FO_TEMP == FO_TEMP && CCAKE_FO_DS0 == FO_DS0, "record columns");
+
+// forget the surface records and every particle's crossing history (no
+// previous energy density, nothing frozen); rows W_EPREV and W_FROZEN are the
+// last two warm-start rows, contiguous in both copies
+static ccake_status reset_surface(ccake_sim* s) {
+  static_assert(W_FROZEN == W_EPREV + 1 && NWARM == W_FROZEN + 1, "surface rows last");
+  const size_t cap = (size_t)s->b.cap;
+  HIPCHK(s, hipMemsetAsync(s->b.warm + (size_t)W_EPREV * cap, 0, 2 * cap * sizeof(double), s->stream));
+  HIPCHK(s, hipMemsetAsync(s->b.warms + (size_t)W_EPREV * cap, 0, 2 * cap * sizeof(double), s->stream));
+  HIPCHK(s, hipMemsetAsync(s->b.fo_mark, 0xFF, cap * sizeof(int32_t), s->stream));
+  HIPCHK(s, hipMemsetAsync(s->b.fo_ctr, 0, 2 * sizeof(uint32_t), s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return CCAKE_OK;
+}
+
+extern "C" ccake_status ccake_set_freezeout(ccake_sim* s, double e_fo) {
+  if (!s) return CCAKE_E_ARG;
+  if (!(e_fo >= 0.0) || !std::isfinite(e_fo))
+    return fail(s, CCAKE_E_ARG, "ccake_set_freezeout: e_fo must be finite and >= 0");
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  ccake_status st = reset_surface(s);
+  if (st) return st;
+  s->prm.e_fo = e_fo;
+  // captured steps hold the old parameters
+  for (int k = 0; k < 2; ++k) {
+    if (s->graph_ready[k]) (void)hipGraphExecDestroy(s->graph[k]);
+    s->graph_ready[k] = false;
+  }
+  return CCAKE_OK;
+}
+
+extern "C" ccake_status ccake_freezeout_records(ccake_sim* s, int64_t cap, double* out, int64_t* count,
+                                               int32_t mem) {
+  if (!s) return CCAKE_E_ARG;
+  if (!count || cap < 0 || (cap > 0 && !out) || (mem != CCAKE_HOST && mem != CCAKE_DEVICE))
+    return fail(s, CCAKE_E_ARG, "ccake_freezeout_records: bad arguments");
+  uint32_t ctr = 0;
+  HIPCHK(s, hipMemcpyAsync(&ctr, s->b.fo_ctr, sizeof ctr, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  const int64_t found = std::min<int64_t>((int64_t)ctr, s->b.cap);
+  *count = found;
+  const int64_t m = std::min(found, cap);
+  if (m > 0) return stage_out(s, out, s->b.fo_rec, (size_t)m * FO_NCOL, mem);
   return CCAKE_OK;
 }
 

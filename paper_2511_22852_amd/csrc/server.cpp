@@ -367,6 +367,8 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
   (void)hipMemset(s->b.ev, 0xFF, sizeof(int32_t) * max_particles);
   (void)hipMemset(s->b.evt, 0, sizeof(EventDev) * max_events);
   (void)hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (s->ccap + 1));
+  (void)hipMemset(s->b.fo_mark, 0xFF, sizeof(int32_t) * max_particles);
+  (void)hipMemset(s->b.fo_ctr, 0, 2 * sizeof(uint32_t));
   (void)hipDeviceSynchronize();
   s->palloc.init(max_particles);
   s->calloc_.init(s->ccap + max_events);

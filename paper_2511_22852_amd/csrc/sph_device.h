@@ -157,7 +157,7 @@ __device__ __forceinline__ double interval_gap(double v, double c0, double e) {
 }
 
 // Candidate slot ranges of a particle at xa whose binning cell is key: the
-// x-rows of cells within SUBCELLS cells in y (and z), each row trimmed to the
+// x-rows of cells within subcells(D) cells in y (and z), each row trimmed to the
 // cells that intersect the ball of radius reach around xa.  Cells of a row
 // are contiguous in slot order (x is the fastest axis of the key), so each
 // row is one range [lo, hi).  reach must cover the kernel support plus the
@@ -176,11 +176,12 @@ __device__ __forceinline__ void for_each_row(const BatchDev& b, const EventDev& 
   const double R = reach * (1.0 + 1e-9);
   const double R2 = R * R;
   const int32_t* cs = b.cell_start + E.c_base;
-  for (int dz = (D == 3 ? -SUBCELLS : 0); dz <= (D == 3 ? SUBCELLS : 0); ++dz) {
+  constexpr int SUB = subcells(D);
+  for (int dz = (D == 3 ? -SUB : 0); dz <= (D == 3 ? SUB : 0); ++dz) {
     const int z = iz + dz;
     if (z < 0 || z >= nz) continue;
     const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
-    for (int dy = -SUBCELLS; dy <= SUBCELLS; ++dy) {
+    for (int dy = -SUB; dy <= SUB; ++dy) {
       const int y = iy + dy;
       if (y < 0 || y >= ny) continue;
       const double gy = interval_gap(xa[1], E.lo[1] + y * e, e);
@@ -188,8 +189,8 @@ __device__ __forceinline__ void for_each_row(const BatchDev& b, const EventDev& 
       if (!(r2 >= 0.0)) continue;
       const double rx = sqrt(r2) * (1.0 + 1e-9);
       int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
-      x0 = max(x0, max(ix - SUBCELLS, 0));
-      x1 = min(x1, min(ix + SUBCELLS, nx - 1));
+      x0 = max(x0, max(ix - SUB, 0));
+      x1 = min(x1, min(ix + SUB, nx - 1));
       if (x0 > x1) continue;
       const int c = (z * ny + y) * nx;
       f(cs[c + x0], cs[c + x1 + 1]);
@@ -212,7 +213,8 @@ __device__ __forceinline__ void for_each_row(const BatchDev& b, const EventDev& 
 // RowCursor below.
 template <int D>
 struct RowBlock {
-  static constexpr int W = 2 * SUBCELLS + 1;
+  static constexpr int SUB = subcells(D);
+  static constexpr int W = 2 * SUB + 1;
   static constexpr int ROWS = D == 3 ? W * W : W;
 };
 
@@ -240,7 +242,7 @@ __device__ __forceinline__ void team_rows(const BatchDev& b, const EventDev& E, 
     s0[q] = e0[q] = s1[q] = e1[q] = 0;
     xl[q] = xh[q] = 0.0;
     if (r >= ROWS) continue;
-    const int dz = D == 3 ? r / W - SUBCELLS : 0, dy = r % W - SUBCELLS;
+    const int dz = D == 3 ? r / W - RowBlock<D>::SUB : 0, dy = r % W - RowBlock<D>::SUB;
     const int z = iz + dz, y = iy + dy;
     if (z < 0 || z >= nz || y < 0 || y >= ny) continue;
     const double gz = D == 3 ? interval_gap(xa[2], E.lo[2] + z * e, e) : 0.0;
@@ -249,8 +251,8 @@ __device__ __forceinline__ void team_rows(const BatchDev& b, const EventDev& E, 
     if (!(r2 >= 0.0)) continue;
     const double rx = sqrt(r2) * (1.0 + 1e-9);
     int x0 = (int)floor((xa[0] - rx - E.lo[0]) * ie), x1 = (int)floor((xa[0] + rx - E.lo[0]) * ie);
-    x0 = max(x0, max(ix - SUBCELLS, 0));
-    x1 = min(x1, min(ix + SUBCELLS, nx - 1));
+    x0 = max(x0, max(ix - RowBlock<D>::SUB, 0));
+    x1 = min(x1, min(ix + RowBlock<D>::SUB, nx - 1));
     if (x0 > x1) continue;
     const int c = (z * ny + y) * nx;
     s0[q] = cs[c + x0];

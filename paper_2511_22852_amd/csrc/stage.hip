@@ -382,12 +382,12 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
         d2[u] = dist2<D>(A.xa, xb[u]);
         ok[u] = v[u] && d2[u] < r2max && d2[u] > 0.0;
       }
-      RT r[U][4 * GR::G];
+      RT rec[U][4 * GR::G];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int g = 0; g < GR::G; ++g) H.q(g)[k[u]].get(r[u] + 4 * g);
-      A.template add_block<U>(ok, xb, d2, r);
+        for (int g = 0; g < GR::G; ++g) H.q(g)[k[u]].get(rec[u] + 4 * g);
+      A.template add_block<U>(ok, xb, d2, rec);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (DIFF && ok[u]) {
@@ -436,10 +436,47 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
 
 
 // ---------------------------------------------------------------------------
+// Freeze-out crossing of particle j at the start of a step ("Freeze-out
+// hypersurface construction", eq. efo_surface): its energy density fell from
+// >= e_fo at the previous step start to < e_fo now, and it has not crossed
+// before.  The record gets the crossing time (e linear in x^0 between the two
+// step starts), the position moved back to it along dx^i/dx^0 = u^i / u^0,
+// and u^i, T, mu_q now; the update pass adds d sigma_mu (k_eom).
+template <int D>
+__device__ __forceinline__ void freezeout_crossing(const BatchDev& b, const Params& prm, const double* __restrict__ Y,
+                                                   int64_t j, const EventDev& E, const Thermo& th, const double u[4],
+                                                   double gam) {
+  const int64_t cap = b.cap;
+  const double ep = b.warms[(int64_t)W_EPREV * cap + j];
+  const bool frozen = b.warms[(int64_t)W_FROZEN * cap + j] != 0.0;
+  b.warms[(int64_t)W_EPREV * cap + j] = th.e;
+  if (frozen || !(ep >= prm.e_fo && th.e < prm.e_fo)) return;
+  b.warms[(int64_t)W_FROZEN * cap + j] = 1.0;
+  const uint32_t at = atomicAdd(&b.fo_ctr[0], 1u);
+  if (at >= (uint32_t)cap) return;  // each particle crosses once: cannot happen
+  double* r = b.fo_rec + (int64_t)at * FO_NCOL;
+  const double tfo = E.t - (E.t - E.t_prev) * (prm.e_fo - th.e) / (ep - th.e);
+  r[FO_ID] = (double)b.ids[j];
+  r[FO_T] = tfo;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r[FO_X1 + k] = k < D ? row(Y, cap, R_X1 + k, j) - (E.t - tfo) * u[1 + k] / gam : 0.0;
+    r[FO_U1 + k] = k < D ? u[1 + k] : 0.0;
+  }
+  r[FO_TEMP] = th.T;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) r[FO_MUB + q] = th.mu[q];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) r[FO_DS0 + m] = 0.0;
+  b.fo_slot[at] = (int32_t)j;
+  b.fo_mark[j] = (int32_t)at;
+}
+
+// fo: look for a freeze-out crossing (first stage of a step, surface on)
 template <int D, bool VISC, bool MIXED, int NQ>
 __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& prm, const EosDev& eos,
                                              const double* __restrict__ Y, int stage, int64_t j, int e, double* aux,
-                                             uint32_t& c_backup, uint32_t& c_iters, uint32_t& c_noconv) {
+                                             bool fo, uint32_t& c_backup, uint32_t& c_iters, uint32_t& c_noconv) {
   const EventDev& E = b.evt[e];
   const double t = E.t + stage * E.dt;
   const int64_t cap = b.cap;
@@ -468,16 +505,17 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
   // particle's last roots
   Thermo th;
   if (!(eos.inv.val && inv_lookup<NQ>(eos.inv, dens, th))) {
-    double warm[NWARM], wnew[NWARM];
+    double warm[NWARM_EOS], wnew[NWARM_EOS];
 #pragma unroll
-    for (int w = 0; w < NWARM; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
+    for (int w = 0; w < NWARM_EOS; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
     eos_invert<NQ>(eos, 0, dens, warm, th, wnew);
 #pragma unroll
-    for (int w = 0; w < NWARM; ++w) b.warms[(int64_t)w * cap + j] = wnew[w];
+    for (int w = 0; w < NWARM_EOS; ++w) b.warms[(int64_t)w * cap + j] = wnew[w];
   }
   c_noconv = th.ok ? 0u : 1u;
   c_backup = (!th.in_table && eos.kind == EOS_TABLE) ? 1u : 0u;
   c_iters = (uint32_t)th.iters;
+  if (fo) freezeout_crossing<D>(b, prm, Y, j, E, th, u, gam);
 
   const double w = th.e + th.p;
   const double eta = prm.eta_over_s * dens[0];
@@ -598,13 +636,14 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
 
 template <int D, bool VISC, bool MIXED, int NQ>
 __global__ void __launch_bounds__(128) k_eos(BatchDev b, Params prm, EosDev eos, const double* __restrict__ Y,
-                                             int stage, int64_t nslots, double* aux) {
+                                             int stage, int64_t nslots, double* aux, int fo) {
   const int64_t j = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   int e = -1;
   uint32_t c_backup = 0, c_iters = 0, c_noconv = 0;
   if (j < nslots) {
     e = b.ev[j];
-    if (e >= 0) eos_particle<D, VISC, MIXED, NQ>(b, prm, eos, Y, stage, j, e, aux, c_backup, c_iters, c_noconv);
+    if (e >= 0)
+      eos_particle<D, VISC, MIXED, NQ>(b, prm, eos, Y, stage, j, e, aux, fo != 0, c_backup, c_iters, c_noconv);
   }
   wave_count_eos(b.evt, e, c_backup, c_iters, c_noconv);
 }
@@ -612,13 +651,10 @@ __global__ void __launch_bounds__(128) k_eos(BatchDev b, Params prm, EosDev eos,
 
 // Spatial gradient of the energy density for the freeze-out surface
 // ("Freeze-out hypersurface construction"), n = 1 difference form like
-// d_k u^j: d_i e_a = (1/sigma*_a) sum_b (e_b - e_a) d_i W_ab.  One thread per
-// particle; runs only for diagnostic evaluations.
+// d_k u^j: d_i e_a = (1/sigma*_a) sum_b (e_b - e_a) d_i W_ab, at slot j.
 template <int D>
-__global__ void __launch_bounds__(128) k_fo_grad(BatchDev b, Params prm, const double* __restrict__ Y,
-                                                 int64_t nslots) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nslots) return;
+__device__ inline void fo_grad_particle(const BatchDev& b, const Params& prm, const double* __restrict__ Y,
+                                        int64_t j) {
   const int e = b.ev[j];
   if (e < 0) return;
   const EventDev& E = b.evt[e];
@@ -645,6 +681,27 @@ __global__ void __launch_bounds__(128) k_fo_grad(BatchDev b, Params prm, const d
   for (int q = 0; q < 3; ++q) b.gsum[(int64_t)(GS_DE1 + q) * cap + j] = q < D ? de[q] * isg : 0.0;
 }
 
+// every particle (diagnostic evaluations)
+template <int D>
+__global__ void __launch_bounds__(128) k_fo_grad(BatchDev b, Params prm, const double* __restrict__ Y,
+                                                 int64_t nslots) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nslots) fo_grad_particle<D>(b, prm, Y, j);
+}
+
+// the particles that crossed e_fo in this step (records [fo_ctr[1], fo_ctr[0]))
+template <int D>
+__global__ void __launch_bounds__(64) k_fo_grad_list(BatchDev b, Params prm, const double* __restrict__ Y) {
+  const uint32_t lo = b.fo_ctr[1], hi = b.fo_ctr[0] < (uint32_t)b.cap ? b.fo_ctr[0] : (uint32_t)b.cap;
+  for (uint32_t q = lo + blockIdx.x * blockDim.x + threadIdx.x; q < hi; q += gridDim.x * blockDim.x)
+    fo_grad_particle<D>(b, prm, Y, b.fo_slot[q]);
+}
+
+// records found before this step: the first stage's crossings are appended after them
+__global__ void k_fo_begin(BatchDev b) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) b.fo_ctr[1] = b.fo_ctr[0];
+}
+
 // Source densities I^mu, I_q at position x and time t: sum over the active
 // sources of the rates times the normalised Gaussian around the moving
 // centre, divided by sqrt(-g) (eq. conservation_source with the smeared
@@ -668,6 +725,46 @@ __device__ inline void source_density(const SourceSet& S, double t, double sqg, 
 #pragma unroll
     for (int q = 0; q < 3; ++q) Iq[q] += s.dndt[q] * g;
   }
+}
+
+// Freeze-out surface element at slot j ("Freeze-out hypersurface
+// construction", eq. fonormal): d_0 e from D e = -(e + p + Pi) theta +
+// pi:sigma + u.I with D = gamma d_0 + u^i d_i and the SPH gradient d_i e;
+// n_mu = -d_mu e / sqrt(|d e . d e|), d sigma_mu = n_mu / (sigma |u.n|) (m = 1).
+template <int D>
+__device__ inline void surface_element(const BatchDev& b, int64_t j, const EomIn& in, const EomOut& o,
+                                       const double Gk[4], double dmu[4], double dsl[4]) {
+  const int64_t cap = b.cap;
+  const double ee = b.th[(int64_t)T_E * cap + j], pp = b.th[(int64_t)T_P * cap + j];
+  const double gm[4] = {1.0, -1.0, -1.0, -Gk[3]};
+  const double giv[4] = {1.0, -1.0, -1.0, -1.0 / Gk[3]};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) dmu[m] = 0.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) dmu[1 + q] = b.gsum[(int64_t)(GS_DE1 + q) * cap + j];
+  double uI = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) uI += gm[m] * in.u[m] * in.I[m];
+  const double De = -(ee + pp + in.Pi) * o.theta + o.pisig + uI;
+  double adv = 0.0;
+#pragma unroll
+  for (int k = 1; k <= D; ++k) adv += in.u[k] * dmu[k];
+  dmu[0] = (De - adv) / in.u[0];
+  double nn = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) nn += giv[m] * dmu[m] * dmu[m];
+  const double norm = sqrt(fabs(nn));
+  double nl[4] = {0.0, 0.0, 0.0, 0.0}, un = 0.0;
+  if (norm > 0.0) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      nl[m] = -dmu[m] / norm;
+      un += in.u[m] * nl[m];
+    }
+  }
+  const double dsig = (norm > 0.0 && fabs(un) > 0.0) ? 1.0 / (in.sigma * fabs(un)) : 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) dsl[m] = dsig * nl[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -848,45 +945,25 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
       aux[X_REINV_SHEAR * n + ii] = res;
       aux[X_KN_BULK * n + ii] = knb;
       aux[X_REINV_BULK * n + ii] = reb;
-      // freeze-out surface element ("Freeze-out hypersurface construction"):
-      // d_0 e from D e = -(e + p + Pi) theta + pi:sigma + u.I, D = gamma d_0 + u^i d_i;
-      // n_mu = -d_mu e / sqrt(|d e . d e|), d sigma_mu = n_mu / (sigma |u.n|)
-      {
-        const double ee = T_[(int64_t)T_E * cap + j], pp = T_[(int64_t)T_P * cap + j];
-        const double gm[4] = {1.0, -1.0, -1.0, -Gk[3]};
-        const double giv[4] = {1.0, -1.0, -1.0, -1.0 / Gk[3]};
-        double dmu[4] = {0.0, 0.0, 0.0, 0.0};
+      double dmu[4], dsl[4];
+      surface_element<D>(b, j, in, o, Gk, dmu, dsl);
 #pragma unroll
-        for (int q = 0; q < D; ++q) dmu[1 + q] = b.gsum[(int64_t)(GS_DE1 + q) * cap + j];
-        double uI = 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) uI += gm[m] * in.u[m] * in.I[m];
-        const double De = -(ee + pp + in.Pi) * o.theta + o.pisig + uI;
-        double adv = 0.0;
-#pragma unroll
-        for (int k = 1; k <= D; ++k) adv += in.u[k] * dmu[k];
-        dmu[0] = (De - adv) / in.u[0];
-        double nn = 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) nn += giv[m] * dmu[m] * dmu[m];
-        const double norm = sqrt(fabs(nn));
-        double nl[4] = {0.0, 0.0, 0.0, 0.0}, un = 0.0;
-        if (norm > 0.0) {
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            nl[m] = -dmu[m] / norm;
-            un += in.u[m] * nl[m];
-          }
-        }
-        const double dsig = (norm > 0.0 && fabs(un) > 0.0) ? 1.0 / (in.sigma * fabs(un)) : 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          aux[(X_DE0 + m) * n + ii] = dmu[m];
-          aux[(X_DSIG0 + m) * n + ii] = dsig * nl[m];
-        }
+      for (int m = 0; m < 4; ++m) {
+        aux[(X_DE0 + m) * n + ii] = dmu[m];
+        aux[(X_DSIG0 + m) * n + ii] = dsl[m];
       }
     }
     return;
+  }
+  if (mode == 0 && prm.e_fo > 0.0) {
+    const int32_t at = b.fo_mark[j];
+    if (at >= 0) {
+      double dmu[4], dsl[4];
+      surface_element<D>(b, j, in, o, Gk, dmu, dsl);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) b.fo_rec[(int64_t)at * FO_NCOL + FO_DS0 + m] = dsl[m];
+      b.fo_mark[j] = -1;
+    }
   }
   const double dt = E.dt;
   bool finite = true;
@@ -988,10 +1065,13 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
     CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 4, false>), dim3(gt), dim3(256), b, prm, Y, none);
   else
     CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 1, false>), dim3(gt), dim3(256), b, prm, Y, none);
+  // the freeze-out surface is looked for at the step start of a step
+  const int fo = (mode == 0 && prm.e_fo > 0.0) ? 1 : 0;
+  if (fo) hipLaunchKernelGGL(k_fo_begin, dim3(1), dim3(64), 0, s, b);
   if (prm.ncharge)
-    CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 3>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux);
+    CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 3>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux, fo);
   else
-    CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 0>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux);
+    CCAKE_STAGE_LAUNCH(ee, (k_eos<D, VISC, MIXED, 0>), dim3(gp), dim3(128), b, prm, eos, Y, stage, nslots, aux, fo);
   if (!rates) return;
   // diffusion sums: 1 without, 2 with the bulk-pressure gradient
   if (prm.diffusion && (prm.d_JPi[0] != 0.0 || prm.d_JPi[1] != 0.0 || prm.d_JPi[2] != 0.0))
@@ -1002,6 +1082,10 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
     CCAKE_STAGE_LAUNCH(eg, (k_grad<D, VISC, MIXED, 0>), dim3(gt), dim3(256), b, prm, Y, stage);
   // diagnostic evaluations only (never profiled)
   if (aux) hipLaunchKernelGGL((k_fo_grad<D>), dim3(gp), dim3(128), 0, s, b, prm, Y, nslots);
+  if (fo) {
+    const unsigned gl = nblocks(nslots, 64) < 512 ? nblocks(nslots, 64) : 512;
+    hipLaunchKernelGGL((k_fo_grad_list<D>), dim3(gl), dim3(64), 0, s, b, prm, Y);
+  }
   CCAKE_STAGE_LAUNCH(em, (k_eom<D, VISC>), dim3(gp), dim3(128), b, prm, Y, stage, mode, nslots, fout, aux);
 }
 

@@ -125,6 +125,38 @@ def test_pairs_cached_bit_exact(B, O, name):
     sim.close()
 
 
+def test_pairs_single_cell_fallback(B, O):
+    """A dense cluster of 1,444 particles plus two far outliers: no cell grid
+    within the event's capacity covers the bounding box, so the grid falls
+    back to one cell around the whole event (flagged as a capacity error),
+    sorted by the wave-parallel rank sort for cells above the LDS size.  The
+    pairs of a fresh binning and those the density kernel accepts after two
+    steps (neighbour tiles over a single oversized row) must still equal the
+    brute-force pair set."""
+    xi = I.lattice((38, 38), 0.1, -1.85)
+    xi = np.concatenate([xi, np.array([[1e9, -1e9], [1e9, -1e9]])], axis=1)
+    n = xi.shape[1]
+    prm, oe, cfg, ge = make(O, B, dim=2, hyperbolic=False, h=0.15, eos="conformal")
+    prm_bf = O.params(dim=2, hyperbolic=False, h=0.15, use_cells=0)
+    dens = np.zeros((4, n))
+    dens[0] = 10.0
+    sim = B.Sim(cfg, ge, n)
+    with pytest.raises(B.CcakeError) as e:
+        sim.init_particles(1.0, xi, np.zeros_like(xi), 0, dens)
+    assert e.value.status == B.E_CAPACITY
+    y = sim.get_state()
+    ga, gb = sim.pairs()
+    oa, ob = O.pairs(prm_bf, y)
+    assert ga.size == oa.size and np.array_equal(ga, oa) and np.array_equal(gb, ob)
+    sim.set_state(1.0, y)
+    sim.step(0.005, 2)
+    y = sim.get_state()
+    ga, gb = sim.pairs(cached=True)
+    oa, ob = O.pairs(prm_bf, y)
+    assert ga.size == oa.size and np.array_equal(ga, oa) and np.array_equal(gb, ob)
+    sim.close()
+
+
 # ------------------------------------------------------------- rates -------
 def lumpy_small(side=48, rhoB=0.05, rhoQ=0.02, seed=1):
     return I.lumpy_2d_workload(n_side=side, seed=seed, n_hot=10, radius=1.0, rhoB=rhoB, rhoQ=rhoQ)
