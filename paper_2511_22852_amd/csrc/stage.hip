@@ -985,7 +985,8 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
     }
     finite = finite && isfinite(val);
   }
-  if (mode == 1) {
+  // (a step that keeps its binning already works on the home copies)
+  if (mode == 1 && b.warms != b.warm) {
     b.id[j] = b.ids[j];
 #pragma unroll
     for (int w = 0; w < NWARM; ++w) b.warm[(int64_t)w * cap + j] = b.warms[(int64_t)w * cap + j];
