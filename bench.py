@@ -426,7 +426,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-events", type=int, default=128, help="serving load: events (0 = skip)")
+    ap.add_argument("--serve-events", type=int, default=256, help="serving load: events (0 = skip)")
     ap.add_argument("--no-c1b", action="store_true",
                     help="skip the event with ten times smaller charge fractions (rhoB = 0.005 s, rhoQ = 0.002 s)")
     ap.add_argument("--serve-steps", type=int, default=1480,

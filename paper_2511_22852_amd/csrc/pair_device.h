@@ -26,6 +26,13 @@
 
 namespace ccake {
 
+// FP32 form: blocks of candidate passes summed plainly before each
+// compensated addition (KAHAN_BLOCK passes of U candidates per lane)
+#ifndef CCAKE_KAHAN_BLOCK
+#define CCAKE_KAHAN_BLOCK 4
+#endif
+constexpr int KAHAN_BLOCK = CCAKE_KAHAN_BLOCK;
+
 template <int L>
 __device__ __forceinline__ double team_sum(double v) {
 #pragma clang fp contract(off)
@@ -41,26 +48,47 @@ template <bool MIXED, int NS>
 struct DensAcc {
   double ss, sv[4];
   Kahan ks, kv[4];
-  int nnb;
+  float ps, pv[4];  // FP32 block sums not yet added with compensation
+  int nnb, nb;
 
   __device__ __forceinline__ void init() {
     ss = 0.0;
     ks = Kahan{0.f, 0.f};
+    ps = 0.f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       sv[q] = 0.0;
       kv[q] = Kahan{0.f, 0.f};
+      pv[q] = 0.f;
     }
     nnb = 0;
+    nb = 0;
+  }
+
+  // compensated addition of the pending block sums (FP32 form)
+  __device__ __forceinline__ void flush() {
+    if (MIXED) {
+      ks.add(ps);
+      ps = 0.f;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        kv[q].add(pv[q]);
+        pv[q] = 0.f;
+      }
+    }
+    nb = 0;
   }
 
   // U candidates at squared distances d2[u] with the neighbours' scalars
   // v[u] (S, N_B, N_S, N_Q; the first NS are used) in the precision of the
   // sums; those with ok[u] false (rejected or missing) enter with weight
-  // zero.  FP32: the U terms of each sum are added together first and the
-  // block total is added with compensation, so the error stays below
-  // (U + 1) u sum |terms| + O(n u^2) however many candidates there are
-  // (u = 2^-24).  FP64: plain fused multiply-adds.
+  // zero.  FP32: the terms of KAHAN_BLOCK consecutive calls (B = KAHAN_BLOCK
+  // * U terms) are summed plainly and each block total is added with
+  // compensation, so the error stays below (B + 1) u sum |terms| + O(n u^2)
+  // however many candidates there are (u = 2^-24).  The caller flushes the
+  // last partial block (flush) at the end of every chunk of its walk, so
+  // the lanes of a wave that are still walking flush on the same calls.
+  // FP64: plain fused multiply-adds.
   template <int U, class T>
   __device__ __forceinline__ void add_block(const bool (&ok)[U], const double (&d2)[U], double ih,
                                             const T (&v)[U][4]) {
@@ -74,17 +102,13 @@ struct DensAcc {
         const float w = spline_wf(fast_sqrtf((float)d2[u]) * (float)ih);
         W[u] = ok[u] ? w : 0.0f;
       }
-      float ws = W[0];
 #pragma unroll
-      for (int u = 1; u < U; ++u) ws += W[u];
-      ks.add(ws);
+      for (int u = 0; u < U; ++u) ps += W[u];
 #pragma unroll
-      for (int q = 0; q < NS; ++q) {
-        float ps = (float)v[0][q] * W[0];
+      for (int q = 0; q < NS; ++q)
 #pragma unroll
-        for (int u = 1; u < U; ++u) ps = fmaf((float)v[u][q], W[u], ps);
-        kv[q].add(ps);
-      }
+        for (int u = 0; u < U; ++u) pv[q] = fmaf((float)v[u][q], W[u], pv[q]);
+      if (++nb == KAHAN_BLOCK) flush();
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -114,29 +138,54 @@ struct GradAcc {
   RT aPP, aA[3][3], aU[3], aV[3];
   double F[3], du[3][3], dv;
   Kahan kF[3], kdu[3][3], kdv;
+  float pF[3], pdu[3][3], pdv;  // FP32 block sums not yet added with compensation
+  int nb;
 
   __device__ __forceinline__ void init() {
     dv = 0.0;
     kdv = Kahan{0.f, 0.f};
+    pdv = 0.f;
+    nb = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       F[k] = 0.0;
       kF[k] = Kahan{0.f, 0.f};
+      pF[k] = 0.f;
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
         du[k][n] = 0.0;
         kdu[k][n] = Kahan{0.f, 0.f};
+        pdu[k][n] = 0.f;
       }
     }
+  }
+
+  // compensated addition of the pending block sums (FP32 form)
+  __device__ __forceinline__ void flush() {
+    if (MIXED) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        kF[i].add(pF[i]);
+        pF[i] = 0.f;
+#pragma unroll
+        for (int n = 0; n < D; ++n) {
+          kdu[i][n].add(pdu[i][n]);
+          pdu[i][n] = 0.f;
+        }
+      }
+      kdv.add(pdv);
+      pdv = 0.f;
+    }
+    nb = 0;
   }
 
   // U candidates at positions xb[u] and squared distances d2[u] with their
   // records r[u] = (p+Pi)/sigma*^2, u^1..u^D, v^1..v^D, A^{ji}/sigma*^2
   // (j*D + i) in the precision of the sums; a candidate is a pair when
   // ok[u] (which must exclude the self pair, whose kernel gradient is zero),
-  // otherwise it enters with weight zero.  FP32: the U terms of each sum are
-  // added together before the compensated addition (error below
-  // (U + 1) u sum |terms| + O(n u^2), as for the density sums).
+  // otherwise it enters with weight zero.  FP32: blocks of KAHAN_BLOCK calls
+  // summed plainly before each compensated addition, flushed by the caller
+  // at the end of every chunk, as for the density sums.
   template <int U>
   __device__ __forceinline__ void add_block(const bool (&ok)[U], const double (&xb)[U][3], const double (&d2)[U],
                                             const RT (*r)[4 * ((1 + 2 * D + (VISC ? D * D : 0) + 3) / 4)]) {
@@ -167,26 +216,22 @@ struct GradAcc {
               vis = fmaf((float)aA[jj][i] + (float)r[u][1 + 2 * D + jj * D + i], dW[u][jj], vis);
             term = fmaf((float)Gk[i + 1], vis, term);
           }
-          acc = u == 0 ? term : acc + term;
+          pF[i] += term;
         }
-        kF[i].add(acc);
       }
       // velocity gradients and divergence (n = 1 differences)
 #pragma unroll
       for (int kk = 0; kk < D; ++kk)
 #pragma unroll
         for (int nu = 0; nu < D; ++nu) {
-          float acc = ((float)r[0][1 + nu] - (float)aU[nu]) * dW[0][kk];
 #pragma unroll
-          for (int u = 1; u < U; ++u) acc = fmaf((float)r[u][1 + nu] - (float)aU[nu], dW[u][kk], acc);
-          kdu[kk][nu].add(acc);
+          for (int u = 0; u < U; ++u) pdu[kk][nu] = fmaf((float)r[u][1 + nu] - (float)aU[nu], dW[u][kk], pdu[kk][nu]);
         }
-      float dvv = 0.f;
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int kk = 0; kk < D; ++kk) dvv = fmaf((float)r[u][1 + D + kk] - (float)aV[kk], dW[u][kk], dvv);
-      kdv.add(dvv);
+        for (int kk = 0; kk < D; ++kk) pdv = fmaf((float)r[u][1 + D + kk] - (float)aV[kk], dW[u][kk], pdv);
+      if (++nb == KAHAN_BLOCK) flush();
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u) {

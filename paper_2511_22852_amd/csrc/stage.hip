@@ -261,6 +261,7 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
       }
       if (!v[U - 1]) break;
     }
+    A.flush();
     __syncthreads();
   }
   // lanes v < 6 form row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
@@ -398,6 +399,7 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       }
       if (!v[U - 1]) break;
     }
+    A.flush();
     __syncthreads();
   }
   // lane v forms gradient sums v, v + L, ...: F_i, d_k u^j (row-major), div v
