@@ -257,7 +257,7 @@ def run_gpu(B, I, w, eos, precision, steps, warmup, diffusion=False):
     nnb_win = window_neighbours(B, w, sim, steps)
     sim.close()
     return dict(elapsed=elapsed, nnb=nnb, nnb_window=nnb_win, ms=ms, launches=launches, totals=tot.tolist(),
-                backup=cnt.backup, newton_iters=cnt.newton_iters)
+                backup=cnt.backup, newton_iters=cnt.newton_iters, newton_hist=list(cnt.newton_hist))
 
 
 def window_neighbours(B, w, sim, steps, samples=10):
@@ -526,9 +526,10 @@ def main():
         "kernel_ms_per_step": {"mixed": [m / args.steps for m in head["ms"]],
                                "fp64": [m / args.steps for m in res["fp64"]["ms"]],
                                "groups": GROUPS},
-        # counters of the last step: both Heun stages invert every particle once
-        "eos_backup_fraction_last_step": head["backup"] / (2 * w.n),
-        "eos_mean_newton_iterations_last_step": head["newton_iters"] / (2 * w.n),
+        # counters of one evaluation at the final state (every particle inverted once)
+        "eos_backup_fraction_final_state": head["backup"] / w.n,
+        "eos_mean_newton_iterations_final_state": head["newton_iters"] / w.n,
+        "eos_newton_iteration_histogram_final_state": head["newton_hist"],
         "roofline": roof,
         "roofline_by_kernel": roof_all,
     }
@@ -549,7 +550,7 @@ def main():
             "online_eos_inversion_ms_per_step": head["ms"][2] / args.steps,
             "table": f"s: 10^-2..10^3 fm^-3, {grid['per_decade']} per decade; n/s (B, S, Q): {grid['nx']} nodes",
             "build_seconds": build_s,
-            "eos_mean_newton_iterations_last_step": r["newton_iters"] / (2 * w.n),
+            "eos_mean_newton_iterations_final_state": r["newton_iters"] / w.n,
         }
         print(f"[bench] offline EoS: {out['offline_eos_mixed']['ms_per_step']:.4f} ms/step", file=sys.stderr,
               flush=True)
@@ -578,8 +579,8 @@ def main():
             r = run_gpu(B, I, w1b, eos, prec, args.steps, args.warmup)
             c1b[name] = {"value": w1b.n * args.steps / r["elapsed"], "ms_per_step": r["elapsed"] / args.steps * 1e3,
                          "kernel_ms_per_step": [m / args.steps for m in r["ms"]],
-                         "eos_backup_fraction_last_step": r["backup"] / (2 * w1b.n),
-                         "eos_mean_newton_iterations_last_step": r["newton_iters"] / (2 * w1b.n)}
+                         "eos_backup_fraction_final_state": r["backup"] / w1b.n,
+                         "eos_mean_newton_iterations_final_state": r["newton_iters"] / w1b.n}
             print(f"[bench] c1b {name}: {c1b[name]['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
         out["lumpy_2d_viscous_bsq_40k_low_charge"] = dict(
             workload="the headline event with rhoB = 0.005 s, rhoQ = 0.002 s", **c1b)

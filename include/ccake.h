@@ -143,7 +143,11 @@ typedef struct ccake_config {
   double d_JPi[3];
 } ccake_config;
 
-/* Per-event counters of the last evaluation (ccake_totals). */
+/* Per-event counters of the last evaluation (ccake_totals).  newton_hist[k]
+ * counts the particles whose EoS inversion took k Newton iterations (gas and
+ * table solves together), k = 0 .. CCAKE_NEWTON_BINS - 2; the last bin holds
+ * CCAKE_NEWTON_BINS - 1 iterations or more. */
+enum { CCAKE_NEWTON_BINS = 12 };
 typedef struct ccake_counters {
   uint32_t nonfinite;      /* sticky: non-finite particle updates */
   uint32_t noconv;         /* sticky: EoS inversions that failed */
@@ -151,6 +155,8 @@ typedef struct ccake_counters {
   uint32_t newton_iters;   /* last stage: total Newton iterations */
   int32_t first_bad;       /* lowest particle index with a non-finite update, or -1 */
   uint32_t capacity_err;   /* sticky: cell-grid capacity problems */
+  int64_t in_table;        /* particles whose inversion the table answered */
+  int64_t newton_hist[CCAKE_NEWTON_BINS];
 } ccake_counters;
 
 /* ---------------------------------------------------------------- EoS ---- */
@@ -323,11 +329,20 @@ ccake_status ccake_rhs(ccake_sim* sim, double* f, double* aux, int32_t mem);
 /* One diagnostic field (CCAKE_AUX_*) at the current state, caller order.     */
 ccake_status ccake_read(ccake_sim* sim, int32_t field, double* out, int32_t mem);
 
+/* Several diagnostic fields from one evaluation at the current state: bit k
+ * of mask selects CCAKE_AUX_k, whose n values (caller order) go to out[k]
+ * (host or device per mem; entries of unselected fields are not read).  The
+ * state rows themselves come from ccake_get_state.  CCAKE_E_ARG for a mask
+ * with bits at or beyond CCAKE_NAUX or a selected NULL output.  Synchronises. */
+ccake_status ccake_read_fields(ccake_sim* sim, uint64_t mask, double* const* out, int32_t mem);
+
 /* Totals at the current state: out[8] = (S, N_B, N_S, N_Q, E, M_1, M_2, M_3)
  * with E = sum sqrt(-g) T^00/sigma* and M_i = sum sqrt(-g) G_ii T^0i/sigma*;
  * with diffusion a particle's charge is N_q + sqrt(-g) J^0_q/sigma*
  * (conserved energy and momentum in Cartesian coordinates; "Exact
- * conservation").  cnt (optional) receives the counters.  Synchronises.     */
+ * conservation").  cnt (optional) receives the counters of that evaluation:
+ * the backup count, the in-table count and the histogram of Newton
+ * iterations per particle ("EoS inverter").  Synchronises.                  */
 ccake_status ccake_totals(ccake_sim* sim, double* out, ccake_counters* cnt);
 
 /* Test support: the neighbour relation {(a, b) : |x_a - x_b|^2 < (2h)^2}
@@ -406,9 +421,16 @@ typedef struct ccake_event_result {
   double totals[8];
 } ccake_event_result;
 
+/* Device bytes of a server's arena (every resident event's state, the cell
+ * grid and the event table) for max_particles and max_events.               */
+ccake_status ccake_server_workspace_bytes(const ccake_config* cfg, int64_t max_particles, int32_t max_events,
+                                          size_t* bytes);
+/* workspace: caller-owned device memory of at least ws_bytes >=
+ * ccake_server_workspace_bytes bytes (256-byte aligned), which must outlive
+ * the server; NULL lets the server allocate (and free) its arena itself.    */
 ccake_status ccake_server_create(ccake_server** out, const ccake_config* cfg, const ccake_eos* eos,
                                  size_t budget_bytes, int64_t max_particles, int32_t max_events, double dt,
-                                 void* stream);
+                                 void* stream, void* workspace, size_t ws_bytes);
 /* Copies the event's arrays and queues it; returns its ticket.  Rejects with
  * CCAKE_E_CAPACITY an event that can never fit the budget or capacity.      */
 ccake_status ccake_server_submit(ccake_server* srv, const ccake_event_desc* ev, int64_t* ticket);

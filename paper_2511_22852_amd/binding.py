@@ -43,9 +43,9 @@ EXPORTS = [
     "ccake_eos_offline_eval",
     "ccake_workspace_bytes", "ccake_create",
     "ccake_init_particles", "ccake_set_state", "ccake_get_state", "ccake_time", "ccake_step",
-    "ccake_check", "ccake_set_sources", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_totals", "ccake_debug_pairs",
+    "ccake_check", "ccake_set_sources", "ccake_set_profiling", "ccake_kernel_times", "ccake_rhs", "ccake_read", "ccake_read_fields", "ccake_totals", "ccake_debug_pairs",
     "ccake_debug_pairs_cached", "ccake_set_freezeout", "ccake_freezeout_records",
-    "ccake_destroy", "ccake_server_create", "ccake_server_submit", "ccake_server_poll",
+    "ccake_destroy", "ccake_server_workspace_bytes", "ccake_server_create", "ccake_server_submit", "ccake_server_poll",
     "ccake_server_drain", "ccake_server_release", "ccake_server_stats", "ccake_server_destroy",
     "ccake_last_error",
 ]
@@ -96,10 +96,14 @@ class Source(ctypes.Structure):
 MAX_SOURCES = 16
 
 
+NEWTON_BINS = 12
+
+
 class Counters(ctypes.Structure):
     _fields_ = [("nonfinite", ctypes.c_uint32), ("noconv", ctypes.c_uint32), ("backup", ctypes.c_uint32),
                 ("newton_iters", ctypes.c_uint32), ("first_bad", ctypes.c_int32),
-                ("capacity_err", ctypes.c_uint32)]
+                ("capacity_err", ctypes.c_uint32), ("in_table", ctypes.c_int64),
+                ("newton_hist", ctypes.c_int64 * NEWTON_BINS)]
 
 
 class EventDesc(ctypes.Structure):
@@ -153,6 +157,8 @@ def lib():
             "ccake_kernel_times": [vp, dp, ctypes.POINTER(i64)],
             "ccake_rhs": [vp, vp, vp, i32],
             "ccake_read": [vp, i32, vp, i32],
+            "ccake_read_fields": [vp, ctypes.c_uint64, ctypes.POINTER(vp), i32],
+            "ccake_server_workspace_bytes": [ctypes.POINTER(Config), i64, i32, ctypes.POINTER(ctypes.c_size_t)],
             "ccake_totals": [vp, dp, ctypes.POINTER(Counters)],
             "ccake_debug_pairs": [vp, i64, vp, vp, ctypes.POINTER(i64)],
             "ccake_debug_pairs_cached": [vp, i64, vp, vp, ctypes.POINTER(i64)],
@@ -160,7 +166,7 @@ def lib():
             "ccake_freezeout_records": [vp, i64, vp, ctypes.POINTER(i64), i32],
             "ccake_destroy": [vp],
             "ccake_server_create": [ctypes.POINTER(vp), ctypes.POINTER(Config), vp, ctypes.c_size_t, i64, i32,
-                                    dbl, vp],
+                                    dbl, vp, vp, ctypes.c_size_t],
             "ccake_server_submit": [vp, ctypes.POINTER(EventDesc), ctypes.POINTER(i64)],
             "ccake_server_poll": [vp, ctypes.POINTER(EventResult), i32, ctypes.POINTER(i32)],
             "ccake_server_drain": [vp],
@@ -389,6 +395,20 @@ class Sim:
         _check(lib().ccake_read(self.h, field, _ptr(out), HOST), self.h)
         return out
 
+    def read_fields(self, fields):
+        """Several diagnostic fields (AUX_*) from one evaluation
+        (ccake_read_fields): {field: array}."""
+        fields = sorted(set(int(f) for f in fields))
+        outs = {f: np.empty(self.n) for f in fields}
+        ptrs = (ctypes.c_void_p * NAUX)()
+        mask = 0
+        for f in fields:
+            if 0 <= f < NAUX:
+                ptrs[f] = outs[f].ctypes.data
+            mask |= 1 << f  # the library rejects fields it does not have
+        _check(lib().ccake_read_fields(self.h, mask, ptrs, HOST), self.h)
+        return outs
+
     def totals(self):
         out = np.empty(8)
         cnt = Counters()
@@ -446,14 +466,24 @@ class Server:
     when they reach their end time."""
 
     def __init__(self, cfg: Config, eos: Eos, budget_bytes: int, max_particles: int, max_events: int, dt: float,
-                 device="cuda:0"):
+                 device="cuda:0", own_arena=False):
+        """own_arena: let the server allocate its arena (no caller workspace)."""
         import torch
         self.cfg, self.eos, self.device = cfg, eos, torch.device(device)
         self.stream = torch.cuda.Stream(device=self.device)
+        # the arena is a torch tensor the server borrows
+        nb = ctypes.c_size_t()
+        _check(lib().ccake_server_workspace_bytes(ctypes.byref(cfg), int(max_particles), int(max_events),
+                                                  ctypes.byref(nb)), what="ccake_server_workspace_bytes")
+        self.ws, base = None, 0
+        if not own_arena:
+            self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+            base = (self.ws.data_ptr() + 255) & ~255
         h = ctypes.c_void_p()
         _check(lib().ccake_server_create(ctypes.byref(h), ctypes.byref(cfg), eos.h, int(budget_bytes),
                                          int(max_particles), int(max_events), dt,
-                                         ctypes.c_void_p(self.stream.cuda_stream)), what="ccake_server_create")
+                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.c_void_p(base),
+                                         nb.value), what="ccake_server_create")
         self.h = h
 
     def submit(self, t0, t_end, xi, u, dens_kind, dens, tag=0):

@@ -792,6 +792,23 @@ extern "C" ccake_status ccake_read(ccake_sim* s, int32_t field, double* out, int
   return stage_out(s, out, (double*)(s->base + s->L.aux) + (size_t)field * s->n, (size_t)s->n, mem);
 }
 
+extern "C" ccake_status ccake_read_fields(ccake_sim* s, uint64_t mask, double* const* out, int32_t mem) {
+  if (!s) return CCAKE_E_ARG;
+  if (!out || (mask >> CCAKE_NAUX) != 0 || (mem != CCAKE_HOST && mem != CCAKE_DEVICE))
+    return fail(s, CCAKE_E_ARG, "ccake_read_fields: bad arguments");
+  for (int k = 0; k < CCAKE_NAUX; ++k)
+    if (((mask >> k) & 1u) && !out[k]) return fail(s, CCAKE_E_ARG, "ccake_read_fields: field %d has no output", k);
+  ccake_status st = evaluate(s, true);
+  if (st) return st;
+  const double* aux = (const double*)(s->base + s->L.aux);
+  for (int k = 0; k < CCAKE_NAUX; ++k)
+    if ((mask >> k) & 1u) {
+      st = stage_out(s, out[k], aux + (size_t)k * s->n, (size_t)s->n, mem);
+      if (st) return st;
+    }
+  return CCAKE_OK;
+}
+
 extern "C" ccake_status ccake_totals(ccake_sim* s, double* out, ccake_counters* cnt) {
   if (!s) return CCAKE_E_ARG;
   if (!out) return fail(s, CCAKE_E_ARG, "ccake_totals: out is NULL");
@@ -810,6 +827,21 @@ extern "C" ccake_status ccake_totals(ccake_sim* s, double* out, ccake_counters* 
     cnt->newton_iters = E.newton_iters;
     cnt->first_bad = E.first_bad == INT32_MAX ? -1 : E.first_bad;
     cnt->capacity_err = E.capacity_err;
+    // per-particle iterations and table flags of this evaluation
+    std::vector<double> it((size_t)s->n), tab((size_t)s->n);
+    const double* aux = (const double*)(s->base + s->L.aux);
+    st = stage_out(s, it.data(), aux + (size_t)CCAKE_AUX_NEWTON * s->n, (size_t)s->n, CCAKE_HOST);
+    if (st) return st;
+    st = stage_out(s, tab.data(), aux + (size_t)CCAKE_AUX_INTABLE * s->n, (size_t)s->n, CCAKE_HOST);
+    if (st) return st;
+    cnt->in_table = 0;
+    for (int k = 0; k < CCAKE_NEWTON_BINS; ++k) cnt->newton_hist[k] = 0;
+    for (int64_t i = 0; i < s->n; ++i) {
+      const double v = it[(size_t)i];
+      const int bin = v >= CCAKE_NEWTON_BINS - 1 ? CCAKE_NEWTON_BINS - 1 : (v > 0.0 ? (int)v : 0);
+      cnt->newton_hist[bin] += 1;
+      cnt->in_table += tab[(size_t)i] != 0.0 ? 1 : 0;
+    }
   }
   return CCAKE_OK;
 }

@@ -17,6 +17,7 @@
 #include <climits>
 #include <cmath>
 #include <condition_variable>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -101,6 +102,7 @@ struct ccake_server : Handle {
   int max_events = 0;
   double dt = 0;
   char* arena = nullptr;
+  bool own_arena = false;  // allocated by the server (no caller workspace)
   Layout L;
   BatchDev b;
   double* h_stage = nullptr;  // pinned staging for uploads / downloads
@@ -326,11 +328,27 @@ static void worker_loop(ccake_server* s) {
   }
 }
 
+static int64_t server_cell_capacity(int64_t max_particles, int32_t max_events) {
+  return 4 * max_particles + (int64_t)max_events * 8200;
+}
+
+extern "C" ccake_status ccake_server_workspace_bytes(const ccake_config* cfg, int64_t max_particles,
+                                                     int32_t max_events, size_t* bytes) {
+  std::string why;
+  if (!bytes || !validate_config(cfg, &why) || max_particles <= 0 || max_events <= 0) return CCAKE_E_ARG;
+  *bytes = make_layout(max_particles, server_cell_capacity(max_particles, max_events), max_events).total;
+  return CCAKE_OK;
+}
+
 extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_config* cfg, const ccake_eos* eos,
                                             size_t budget_bytes, int64_t max_particles, int32_t max_events,
-                                            double dt, void* stream) {
+                                            double dt, void* stream, void* workspace, size_t ws_bytes) {
   std::string why;
   if (!out || !eos || !validate_config(cfg, &why) || max_particles <= 0 || max_events <= 0 || !(dt > 0.0))
+    return CCAKE_E_ARG;
+  if (workspace && (((uintptr_t)workspace & 255u) != 0 ||
+                    ws_bytes < make_layout(max_particles, server_cell_capacity(max_particles, max_events),
+                                           max_events).total))
     return CCAKE_E_ARG;
   if (eos->dev.kind == EOS_CONFORMAL && cfg->ncharge != 0) return CCAKE_E_ARG;
   if (eos->dev.inv.val && eos->dev.inv.ncharge != cfg->ncharge) return CCAKE_E_ARG;
@@ -343,7 +361,7 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
   s->dt = dt;
   s->max_particles = max_particles;
   s->max_events = max_events;
-  s->ccap = 4 * max_particles + (int64_t)max_events * 8200;
+  s->ccap = server_cell_capacity(max_particles, max_events);
   s->L = make_layout(max_particles, s->ccap, max_events);
   // bytes per resident particle of the arena (everything but the cells)
   s->per_particle_bytes = (s->L.cs) / (size_t)max_particles + 1;
@@ -358,7 +376,11 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
     }
     s->own_stream = true;
   }
-  if (hipMalloc((void**)&s->arena, s->L.total) != hipSuccess) {
+  if (workspace) {
+    s->arena = (char*)workspace;
+  } else if (hipMalloc((void**)&s->arena, s->L.total) == hipSuccess) {
+    s->own_arena = true;
+  } else {
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return CCAKE_E_NOMEM;
@@ -468,7 +490,7 @@ extern "C" ccake_status ccake_server_destroy(ccake_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipStreamSynchronize(s->stream);
   for (auto& r : s->done) delete[] r.state;
-  if (s->arena) (void)hipFree(s->arena);
+  if (s->arena && s->own_arena) (void)hipFree(s->arena);
   if (s->own_stream) (void)hipStreamDestroy(s->stream);
   delete s;
   return CCAKE_OK;

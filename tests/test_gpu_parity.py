@@ -460,6 +460,31 @@ def test_totals_parity(B, O):
     assert cnt.nonfinite == 0 and cnt.noconv == 0
 
 
+def test_read_fields_and_counters(B, O):
+    """ccake_read_fields returns what ccake_read returns field by field, and
+    the counters of ccake_totals aggregate the evaluation's per-particle
+    Newton iterations and table flags (the table flags equal the oracle's)."""
+    prm, oe, cfg, ge, y, t0 = prepared(B, O, "lumpy2d_visc_table_inside")
+    _, aux_o, _ = O.rhs(prm, oe, t0, y)
+    sim = sim_from_state(B, cfg, ge, y, t0)
+    want = [B.AUX_T, B.AUX_E, B.AUX_NEWTON, B.AUX_INTABLE, B.AUX_DSIG0, B.AUX_NNB]
+    f = sim.read_fields(want)
+    assert sorted(f) == sorted(want)
+    for k in want:
+        assert np.array_equal(f[k], sim.read(k)), k
+    _, cnt = sim.totals()
+    it = f[B.AUX_NEWTON].astype(np.int64)
+    hist = np.bincount(np.minimum(it, B.NEWTON_BINS - 1), minlength=B.NEWTON_BINS)
+    assert list(cnt.newton_hist) == hist.tolist()
+    assert sum(cnt.newton_hist) == sim.n
+    assert cnt.newton_iters == int(it.sum())
+    n_tab = int(f[B.AUX_INTABLE].sum())
+    assert cnt.in_table == n_tab == int(aux_o[O.A_INTABLE].sum())
+    assert cnt.backup == sim.n - n_tab
+    with pytest.raises(B.CcakeError):
+        sim.read_fields([B.NAUX])
+
+
 def test_determinism_and_checkpoint(B, O):
     prm, oe, cfg, ge, y, t0 = prepared(B, O, "lumpy2d_visc_table_backup")
     runs = []

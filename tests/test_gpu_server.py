@@ -84,6 +84,26 @@ def test_alone_equals_in_mix(B, eos, eos_offline, precision, inverter):
     srv.close()
 
 
+def test_server_arena_owner(B, eos):
+    """The server on a caller-owned arena (a torch tensor) and on its own
+    allocation gives the same results, bit for bit."""
+    cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=0.24, precision=1, **TR)
+    evs = events(3, seed=4)
+    out = []
+    for own in (False, True):
+        srv = B.Server(cfg, eos, budget_bytes=1 << 30, max_particles=20000, max_events=4, dt=0.005, own_arena=own)
+        assert (srv.ws is None) == own
+        for i, w in enumerate(evs):
+            srv.submit(w.t0, w.t0 + 12 * w.dt, w.xi, w.u, w.dens_kind, w.dens, tag=i)
+        srv.drain()
+        res = sorted(srv.poll(16), key=lambda r: r["tag"])
+        srv.close()
+        assert [r["status"] for r in res] == [0] * len(evs)
+        out.append([r["state"] for r in res])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_budget_limits_residency(B, eos):
     cfg = B.config(dim=2, hyperbolic=True, viscous=True, ncharge=3, h=0.24, precision=1, **TR)
     w = I.lumpy_2d_workload(n_side=30, seed=5, n_hot=4, radius=0.8)
