@@ -76,6 +76,10 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
   const double gam = in.u[0];
   const double* u = in.u;
   const double u3 = D == 3 ? u[3] : 0.0;
+  // shared reciprocals (one division each instead of one per quotient)
+  constexpr double THIRD = 1.0 / 3.0;
+  const double igam = 1.0 / gam, isig = 1.0 / in.sigma;
+  const double igs = igam * isig;
 
   Aff A[4];
   A[0] = aff(0.0);
@@ -84,7 +88,7 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
   A[3] = D == 3 ? Aff{0.0, 0.0, 0.0, 1.0} : aff(0.0);
 
   // dgamma/dx0 and theta
-  Aff dgam = (1.0 / gam) * ((G[1] * u[1]) * A[1] + (G[2] * u[2]) * A[2] + (G[3] * u3) * A[3] +
+  Aff dgam = igam * ((G[1] * u[1]) * A[1] + (G[2] * u[2]) * A[2] + (G[3] * u3) * A[3] +
                             0.5 * Gd[3] * u3 * u3);
   Aff theta = dgam + gam * (in.divv + dlng);
   Aff dudt[4] = {dgam, A[1], A[2], A[3]};
@@ -122,7 +126,7 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
     for (int n = m; n < 4; ++n) {
       const double Delta = (m == n ? gi[m] : 0.0) - uu[m] * uu[n];
       Aff val = 0.5 * (gi[m] * nab[m][n] + gi[n] * nab[n][m]) - 0.5 * (uu[m] * Du[n] + uu[n] * Du[m]) -
-                (Delta / 3.0) * theta;
+                (Delta * THIRD) * theta;
       sg[m][n] = val;
       sg[n][m] = val;
     }
@@ -142,13 +146,13 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
 
   // relaxation of pi^{ij}/sigma
   Aff dP[4][4];
-  const double igs = 1.0 / (gam * in.sigma);
   if (VISC) {
+    const double itp = 1.0 / in.taupi;
 #pragma unroll
     for (int i = 1; i < 4; ++i)
 #pragma unroll
       for (int j = i; j < 4; ++j) {
-        Aff val = (1.0 / in.taupi) * ((2.0 * in.eta) * sg[i][j] + (-in.pi[i][j])) +
+        Aff val = itp * ((2.0 * in.eta) * sg[i][j] + (-in.pi[i][j])) +
                   ((1.0 - prm.c_pipi) * in.pi[i][j]) * theta + (prm.c_piPi * Pi) * sg[i][j];
         if (prm.c_pisig != 0.0) {
           // pi_lambda^<i sigma^j>lambda: both factors are transverse, so the
@@ -161,7 +165,7 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
             Aji = Aji + (in.pi[j][l] * g[l]) * sg[l][i];
           }
           const double Delta = (i == j ? gi[i] : 0.0) - uu[i] * uu[j];
-          val = val + prm.c_pisig * (0.5 * (Aij + Aji) + (-Delta / 3.0) * pisig);
+          val = val + prm.c_pisig * (0.5 * (Aij + Aji) + (-Delta * THIRD) * pisig);
         }
 #pragma unroll
         for (int l = 0; l < 4; ++l) val = val - (uu[i] * in.pi[j][l] + uu[j] * in.pi[i][l]) * Dl[l];
@@ -176,24 +180,24 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
 
   // momentum balance rows
   const double wP = in.w + Pi;
-  Aff dwPs = (1.0 / (in.sigma * gam)) * (pisig + Dp + DPi + uI);
+  Aff dwPs = igs * (pisig + Dp + DPi + uI);
   Aff R[4];
 #pragma unroll
   for (int i = 1; i <= D; ++i) {
     const double Qi = G[i] * uu[i];
     Aff dQ = G[i] * A[i] + Gd[i] * uu[i];
-    Aff r = (wP / in.sigma) * dQ + Qi * dwPs + (sqrtg * in.F[i] - G[i] * in.I[i] * igs);
+    Aff r = (wP * isig) * dQ + Qi * dwPs + (sqrtg * in.F[i] - G[i] * in.I[i] * igs);
     if (VISC) {
       double sQP = 0.0;
       Aff dsQP = aff(0.0);
 #pragma unroll
       for (int j = 1; j < 4; ++j) {
-        const double Pji = in.pi[j][i] / in.sigma;
+        const double Pji = in.pi[j][i] * isig;
         sQP += G[j] * uu[j] * Pji;
         dsQP = dsQP + Pji * (G[j] * A[j] + Gd[j] * uu[j]) + (G[j] * uu[j]) * dP[j][i];
       }
-      const double ig2 = 1.0 / (gam * gam);
-      r = r + (Gd[i] * ig2 * sQP) + (-2.0 * G[i] * ig2 / gam * sQP) * dgam + (G[i] * ig2) * dsQP;
+      const double ig2 = igam * igam;
+      r = r + (Gd[i] * ig2 * sQP) + (-2.0 * G[i] * ig2 * igam * sQP) * dgam + (G[i] * ig2) * dsQP;
     }
     R[i] = r;
   }
@@ -204,8 +208,9 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
     const double m11 = R[1].c1, m12 = R[1].c2, m21 = R[2].c1, m22 = R[2].c2;
     const double det = m11 * m22 - m12 * m21;
     const double b1 = -R[1].c0, b2 = -R[2].c0;
-    a[1] = (b1 * m22 - m12 * b2) / det;
-    a[2] = (m11 * b2 - b1 * m21) / det;
+    const double id = 1.0 / det;
+    a[1] = (b1 * m22 - m12 * b2) * id;
+    a[2] = (m11 * b2 - b1 * m21) * id;
   } else {
     double M[3][3], b[3];
 #pragma unroll
@@ -251,14 +256,14 @@ __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out
     out.sigsig = ss;
     const double ps = at(pisig, a), th = out.theta;
     out.pisig = ps;
-    out.dS = (-Pi * th + ps + heat) / (gam * in.sigma * in.T);
+    out.dS = (-Pi * th + ps + heat) * igs / in.T;
     out.dB = (at(DPi, a) + Pi * th) * igs;
 #pragma unroll
     for (int i = 1; i < 4; ++i)
 #pragma unroll
       for (int j = 1; j < 4; ++j) out.dP[i][j] = at(dP[i][j], a);
   } else {
-    out.dS = heat / (gam * in.sigma * in.T);
+    out.dS = heat * igs / in.T;
     out.dB = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)

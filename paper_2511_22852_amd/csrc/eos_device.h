@@ -70,6 +70,18 @@ __device__ inline void gas_eval(double T, const double mu[3], double* p, double 
   }
 }
 
+// Reciprocal of a (finite, nonzero) by the hardware estimate refined with
+// two Newton-Raphson steps r <- r (2 - a r), to within a few ulp: for the
+// pivots of the Newton solves, where it replaces a correctly rounded
+// division (a long dependent chain) at no cost to the converged roots.
+__device__ __forceinline__ double fast_rcp(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Cell of x and its fractional position; node0 is the node index of the
 // lower corner.  The cell index is clamped so that extrapolation off the axes
 // uses the boundary cell.
@@ -77,7 +89,7 @@ __device__ __forceinline__ int64_t tab_locate(const EosDev& e, const double x[4]
   int64_t node = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const double u = (x[k] - e.lo[k]) / e.d[k];
+    const double u = (x[k] - e.lo[k]) * e.inv_d[k];
     int i = (int)floor(u);
     i = i < 0 ? 0 : (i > e.n[k] - 2 ? e.n[k] - 2 : i);
     f[k] = u - (double)i;
@@ -212,6 +224,7 @@ __device__ inline void inv_resid(const EosDev& e, bool use_table, int mode, cons
 // system stays in registers.
 template <int NU>
 __device__ inline bool lsolve(double A[4][4], double b[4], double x[4]) {
+  double ipv[4];  // reciprocal pivots
 #pragma unroll
   for (int col = 0; col < NU; ++col) {
     int piv = col;
@@ -238,10 +251,10 @@ __device__ inline bool lsolve(double A[4][4], double b[4], double x[4]) {
       b[col] = sw ? c : a;
       b[r] = sw ? a : c;
     }
-    const double ip = 1.0 / A[col][col];
+    ipv[col] = fast_rcp(A[col][col]);
 #pragma unroll
     for (int r = col + 1; r < NU; ++r) {
-      const double fct = A[r][col] * ip;
+      const double fct = A[r][col] * ipv[col];
 #pragma unroll
       for (int j = col; j < NU; ++j) A[r][j] -= fct * A[col][j];
       b[r] -= fct * b[col];
@@ -252,7 +265,7 @@ __device__ inline bool lsolve(double A[4][4], double b[4], double x[4]) {
     double acc = b[i];
 #pragma unroll
     for (int j = i + 1; j < NU; ++j) acc -= A[i][j] * x[j];
-    x[i] = acc / A[i][i];
+    x[i] = acc * ipv[i];
   }
   return true;
 }

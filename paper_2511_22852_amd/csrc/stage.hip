@@ -490,12 +490,14 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
   const double gam = sqrt(1.0 + u[1] * u[1] + u[2] * u[2] + G3 * u[3] * u[3]);
   u[0] = gam;
   const double norm = gam * sqrt_g(prm, t);
-  const double sigma = ss / norm;
+  // shared reciprocals (one division each instead of one per quotient)
+  const double inorm = 1.0 / norm, igam = 1.0 / gam;
+  const double sigma = ss * inorm;
   double dens[4] = {0.0, 0.0, 0.0, 0.0};
   if (smoothed) {
-    dens[0] = b.dsum[(int64_t)DS_S * cap + j] / norm;
+    dens[0] = b.dsum[(int64_t)DS_S * cap + j] * inorm;
     if (NQ)
-      for (int q = 0; q < 3; ++q) dens[1 + q] = b.dsum[(int64_t)(DS_NB + q) * cap + j] / norm;
+      for (int q = 0; q < 3; ++q) dens[1 + q] = b.dsum[(int64_t)(DS_NB + q) * cap + j] * inorm;
   } else {
     dens[0] = row(Y, cap, R_S, j) * sigma;
     if (NQ)
@@ -550,7 +552,7 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
       double acc = 0.0;
 #pragma unroll
       for (int k = 1; k < 4; ++k) acc += Gq[k] * u[k] * pi[k][i];
-      pi[0][i] = pi[i][0] = acc / gam;
+      pi[0][i] = pi[i][0] = acc * igam;
     }
   }
 
@@ -581,11 +583,11 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
   for (int jj = 1; jj < 4; ++jj)
 #pragma unroll
     for (int ii = 1; ii < 4; ++ii)
-      rec[Q_A11 + (jj - 1) * 3 + (ii - 1)] = (pi[jj][ii] - (u[jj] / gam) * pi[0][ii]) * is2;
+      rec[Q_A11 + (jj - 1) * 3 + (ii - 1)] = (pi[jj][ii] - (u[jj] * igam) * pi[0][ii]) * is2;
 #pragma unroll
   for (int k = 1; k < 4; ++k) {
     rec[Q_U1 + k - 1] = u[k];
-    rec[Q_V1 + k - 1] = u[k] / gam;
+    rec[Q_V1 + k - 1] = u[k] * igam;
   }
 #pragma unroll
   for (int r = 0; r < NREC; ++r) {
@@ -601,6 +603,7 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
   // F^k_q / sigma*^2 with F = J - v J^0, J^k = sigma V^k, J^0 = G_k u^k J^k / gamma
   if (NQ && prm.diffusion) {
     const double Gq[4] = {0.0, 1.0, 1.0, G3};
+    const double iT = 1.0 / th.T;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       double J[3], J0 = 0.0;
@@ -609,12 +612,12 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
         J[k] = k < D ? sigma * row(Y, cap, R_JB1 + 3 * q + k, j) : 0.0;
         J0 += Gq[1 + k] * u[1 + k] * J[k];
       }
-      J0 /= gam;
-      b.drec[(int64_t)(QD_AB + q) * cap + j] = th.mu[q] / th.T;
+      J0 *= igam;
+      b.drec[(int64_t)(QD_AB + q) * cap + j] = th.mu[q] * iT;
       if (q == 0) b.drec[(int64_t)QD_PI * cap + j] = Pi;
 #pragma unroll
       for (int k = 0; k < D; ++k)
-        b.drec[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] = (J[k] - (u[1 + k] / gam) * J0) * is2;
+        b.drec[(int64_t)(QD_FB1 + 3 * q + k) * cap + j] = (J[k] - (u[1 + k] * igam) * J0) * is2;
     }
   }
   if (aux) {
@@ -793,9 +796,10 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
 #pragma unroll
   for (int k = 1; k < 4; ++k) in.u[k] = k <= D ? row(Y, cap, R_U1 + k - 1, j) : 0.0;
   const double gam = sqrt(1.0 + in.u[1] * in.u[1] + in.u[2] * in.u[2] + G3 * in.u[3] * in.u[3]);
+  const double igam = 1.0 / gam;
   in.u[0] = gam;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) in.v[k] = in.u[k] / gam;
+  for (int k = 0; k < 4; ++k) in.v[k] = in.u[k] * igam;
 #pragma unroll
   for (int n = 0; n < 4; ++n) in.dudx[0][n] = 0.0;
 #pragma unroll
@@ -807,7 +811,7 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
       in.dudx[k][n] = v;
       acc += Gk[n] * in.u[n] * v;
     }
-    in.dudx[k][0] = acc / gam;
+    in.dudx[k][0] = acc * igam;
   }
   in.divv = b.gsum[(int64_t)GS_DIVV * cap + j];
   in.F[0] = 0.0;
@@ -844,12 +848,12 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
       double acc = 0.0;
 #pragma unroll
       for (int k = 1; k < 4; ++k) acc += Gk[k] * in.u[k] * in.pi[k][i];
-      in.pi[0][i] = in.pi[i][0] = acc / gam;
+      in.pi[0][i] = in.pi[i][0] = acc * igam;
     }
     double acc = 0.0;
 #pragma unroll
     for (int i = 1; i < 4; ++i) acc += Gk[i] * in.u[i] * in.pi[0][i];
-    in.pi[0][0] = acc / gam;
+    in.pi[0][0] = acc * igam;
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) in.I[k] = 0.0;
