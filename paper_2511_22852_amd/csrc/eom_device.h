@@ -28,17 +28,32 @@
 
 namespace ccake {
 
-struct Aff {
+// An affine function of the acceleration; in 2+1D the a_3 coefficient is a
+// compile-time zero (no storage traffic, no arithmetic).
+template <int D>
+struct AffT {
   double c0, c1, c2, c3;  // value = c0 + c1 a_1 + c2 a_2 + c3 a_3
 };
-
-__device__ __forceinline__ Aff aff(double v) { return Aff{v, 0.0, 0.0, 0.0}; }
-__device__ __forceinline__ Aff operator+(Aff x, Aff y) { return Aff{x.c0 + y.c0, x.c1 + y.c1, x.c2 + y.c2, x.c3 + y.c3}; }
-__device__ __forceinline__ Aff operator-(Aff x, Aff y) { return Aff{x.c0 - y.c0, x.c1 - y.c1, x.c2 - y.c2, x.c3 - y.c3}; }
-__device__ __forceinline__ Aff operator*(double s, Aff x) { return Aff{s * x.c0, s * x.c1, s * x.c2, s * x.c3}; }
-__device__ __forceinline__ Aff operator+(Aff x, double v) { return Aff{x.c0 + v, x.c1, x.c2, x.c3}; }
-__device__ __forceinline__ double at(Aff x, const double a[4]) { return x.c0 + x.c1 * a[1] + x.c2 * a[2] + x.c3 * a[3]; }
-__device__ __forceinline__ double coef(Aff x, int j) { return j == 1 ? x.c1 : (j == 2 ? x.c2 : x.c3); }
+template <int D>
+__device__ __forceinline__ AffT<D> operator+(AffT<D> x, AffT<D> y) {
+  return AffT<D>{x.c0 + y.c0, x.c1 + y.c1, x.c2 + y.c2, D == 3 ? x.c3 + y.c3 : 0.0};
+}
+template <int D>
+__device__ __forceinline__ AffT<D> operator-(AffT<D> x, AffT<D> y) {
+  return AffT<D>{x.c0 - y.c0, x.c1 - y.c1, x.c2 - y.c2, D == 3 ? x.c3 - y.c3 : 0.0};
+}
+template <int D>
+__device__ __forceinline__ AffT<D> operator*(double s, AffT<D> x) {
+  return AffT<D>{s * x.c0, s * x.c1, s * x.c2, D == 3 ? s * x.c3 : 0.0};
+}
+template <int D>
+__device__ __forceinline__ AffT<D> operator+(AffT<D> x, double v) {
+  return AffT<D>{x.c0 + v, x.c1, x.c2, D == 3 ? x.c3 : 0.0};
+}
+template <int D>
+__device__ __forceinline__ double at(AffT<D> x, const double a[4]) {
+  return D == 3 ? x.c0 + x.c1 * a[1] + x.c2 * a[2] + x.c3 * a[3] : x.c0 + x.c1 * a[1] + x.c2 * a[2];
+}
 
 struct EomIn {
   double t;
@@ -63,6 +78,8 @@ struct EomOut {
 
 template <int D, bool VISC>
 __device__ inline void eom_solve(const Params& prm, const EomIn& in, EomOut& out) {
+  using Aff = AffT<D>;
+  auto aff = [](double v) { return Aff{v, 0.0, 0.0, 0.0}; };
   const bool hyp = prm.hyperbolic != 0;
   const double t = in.t;
   const double G[4] = {0.0, 1.0, 1.0, hyp ? t * t : 1.0};

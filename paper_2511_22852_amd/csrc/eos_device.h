@@ -85,8 +85,8 @@ __device__ __forceinline__ double fast_rcp(double a) {
 // Cell of x and its fractional position; node0 is the node index of the
 // lower corner.  The cell index is clamped so that extrapolation off the axes
 // uses the boundary cell.
-__device__ __forceinline__ int64_t tab_locate(const EosDev& e, const double x[4], double f[4]) {
-  int64_t node = 0;
+__device__ __forceinline__ int32_t tab_locate(const EosDev& e, const double x[4], double f[4]) {
+  int32_t node = 0;  // the table holds fewer than 2^31 nodes
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double u = (x[k] - e.lo[k]) * e.inv_d[k];
@@ -107,14 +107,15 @@ __device__ __forceinline__ int64_t tab_locate(const EosDev& e, const double x[4]
 template <int C0, int NC, bool GRAD>
 __device__ inline void tab_interp(const EosDev& e, const double x[4], double v[NC], double g[NC][4]) {
   double f[4];
-  const int64_t node0 = tab_locate(e, x, f);
-  const int64_t s2 = e.n[3], s1 = (int64_t)e.n[2] * s2, s0 = (int64_t)e.n[1] * s1;
+  const int32_t node0 = tab_locate(e, x, f);
+  // corner offsets of axes 0..2 (the same for every lane)
+  const int32_t s2 = e.n[3], s1 = e.n[2] * s2, s0 = e.n[1] * s1;
   // axis 3: lerp the pairs (b3 = 0, 1), which are adjacent nodes
   double a[8][NC], a3[8][NC];
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const int64_t node = node0 + ((m >> 2) & 1) * s0 + ((m >> 1) & 1) * s1 + (m & 1) * s2;
-    const double* p0 = e.tab + node * TC_STRIDE + C0;
+    const int32_t node = node0 + ((m & 4) ? s0 : 0) + ((m & 2) ? s1 : 0) + ((m & 1) ? s2 : 0);
+    const double* p0 = e.tab + (uint64_t)(uint32_t)node * TC_STRIDE + C0;
     const double* p1 = p0 + TC_STRIDE;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {

@@ -240,6 +240,8 @@ extern "C" ccake_status ccake_eos_create_table(ccake_eos** out, const int32_t n[
   for (int k = 0; k < 4; ++k)
     if (n[k] < 2 || !(hi[k] > lo[k]) || !std::isfinite(lo[k]) || !std::isfinite(hi[k])) return CCAKE_E_ARG;
   if (!(lo[0] > 0.0)) return CCAKE_E_ARG;
+  // node indices are 32-bit on the device
+  if ((int64_t)n[0] * n[1] * n[2] * n[3] > (int64_t)INT32_MAX) return CCAKE_E_ARG;
   ccake_status st = eos_alloc(out);
   if (st) return st;
   ccake_eos* e = *out;
