@@ -112,7 +112,8 @@ struct DensAcc {
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double w = spline_w(sqrt(d2[u]) * ih);
+        const double r = d2[u] > 0.0 ? d2[u] * rsqrt_nr(d2[u]) : 0.0;
+        const double w = spline_w(r * ih);
         const double W = ok[u] ? w : 0.0;
         ss += W;
 #pragma unroll
@@ -235,8 +236,8 @@ struct GradAcc {
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double rr = sqrt(d2[u]);
-        double f = spline_dw(rr * ih) / rr;
+        const double ir = rsqrt_nr(d2[u]);
+        double f = spline_dw(d2[u] * ir * ih) * ir;
         f = ok[u] ? f : 0.0;
         double dW[3];
 #pragma unroll
@@ -318,8 +319,8 @@ struct DiffAcc {
   __device__ __forceinline__ void add(const double xa[3], const double xb[3], double d2, double ih, const double ab[3],
                                       const double Fb[3][3], double Pb) {
     if (!(d2 > 0.0)) return;  // self pair: grad W = 0
-    const double r = sqrt(d2);
-    const double f = spline_dw(r * ih) / r;
+    const double ir = rsqrt_nr(d2);
+    const double f = spline_dw(d2 * ir * ih) * ir;
     double dW[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) dW[k] = k < D ? f * (xa[k] - xb[k]) : 0.0;

@@ -56,10 +56,22 @@ __device__ __forceinline__ float spline_dwf(float q) {
 }
 
 // Hardware square root and reciprocal square root (about 1 ulp; the FP32
-// pair sums carry their own compensated error budget, the FP64 path keeps
-// correctly rounded operations)
+// pair sums carry their own compensated error budget)
 __device__ __forceinline__ float fast_sqrtf(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rsqf(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// FP64 reciprocal square root of x > 0: the hardware estimate refined by two
+// Newton-Raphson steps y <- y (3 - x y^2) / 2 (each doubles the correct
+// bits), to within a few ulp; the FP64 pair sums use r = x y and 1/r = y in
+// place of a correctly rounded square root and division (per-term
+// differences of a few ulp, far below the parity tolerance of the sums).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x * y;
+  y = fma(y, fma(-h, y, 0.5), y);
+  h = 0.5 * x * y;
+  return fma(y, fma(-h, y, 0.5), y);
+}
 
 // Compensated (Kahan) FP32 accumulator; value = s - c.
 struct Kahan {
