@@ -487,11 +487,12 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
 
   const double G3 = metric_G3(prm, t);
   double u[4] = {0.0, row(Y, cap, R_U1, j), row(Y, cap, R_U2, j), D == 3 ? row(Y, cap, R_U3, j) : 0.0};
-  const double gam = sqrt(1.0 + u[1] * u[1] + u[2] * u[2] + G3 * u[3] * u[3]);
+  const double g2 = 1.0 + u[1] * u[1] + u[2] * u[2] + G3 * u[3] * u[3];
+  const double igam = rsqrt_nr(g2), gam = g2 * igam;
   u[0] = gam;
   const double norm = gam * sqrt_g(prm, t);
   // shared reciprocals (one division each instead of one per quotient)
-  const double inorm = 1.0 / norm, igam = 1.0 / gam;
+  const double inorm = 1.0 / norm;
   const double sigma = ss * inorm;
   double dens[4] = {0.0, 0.0, 0.0, 0.0};
   if (smoothed) {
@@ -795,8 +796,8 @@ __global__ void __launch_bounds__(128) k_eom(BatchDev b, Params prm, const doubl
   in.u[0] = 0.0;
 #pragma unroll
   for (int k = 1; k < 4; ++k) in.u[k] = k <= D ? row(Y, cap, R_U1 + k - 1, j) : 0.0;
-  const double gam = sqrt(1.0 + in.u[1] * in.u[1] + in.u[2] * in.u[2] + G3 * in.u[3] * in.u[3]);
-  const double igam = 1.0 / gam;
+  const double g2 = 1.0 + in.u[1] * in.u[1] + in.u[2] * in.u[2] + G3 * in.u[3] * in.u[3];
+  const double igam = rsqrt_nr(g2), gam = g2 * igam;
   in.u[0] = gam;
 #pragma unroll
   for (int k = 0; k < 4; ++k) in.v[k] = in.u[k] * igam;
