@@ -480,13 +480,30 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
                                              const double* __restrict__ Y, int stage, int64_t j, int e, double* aux,
                                              bool fo, uint32_t& c_backup, uint32_t& c_iters, uint32_t& c_noconv) {
   const EventDev& E = b.evt[e];
-  const double t = E.t + stage * E.dt;
   const int64_t cap = b.cap;
   const bool smoothed = prm.density_mode == 0;
+  // every input of the particle, loaded together (one memory round trip
+  // instead of a chain): sums, flow, densities (smoothed sums or the
+  // particle's own S, N), dissipative state, warm start
   const double ss = b.dsum[(int64_t)DS_SIG * cap + j];
+  double u[4] = {0.0, row(Y, cap, R_U1, j), row(Y, cap, R_U2, j), D == 3 ? row(Y, cap, R_U3, j) : 0.0};
+  const double* dsrc = smoothed ? b.dsum + (int64_t)DS_S * cap : Y + (int64_t)R_S * cap;
+  static_assert(DS_NB == DS_S + 1 && R_NB == R_S + 1, "S and N rows consecutive");
+  double dv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dv[q] = (q == 0 || NQ) ? dsrc[(int64_t)q * cap + j] : 0.0;
+  double yv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (VISC) {
+    const int rv[7] = {R_B, R_P11, R_P12, R_P22, R_P33, R_P13, R_P23};
+#pragma unroll
+    for (int k = 0; k < (D == 3 ? 7 : 5); ++k) yv[k] = row(Y, cap, rv[k], j);
+  }
+  double warm[NWARM_EOS];
+#pragma unroll
+  for (int w = 0; w < NWARM_EOS; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
+  const double t = E.t + stage * E.dt;
 
   const double G3 = metric_G3(prm, t);
-  double u[4] = {0.0, row(Y, cap, R_U1, j), row(Y, cap, R_U2, j), D == 3 ? row(Y, cap, R_U3, j) : 0.0};
   const double g2 = 1.0 + u[1] * u[1] + u[2] * u[2] + G3 * u[3] * u[3];
   const double igam = rsqrt_nr(g2), gam = g2 * igam;
   u[0] = gam;
@@ -494,25 +511,17 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
   // shared reciprocals (one division each instead of one per quotient)
   const double inorm = 1.0 / norm;
   const double sigma = ss * inorm;
-  double dens[4] = {0.0, 0.0, 0.0, 0.0};
-  if (smoothed) {
-    dens[0] = b.dsum[(int64_t)DS_S * cap + j] * inorm;
-    if (NQ)
-      for (int q = 0; q < 3; ++q) dens[1 + q] = b.dsum[(int64_t)(DS_NB + q) * cap + j] * inorm;
-  } else {
-    dens[0] = row(Y, cap, R_S, j) * sigma;
-    if (NQ)
-      for (int q = 0; q < 3; ++q) dens[1 + q] = row(Y, cap, R_NB + q, j) * sigma;
-  }
+  double dens[4];
+  const double dscale = smoothed ? inorm : sigma;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dens[q] = dv[q] * dscale;
 
   // EoS inversion (s, n) -> (T, mu): the offline table when the EoS carries
   // one and (s, n) is on its grid, else online, warm-started from the
   // particle's last roots
   Thermo th;
   if (!(eos.inv.val && inv_lookup<NQ>(eos.inv, dens, th))) {
-    double warm[NWARM_EOS], wnew[NWARM_EOS];
-#pragma unroll
-    for (int w = 0; w < NWARM_EOS; ++w) warm[w] = b.warms[(int64_t)w * cap + j];
+    double wnew[NWARM_EOS];
     eos_invert<NQ>(eos, 0, dens, warm, th, wnew);
 #pragma unroll
     for (int w = 0; w < NWARM_EOS; ++w) b.warms[(int64_t)w * cap + j] = wnew[w];
@@ -538,14 +547,14 @@ __device__ __forceinline__ void eos_particle(const BatchDev& b, const Params& pr
 #pragma unroll
     for (int n = 0; n < 4; ++n) pi[m][n] = 0.0;
   if (VISC) {
-    Pi = sigma * row(Y, cap, R_B, j);
-    pi[1][1] = sigma * row(Y, cap, R_P11, j);
-    pi[1][2] = pi[2][1] = sigma * row(Y, cap, R_P12, j);
-    pi[2][2] = sigma * row(Y, cap, R_P22, j);
-    pi[3][3] = sigma * row(Y, cap, R_P33, j);
+    Pi = sigma * yv[0];
+    pi[1][1] = sigma * yv[1];
+    pi[1][2] = pi[2][1] = sigma * yv[2];
+    pi[2][2] = sigma * yv[3];
+    pi[3][3] = sigma * yv[4];
     if (D == 3) {
-      pi[1][3] = pi[3][1] = sigma * row(Y, cap, R_P13, j);
-      pi[2][3] = pi[3][2] = sigma * row(Y, cap, R_P23, j);
+      pi[1][3] = pi[3][1] = sigma * yv[5];
+      pi[2][3] = pi[3][2] = sigma * yv[6];
     }
     const double Gq[4] = {0.0, 1.0, 1.0, G3};
 #pragma unroll
