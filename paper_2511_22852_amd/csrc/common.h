@@ -123,6 +123,18 @@ struct SourceSet {
 #ifndef CCAKE_SUBCELLS3
 #define CCAKE_SUBCELLS3 2
 #endif
+// Entries per target of the accepted-pair lists (2D, 3D; 0: no lists):
+// about six times the mean neighbour count of the 3D benchmark events; a
+// target with more pairs falls back to the candidate walk in the gradient
+// pass.  In 2D the candidate walk accepts most of what it reads and writing
+// the lists costs the density pass more than the gradient pass saves.
+#ifndef CCAKE_LIST_CAP2
+#define CCAKE_LIST_CAP2 0
+#endif
+#ifndef CCAKE_LIST_CAP3
+#define CCAKE_LIST_CAP3 4096
+#endif
+__host__ __device__ constexpr int list_cap(int dim) { return dim == 3 ? CCAKE_LIST_CAP3 : CCAKE_LIST_CAP2; }
 __host__ __device__ constexpr int subcells(int dim) { return dim == 3 ? CCAKE_SUBCELLS3 : CCAKE_SUBCELLS2; }
 __host__ __device__ constexpr int row_count(int dim) {
   return dim == 3 ? (2 * subcells(3) + 1) * (2 * subcells(3) + 1) : 2 * subcells(2) + 1;
@@ -223,6 +235,9 @@ struct BatchDev {
   int32_t* fo_slot;  // [cap] sorted slot of each record's particle (step of its crossing)
   int32_t* fo_mark;  // [cap] per sorted slot: record found in this step's first stage, or -1
   uint32_t* fo_ctr;  // [2] records so far, records before this step
+  uint16_t* plist;   // [cap][list_cap] accepted candidates of each target (halo indices, walk order)
+  int32_t* pcnt;     // [cap] their number, or -1 when they do not fit (the gradient pass walks)
+  int32_t list_cap;  // entries per target
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

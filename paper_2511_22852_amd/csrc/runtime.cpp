@@ -118,7 +118,7 @@ static size_t take(size_t* o, size_t bytes) {
   return at;
 }
 
-Layout make_layout(int64_t cap, int64_t ccap, int nev) {
+Layout make_layout(int64_t cap, int64_t ccap, int nev, int dim) {
   Layout L;
   size_t o = 0;
   const size_t D8 = sizeof(double), I4 = sizeof(int32_t);
@@ -146,6 +146,8 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   L.fo_slot = take(&o, I4 * cap);
   L.fo_mark = take(&o, I4 * cap);
   L.fo_ctr = take(&o, I4 * 2);
+  L.plist = take(&o, sizeof(uint16_t) * (size_t)list_cap(dim) * cap);
+  L.pcnt = take(&o, I4 * cap);
   L.cs = take(&o, I4 * (ccap + 1));
   L.cf = take(&o, I4 * (ccap + 1));
   L.evt = take(&o, sizeof(EventDev) * nev);
@@ -155,7 +157,7 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev) {
   return L;
 }
 
-BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int nev) {
+BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int nev, int dim) {
   BatchDev b;
   b.Y0 = (double*)(base + L.Y0);
   b.Ys = (double*)(base + L.Ys);
@@ -180,6 +182,9 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.fo_slot = (int32_t*)(base + L.fo_slot);
   b.fo_mark = (int32_t*)(base + L.fo_mark);
   b.fo_ctr = (uint32_t*)(base + L.fo_ctr);
+  b.plist = (uint16_t*)(base + L.plist);
+  b.pcnt = (int32_t*)(base + L.pcnt);
+  b.list_cap = list_cap(dim);
   b.cell_start = (int32_t*)(base + L.cs);
   b.cell_fill = (int32_t*)(base + L.cf);
   b.evt = (EventDev*)(base + L.evt);
@@ -375,7 +380,7 @@ extern "C" ccake_status ccake_workspace_bytes(const ccake_config* cfg, int64_t n
   std::string why;
   if (!bytes || n <= 0 || !validate_config(cfg, &why)) return CCAKE_E_ARG;
   if (n > INT32_MAX / 2) return CCAKE_E_CAPACITY;
-  *bytes = make_layout(n, cell_capacity(*cfg, n), 1).total;
+  *bytes = make_layout(n, cell_capacity(*cfg, n), 1, cfg->dim).total;
   return CCAKE_OK;
 }
 
@@ -388,7 +393,7 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
   if (eos->dev.kind == EOS_CONFORMAL && cfg->ncharge != 0) return CCAKE_E_ARG;
   if (eos->dev.inv.val && eos->dev.inv.ncharge != cfg->ncharge) return CCAKE_E_ARG;
   const int64_t ccap = cell_capacity(*cfg, n);
-  Layout L = make_layout(n, ccap, 1);
+  Layout L = make_layout(n, ccap, 1, cfg->dim);
   if (bytes < L.total) return CCAKE_E_CAPACITY;
   ccake_sim* s = new ccake_sim();
   s->magic = HANDLE_SIM;
@@ -399,7 +404,7 @@ extern "C" ccake_status ccake_create(ccake_sim** out, const ccake_config* cfg, c
   s->ccap = ccap;
   s->L = L;
   s->base = (char*)workspace;
-  s->b = bind_batch(s->base, L, n, ccap, 1);
+  s->b = bind_batch(s->base, L, n, ccap, 1, cfg->dim);
   s->stream = (hipStream_t)stream;
   s->use_graph = getenv("CCAKE_NO_GRAPH") == nullptr && stream != nullptr;
   s->prm.src = (const SourceSet*)(s->base + L.src);

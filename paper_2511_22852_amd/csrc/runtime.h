@@ -19,7 +19,7 @@ struct Handle {
 
 // byte offsets of the arrays of one batch inside its workspace
 struct Layout {
-  size_t Y0, Ys, Y1, th, rec, recf, drec, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, xbin, rows, fo_rec, fo_slot, fo_mark, fo_ctr, cs, cf, evt,
+  size_t Y0, Ys, Y1, th, rec, recf, drec, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, xbin, rows, fo_rec, fo_slot, fo_mark, fo_ctr, plist, pcnt, cs, cf, evt,
       scratch, src, total;
 };
 
@@ -28,8 +28,8 @@ bool validate_config(const ccake_config* c, std::string* why);
 Params to_params(const ccake_config& c);
 uint32_t live_rows(const Params& p);
 int64_t cell_capacity(const ccake_config& c, int64_t n);
-Layout make_layout(int64_t cap, int64_t ccap, int nev);
-BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int nev);
+Layout make_layout(int64_t cap, int64_t ccap, int nev, int dim);
+BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int nev, int dim);
 
 }  // namespace ccake
 

@@ -336,7 +336,7 @@ extern "C" ccake_status ccake_server_workspace_bytes(const ccake_config* cfg, in
                                                      int32_t max_events, size_t* bytes) {
   std::string why;
   if (!bytes || !validate_config(cfg, &why) || max_particles <= 0 || max_events <= 0) return CCAKE_E_ARG;
-  *bytes = make_layout(max_particles, server_cell_capacity(max_particles, max_events), max_events).total;
+  *bytes = make_layout(max_particles, server_cell_capacity(max_particles, max_events), max_events, cfg->dim).total;
   return CCAKE_OK;
 }
 
@@ -348,7 +348,7 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
     return CCAKE_E_ARG;
   if (workspace && (((uintptr_t)workspace & 255u) != 0 ||
                     ws_bytes < make_layout(max_particles, server_cell_capacity(max_particles, max_events),
-                                           max_events).total))
+                                           max_events, cfg->dim).total))
     return CCAKE_E_ARG;
   if (eos->dev.kind == EOS_CONFORMAL && cfg->ncharge != 0) return CCAKE_E_ARG;
   if (eos->dev.inv.val && eos->dev.inv.ncharge != cfg->ncharge) return CCAKE_E_ARG;
@@ -362,7 +362,7 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
   s->max_particles = max_particles;
   s->max_events = max_events;
   s->ccap = server_cell_capacity(max_particles, max_events);
-  s->L = make_layout(max_particles, s->ccap, max_events);
+  s->L = make_layout(max_particles, s->ccap, max_events, cfg->dim);
   // bytes per resident particle of the arena (everything but the cells)
   s->per_particle_bytes = (s->L.cs) / (size_t)max_particles + 1;
   s->budget = budget_bytes;
@@ -385,7 +385,7 @@ extern "C" ccake_status ccake_server_create(ccake_server** out, const ccake_conf
     delete s;
     return CCAKE_E_NOMEM;
   }
-  s->b = bind_batch(s->arena, s->L, max_particles, s->ccap, max_events);
+  s->b = bind_batch(s->arena, s->L, max_particles, s->ccap, max_events, cfg->dim);
   (void)hipMemset(s->b.ev, 0xFF, sizeof(int32_t) * max_particles);
   (void)hipMemset(s->b.evt, 0, sizeof(EventDev) * max_events);
   (void)hipMemset(s->b.cell_fill, 0, sizeof(int32_t) * (s->ccap + 1));

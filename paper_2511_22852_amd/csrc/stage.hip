@@ -218,6 +218,11 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   TileCursor<L, ROWS> cur;
   cur.start(S.lo[t], S.hi[t], lane);
   constexpr int U = PairU<D>::U;
+  // this team's lanes within the wave; accepted pairs listed so far (the
+  // same on the team's lanes while they walk)
+  constexpr bool LIST = list_cap(D) > 0;
+  const uint64_t tmask = (L == 64 ? ~0ull : ((1ull << L) - 1)) << ((int)threadIdx.x & 63 & ~(L - 1));
+  int32_t nlist = 0;
   for (int32_t c0 = 0; c0 < total; c0 += C) {
     const int32_t c1 = total - c0 < C ? total : c0 + C;
     halo_load(H, S, Y, cap, c0, c1, [&](int32_t sl, Quad<MIXED>* q, size_t) {
@@ -249,6 +254,18 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
         if (G) H.q(0)[k[u]].get(sc[u]);
       }
       A.template add_block<U>(ok, d2, ih, sc);
+      // the accepted candidates, appended in walk order (lane order within
+      // a pass) to the target's list for the gradient pass
+#pragma unroll
+      for (int u = 0; u < (LIST ? U : 0); ++u) {
+        const uint64_t m = __ballot(ok[u]) & tmask;
+        if (ok[u]) {
+          const int32_t at =
+              nlist + (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (at < b.list_cap) b.plist[(int64_t)j * b.list_cap + at] = (uint16_t)(c0 + k[u]);
+        }
+        nlist += __popcll(m);
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (DBG && ok[u]) {
@@ -261,9 +278,18 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
       }
       if (!v[U - 1]) break;
     }
+    // the list's length so far: the lane that walked longest has seen every
+    // append of the chunk
+#pragma unroll
+    for (int off = LIST ? L / 2 : 0; off >= 1; off >>= 1) {
+      const int32_t o = __shfl_xor(nlist, off, 64);
+      nlist = o > nlist ? o : nlist;
+    }
     A.flush();
     __syncthreads();
   }
+  // -1 when the list overflows or its halo indices do not fit 16 bits
+  if (LIST && have && lane == 0) b.pcnt[j] = (nlist <= b.list_cap && total <= 65536) ? nlist : -1;
   // lanes v < 6 form row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
   double part[6], tot[(6 + L - 1) / L];
   A.partials(part);
@@ -357,6 +383,12 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   TileCursor<L, ROWS> cur;
   cur.start(S.lo[t], S.hi[t], lane);
   constexpr int U = PairU<D>::U;
+  // the target's accepted-pair list from this stage's density pass (-1:
+  // it did not fit; walk the candidates instead), next entry lp
+  constexpr bool LIST = list_cap(D) > 0;
+  const int32_t cnt = !LIST ? -1 : have ? min(b.pcnt[j], b.list_cap) : 0;
+  const bool listed = LIST && cnt >= 0;
+  int32_t lp = 0;
   for (int32_t c0 = 0; c0 < total; c0 += C) {
     const int32_t c1 = total - c0 < C ? total : c0 + C;
     halo_load(H, S, Y, cap, c0, c1, [&](int32_t sl, Quad<MIXED>* q, size_t stride) {
@@ -366,12 +398,9 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       for (int g = 0; g < GR::G; ++g) q[g * stride].put(op(4 * g), op(4 * g + 1), op(4 * g + 2), op(4 * g + 3));
     });
     __syncthreads();
-    cur.chunk(c0, c1);
-    for (;;) {
-      int32_t k[U];
-      bool v[U];
-      take<U>(cur, k, v);
-      if (!v[0]) break;
+    // the sums over U candidates per lane (chunk-local halo indices k[u],
+    // pairs where okin[u], the target itself excluded)
+    auto add_pairs = [&](const int32_t (&k)[U], const bool (&okin)[U]) {
       double xb[U][3], d2[U];
       bool ok[U];
 #pragma unroll
@@ -381,7 +410,7 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
         xb[u][1] = p.y;
         xb[u][2] = D == 3 ? H.z()[k[u]] : 0.0;
         d2[u] = dist2<D>(A.xa, xb[u]);
-        ok[u] = v[u] && d2[u] < r2max && d2[u] > 0.0;
+        ok[u] = okin[u] && d2[u] > 0.0;  // the target itself has no gradient term
       }
       RT rec[U][4 * GR::G];
 #pragma unroll
@@ -397,7 +426,61 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
           DA.add(A.xa, xb[u], d2[u], A.ih, ab, Fb, Pb);
         }
       }
-      if (!v[U - 1]) break;
+    };
+    if (listed) {
+      // the target's pairs from the density pass of this stage (the same
+      // positions, so the same pair test) with halo index in [c0, c1):
+      // entries lp + lane, lp + lane + L, ... of its list.  The density pass
+      // appends one ballot group (at most L entries, lanes in lane order) at
+      // a time and its lanes enter a chunk at different phases, so the list
+      // is ordered group by group: entries L or more apart are in halo order.
+      // A lane's first entry at or beyond c1 is therefore followed only by
+      // larger ones, and entries of the previous chunks met again below c0
+      // are skipped.
+      int32_t out = INT32_MAX;  // this lane's first entry at or beyond c1
+      for (int32_t i0 = lp + lane;; i0 += L * U) {
+        int32_t k[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t i = i0 + u * L;
+          const int32_t x = i < cnt ? (int32_t)b.plist[(int64_t)j * b.list_cap + i] : INT32_MAX;
+          ok[u] = x >= c0 && x < c1;
+          if (x >= c1 && i < out) out = i;
+          k[u] = ok[u] ? x - c0 : 0;
+        }
+        const bool end = out != INT32_MAX;
+        if (end && !ok[0]) break;
+        add_pairs(k, ok);
+        if (end) break;
+      }
+      // the team's next chunk starts at the first entry any of its lanes
+      // found at or beyond c1: every entry before it has been taken
+#pragma unroll
+      for (int off = L / 2; off >= 1; off >>= 1) {
+        const int32_t o = __shfl_xor(out, off, 64);
+        out = o < out ? o : out;
+      }
+      lp = out;
+    } else {
+      // more pairs than the list holds: the candidate walk with the pair test
+      cur.chunk(c0, c1);
+      for (;;) {
+        int32_t k[U];
+        bool v[U];
+        take<U>(cur, k, v);
+        if (!v[0]) break;
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double2 p = H.xy()[k[u]];
+          const double xq[3] = {p.x, p.y, D == 3 ? H.z()[k[u]] : 0.0};
+          const double dq = dist2<D>(A.xa, xq);
+          ok[u] = v[u] && dq < r2max && dq > 0.0;
+        }
+        add_pairs(k, ok);
+        if (!v[U - 1]) break;
+      }
     }
     A.flush();
     __syncthreads();
