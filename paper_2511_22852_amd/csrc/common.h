@@ -235,9 +235,8 @@ struct BatchDev {
   int32_t* fo_slot;  // [cap] sorted slot of each record's particle (step of its crossing)
   int32_t* fo_mark;  // [cap] per sorted slot: record found in this step's first stage, or -1
   uint32_t* fo_ctr;  // [2] records so far, records before this step
-  uint16_t* plist;   // [cap][list_cap] accepted candidates of each target (halo indices, walk order)
+  uint16_t* plist;   // [cap][list_cap(dim)] accepted candidates of each target (halo indices, walk order)
   int32_t* pcnt;     // [cap] their number, or -1 when they do not fit (the gradient pass walks)
-  int32_t list_cap;  // entries per target
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

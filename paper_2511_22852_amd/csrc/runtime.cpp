@@ -184,7 +184,6 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.fo_ctr = (uint32_t*)(base + L.fo_ctr);
   b.plist = (uint16_t*)(base + L.plist);
   b.pcnt = (int32_t*)(base + L.pcnt);
-  b.list_cap = list_cap(dim);
   b.cell_start = (int32_t*)(base + L.cs);
   b.cell_fill = (int32_t*)(base + L.cf);
   b.evt = (EventDev*)(base + L.evt);

@@ -220,8 +220,17 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   constexpr int U = PairU<D>::U;
   // this team's lanes within the wave; accepted pairs listed so far (the
   // same on the team's lanes while they walk)
+  // the accepted-pair list of the target (gradient pass), appended one
+  // ballot group at a time: the team's lanes are bits [tsh, tsh + L) of a
+  // wave ballot; nlist counts the team's appends so far (the same on its
+  // lanes while they walk).  Past the capacity the entries pile up on the
+  // last one: such a list is marked unusable below.
   constexpr bool LIST = list_cap(D) > 0;
-  const uint64_t tmask = (L == 64 ? ~0ull : ((1ull << L) - 1)) << ((int)threadIdx.x & 63 & ~(L - 1));
+  static_assert(!LIST || L <= 32, "a team's ballot bits fit one 32-bit word");
+  constexpr uint32_t TEAM_BITS = L == 32 ? ~0u : (1u << L) - 1u;
+  const uint32_t tsh = (uint32_t)threadIdx.x & 63u & ~(uint32_t)(L - 1);
+  const uint32_t below = (1u << lane) - 1u;
+  uint16_t* const mylist = b.plist + (LIST ? (have ? j : j0) * list_cap(D) : 0);
   int32_t nlist = 0;
   for (int32_t c0 = 0; c0 < total; c0 += C) {
     const int32_t c1 = total - c0 < C ? total : c0 + C;
@@ -258,13 +267,12 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
       // a pass) to the target's list for the gradient pass
 #pragma unroll
       for (int u = 0; u < (LIST ? U : 0); ++u) {
-        const uint64_t m = __ballot(ok[u]) & tmask;
+        const uint32_t tb = (uint32_t)(__builtin_amdgcn_ballot_w64(ok[u]) >> tsh);
         if (ok[u]) {
-          const int32_t at =
-              nlist + (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          if (at < b.list_cap) b.plist[(int64_t)j * b.list_cap + at] = (uint16_t)(c0 + k[u]);
+          const int32_t at = nlist + __popc(tb & below);
+          mylist[at < list_cap(D) ? at : list_cap(D) - 1] = (uint16_t)(c0 + k[u]);
         }
-        nlist += __popcll(m);
+        nlist += __popc(tb & TEAM_BITS);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -289,7 +297,7 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
     __syncthreads();
   }
   // -1 when the list overflows or its halo indices do not fit 16 bits
-  if (LIST && have && lane == 0) b.pcnt[j] = (nlist <= b.list_cap && total <= 65536) ? nlist : -1;
+  if (LIST && have && lane == 0) b.pcnt[j] = (nlist <= list_cap(D) && total <= 65536) ? nlist : -1;
   // lanes v < 6 form row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
   double part[6], tot[(6 + L - 1) / L];
   A.partials(part);
@@ -386,8 +394,10 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   // the target's accepted-pair list from this stage's density pass (-1:
   // it did not fit; walk the candidates instead), next entry lp
   constexpr bool LIST = list_cap(D) > 0;
-  const int32_t cnt = !LIST ? -1 : have ? min(b.pcnt[j], b.list_cap) : 0;
+  const int32_t cnt = !LIST ? -1 : have ? min(b.pcnt[j], list_cap(D)) : 0;
   const bool listed = LIST && cnt >= 0;
+  // (a lane without a target reads the list of the workgroup's first one)
+  const uint16_t* const mylist = b.plist + (LIST ? (have ? j : j0) * list_cap(D) : 0);
   int32_t lp = 0;
   for (int32_t c0 = 0; c0 < total; c0 += C) {
     const int32_t c1 = total - c0 < C ? total : c0 + C;
@@ -438,21 +448,38 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       // larger ones, and entries of the previous chunks met again below c0
       // are skipped.
       int32_t out = INT32_MAX;  // this lane's first entry at or beyond c1
+      // the entries of a pass are loaded one pass ahead, so that their
+      // latency hides behind the sums of the previous one
+      auto fetch = [&](int32_t (&xs)[U], int32_t i0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          // unconditional loads (entry 0 stands in past the end), so that
+          // the wait for them can leave the next pass's loads in flight
+          const int32_t i = i0 + u * L;
+          const int32_t v = mylist[i < cnt ? i : 0];
+          xs[u] = i < cnt ? v : INT32_MAX;
+        }
+      };
+      int32_t x[U];
+      fetch(x, lp + lane);
       for (int32_t i0 = lp + lane;; i0 += L * U) {
+        int32_t xn[U];
+        fetch(xn, i0 + L * U);
         int32_t k[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t i = i0 + u * L;
-          const int32_t x = i < cnt ? (int32_t)b.plist[(int64_t)j * b.list_cap + i] : INT32_MAX;
-          ok[u] = x >= c0 && x < c1;
-          if (x >= c1 && i < out) out = i;
-          k[u] = ok[u] ? x - c0 : 0;
+          ok[u] = x[u] >= c0 && x[u] < c1;
+          if (x[u] >= c1 && i < out) out = i;
+          k[u] = ok[u] ? x[u] - c0 : 0;
         }
         const bool end = out != INT32_MAX;
         if (end && !ok[0]) break;
         add_pairs(k, ok);
         if (end) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = xn[u];
       }
       // the team's next chunk starts at the first entry any of its lanes
       // found at or beyond c1: every entry before it has been taken
