@@ -333,19 +333,20 @@ def run_serving(B, I, eos, events, steps, precision, rate=None, max_particles=4_
     arrivals = [0.0] * len(events) if rate is None else list(I.poisson_arrivals(len(events), rate))
     results = []
     start = time.perf_counter()
-    for w, ta in zip(events, arrivals):
+    for k, (w, ta) in enumerate(zip(events, arrivals)):
         delay = ta - (time.perf_counter() - start)
         if delay > 0:
             time.sleep(delay)
-        srv.submit(w.t0, w.t0 + steps * w.dt, w.xi, w.u, w.dens_kind, w.dens, tag=len(results))
+        srv.submit(w.t0, w.t0 + steps * w.dt, w.xi, w.u, w.dens_kind, w.dens, tag=k)
         results += srv.poll(256)
     srv.drain()
     results += srv.poll(1024)
     st = srv.stats()
     srv.close()
-    bad = [r for r in results if r["status"] != 0]
-    if bad:
-        raise RuntimeError(f"{len(bad)} served events failed (status {bad[0]['status']})")
+    # an event whose evolution fails (sticky status: non-finite update, EoS
+    # without a root) is still stepped to its end time and returned with
+    # that status; it is reported here, and its latency counts like any other
+    failed = [dict(tag=int(r["tag"]), status=int(r["status"])) for r in results if r["status"] != 0]
     lat = sorted(r["t_finish"] - r["t_submit"] for r in results)
     first = min(r["t_submit"] for r in results)
     last = max(r["t_finish"] for r in results)
@@ -354,7 +355,7 @@ def run_serving(B, I, eos, events, steps, precision, rate=None, max_particles=4_
     return dict(events=len(results), makespan_s=span, events_per_s=len(results) / span,
                 particle_steps_per_s=st["particle_steps"] / span,
                 p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
-                mean_resident_particles=st["particle_steps"] / max(st["steps"], 1))
+                mean_resident_particles=st["particle_steps"] / max(st["steps"], 1), failed_events=failed)
 
 
 def cpu_baseline_run(I, w, min_seconds):
@@ -612,11 +613,11 @@ def main():
         print(f"[bench] serving: capacity {cap['particle_steps_per_s']:.3e} particle-steps/s, rate {rate:.2f} ev/s",
               file=sys.stderr, flush=True)
         load = run_serving(B, I, eos, events, steps, B.MIXED, rate=rate)
-        print(f"[bench] serving: p50 {load['p50_latency_s']:.3f} s, p99 {load['p99_latency_s']:.3f} s",
-              file=sys.stderr, flush=True)
+        print(f"[bench] serving: p50 {load['p50_latency_s']:.3f} s, p99 {load['p99_latency_s']:.3f} s, "
+              f"failed events {load['failed_events']}", file=sys.stderr, flush=True)
         seq = run_serving(B, I, eos, events, steps, B.FP64, rate=rate, max_events=1)
-        print(f"[bench] FP64 sequential: p50 {seq['p50_latency_s']:.3f} s, p99 {seq['p99_latency_s']:.3f} s",
-              file=sys.stderr, flush=True)
+        print(f"[bench] FP64 sequential: p50 {seq['p50_latency_s']:.3f} s, p99 {seq['p99_latency_s']:.3f} s, "
+              f"failed events {seq['failed_events']}", file=sys.stderr, flush=True)
         out["serving"] = {
             "workload": f"{len(events)} lumpy viscous BSQ events, N ~ U[5000, 80000] (total "
                         f"{sum(e.n for e in events)} particles), {steps} Heun steps each "
@@ -630,6 +631,12 @@ def main():
             "p50_latency_s": load["p50_latency_s"],
             "p99_latency_s": load["p99_latency_s"],
             "mean_resident_particles": load["mean_resident_particles"],
+            "capacity_failed_events": cap["failed_events"],
+            "failed_events": load["failed_events"],
+            "failed_events_note": "events (tag = index in the set) returned with a non-zero status (3: a "
+                                  "non-finite particle update); "
+                                  "the evolution runs to tau = 8 fm/c with no freeze-out, and the dilute edge "
+                                  "of some events (T of a few MeV) becomes unstable late in the run",
             "fp64_sequential": {k: v for k, v in seq.items() if k != "mean_resident_particles"},
             "fp64_sequential_note": "the same events and arrival trace, FP64, one event on the GPU at a time "
                                     "(a server with one event slot), latencies measured live",
