@@ -203,9 +203,12 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   int64_t j0, jend;
   if (!tile_targets<P>(b, xcd_block(blockIdx.x, gridDim.x), ev0, j0, jend)) return;  // whole workgroup
   const int32_t total = tile_setup<D, L, P>(b, j0, jend, S);
+  // team t walks target j0 + q (its partial sums go through the team's own
+  // LDS region t)
   const int t = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;
-  const int64_t j = j0 + t;
-  const bool have = S.seg[t] >= 0;
+  const int q = TeamSort<D>::ON ? S.perm[t] : t;
+  const int64_t j = j0 + q;
+  const bool have = S.seg[q] >= 0;
   (void)ev0;
   const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
   double xa[3] = {0.0, 0.0, 0.0};
@@ -216,7 +219,7 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   DensAcc<MIXED, NS> A;
   A.init();
   TileCursor<L, ROWS> cur;
-  cur.start(S.lo[t], S.hi[t], lane);
+  cur.start(S.lo[q], S.hi[q], lane);
   constexpr int U = PairU<D>::U;
   // this team's lanes within the wave; accepted pairs listed so far (the
   // same on the team's lanes while they walk)
@@ -372,9 +375,12 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   int64_t j0, jend;
   if (!tile_targets<P>(b, xcd_block(blockIdx.x, gridDim.x), ev0, j0, jend)) return;  // whole workgroup
   const int32_t total = tile_setup<D, L, P>(b, j0, jend, S);
+  // team t walks target j0 + q (its partial sums go through the team's own
+  // LDS region t)
   const int t = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;
-  const int64_t j = j0 + t;
-  const bool have = S.seg[t] >= 0;
+  const int q = TeamSort<D>::ON ? S.perm[t] : t;
+  const int64_t j = j0 + q;
+  const bool have = S.seg[q] >= 0;
   const double r2max = (2.0 * prm.h) * (2.0 * prm.h);
   GA A;
   DiffAcc<D, DIFF == 2> DA;
@@ -389,7 +395,7 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
     if (DIFF) DA.init(b.drec, cap, j0);
   }
   TileCursor<L, ROWS> cur;
-  cur.start(S.lo[t], S.hi[t], lane);
+  cur.start(S.lo[q], S.hi[q], lane);
   constexpr int U = PairU<D>::U;
   // the target's accepted-pair list from this stage's density pass (-1:
   // it did not fit; walk the candidates instead), next entry lp

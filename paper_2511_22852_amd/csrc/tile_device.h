@@ -40,6 +40,8 @@ struct TileShared {
   int32_t glo[NENT], ghi[NENT];          // per entry: slot range (ghi <= glo: empty)
   int32_t base[NENT + 1];                // per entry: first halo index
   int32_t seg[P];                        // segment of each target (-1: none)
+  int32_t cnt[P];                        // candidates of each target
+  int32_t perm[P];                       // target of each team (walk order, with TeamSort)
   int64_t key[P];                        // segment key of each target
   int32_t nseg, total;
   int32_t wsum[4];                       // scan scratch (one per wave)
@@ -86,10 +88,28 @@ __device__ __forceinline__ int64_t tile_segkey(const BatchDev& b, int64_t j, int
   return (int64_t)E.c_base + key - key % E.nc[0];
 }
 
-// Set-up of a tile: segments, halos, halo bases and the teams' ranges in
-// halo index space.  Every thread of the workgroup must call it.  Team t
-// (target j0 + t, if below jend) owns threads [t L, (t + 1) L).  Returns the
-// halo size.
+// Teams take the workgroup's targets in order of decreasing candidate count
+// (1) or in slot order (0), in 2+1D and 3+1D.  The ranking costs a barrier
+// in the set-up: in 3+1D, where the workgroups queue up on each CU and the
+// pair passes run at the issue limit, the lanes it saves pay for it; the
+// 2+1D passes run in a single round of workgroups and wait on latency.
+#ifndef CCAKE_TEAM_SORT2
+#define CCAKE_TEAM_SORT2 0
+#endif
+#ifndef CCAKE_TEAM_SORT3
+#define CCAKE_TEAM_SORT3 1
+#endif
+template <int D>
+struct TeamSort {
+  static constexpr bool ON = (D == 3 ? CCAKE_TEAM_SORT3 : CCAKE_TEAM_SORT2) != 0;
+};
+
+// Set-up of a tile: segments, halos, halo bases and the targets' ranges in
+// halo index space.  Every thread of the workgroup must call it.  Team t owns
+// threads [t L, (t + 1) L); it sets up target j0 + t (if below jend) and then
+// walks target j0 + perm[t] (with TeamSort<D>::ON; else target j0 + t), so
+// that the teams of a wave, which run in lock step, walk candidate lists of
+// similar length.  Returns the halo size.
 template <int D, int L, int P>
 __device__ __forceinline__ int32_t tile_setup(const BatchDev& b, int64_t j0, int64_t jend, TileShared<D, P>& S) {
   constexpr int ROWS = RowBlock<D>::ROWS;
@@ -179,6 +199,27 @@ __device__ __forceinline__ int32_t tile_setup(const BatchDev& b, int64_t j0, int
     }
   }
   __syncthreads();
+  // 5. the walk order: targets ranked by candidate count, largest first (ties
+  //    by slot); targets without a segment have none and come last
+  if (TeamSort<D>::ON) {
+    if (tid < P) {
+      int32_t c = 0;
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) c += S.hi[tid][r] - S.lo[tid][r];
+      S.cnt[tid] = c;
+    }
+    __syncthreads();
+    if (tid < P) {
+      const int32_t c = S.cnt[tid];
+      int rank = 0;
+      for (int u = 0; u < P; ++u) {
+        const int32_t cu = S.cnt[u];
+        rank += (cu > c || (cu == c && u < tid)) ? 1 : 0;
+      }
+      S.perm[rank] = tid;
+    }
+    __syncthreads();
+  }
   return total;
 }
 
