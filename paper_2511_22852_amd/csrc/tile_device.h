@@ -116,6 +116,18 @@ __device__ __forceinline__ int32_t tile_setup(const BatchDev& b, int64_t j0, int
   constexpr int NENT = P * ROWS;
   const int tid = threadIdx.x, t = tid / L, lane = tid % L;
   const int64_t j = j0 + t;
+  // the target's cached rows (slot ranges), loaded first so that their
+  // latency overlaps the segment numbering; a slot beyond the event's last
+  // has none
+  constexpr int RL = (ROWS + L - 1) / L;
+  int32_t rlo[RL], rhi[RL];
+#pragma unroll
+  for (int k = 0; k < RL; ++k) {
+    const int r = lane + k * L;
+    const bool ld = r < ROWS && j < jend;
+    rlo[k] = ld ? b.rows[(int64_t)(2 * r) * b.cap + j] : 0;
+    rhi[k] = ld ? b.rows[(int64_t)(2 * r + 1) * b.cap + j] : 0;
+  }
   // 1. segment keys, then segment numbers by a prefix count of the boundaries
   if (lane == 0) S.key[t] = tile_segkey(b, j, jend);
   for (int q = tid; q < NENT; q += 256) {
@@ -133,13 +145,16 @@ __device__ __forceinline__ int32_t tile_setup(const BatchDev& b, int64_t j0, int
     if (tid == 0) S.nseg = __popcll(heads);
   }
   __syncthreads();
-  // 2. the target's cached rows (slot ranges) and the segment halos
+  // 2. the segment halos
   const int sg = S.seg[t];
-  for (int r = lane; r < ROWS; r += L) {
+#pragma unroll
+  for (int k = 0; k < RL; ++k) {
+    const int r = lane + k * L;
+    if (r >= ROWS) break;
     int32_t lo = 0, hi = 0;
     if (sg >= 0) {
-      lo = b.rows[(int64_t)(2 * r) * b.cap + j];
-      hi = b.rows[(int64_t)(2 * r + 1) * b.cap + j];
+      lo = rlo[k];
+      hi = rhi[k];
       if (hi > lo) {
         atomicMin(&S.glo[sg * ROWS + r], lo);
         atomicMax(&S.ghi[sg * ROWS + r], hi);
