@@ -202,14 +202,13 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   int ev0;
   int64_t j0, jend;
   if (!tile_targets<P>(b, xcd_block(blockIdx.x, gridDim.x), ev0, j0, jend)) return;  // whole workgroup
-  const int32_t total = tile_setup<D, L, P>(b, j0, jend, S);
+  const int32_t total = tile_setup<D, L, P>(b, ev0, j0, jend, S);
   // team t walks target j0 + q (its partial sums go through the team's own
   // LDS region t)
   const int t = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;
   const int q = TeamSort<D>::ON ? S.perm[t] : t;
   const int64_t j = j0 + q;
   const bool have = S.seg[q] >= 0;
-  (void)ev0;
   const double h = prm.h, ih = 1.0 / h, r2max = (2.0 * h) * (2.0 * h);
   double xa[3] = {0.0, 0.0, 0.0};
   if (have) {
@@ -374,7 +373,7 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   int ev0;
   int64_t j0, jend;
   if (!tile_targets<P>(b, xcd_block(blockIdx.x, gridDim.x), ev0, j0, jend)) return;  // whole workgroup
-  const int32_t total = tile_setup<D, L, P>(b, j0, jend, S);
+  const int32_t total = tile_setup<D, L, P>(b, ev0, j0, jend, S);
   // team t walks target j0 + q (its partial sums go through the team's own
   // LDS region t)
   const int t = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;

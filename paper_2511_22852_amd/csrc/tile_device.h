@@ -77,13 +77,12 @@ __device__ __forceinline__ bool tile_targets(const BatchDev& b, int64_t t, int& 
   return true;
 }
 
-// Segment key of slot j: the global cell index of the first cell of its
-// cell row (rows of different events never share a key), -1 for no target.
-__device__ __forceinline__ int64_t tile_segkey(const BatchDev& b, int64_t j, int64_t jend) {
+// Segment key of slot j of event E: the global cell index of the first cell
+// of its cell row (rows of different events never share a key), -1 for no
+// target.  Every slot of an active event's range [p_base, p_base + n) holds
+// one of its particles, so a tile's targets need no slot-to-event lookup.
+__device__ __forceinline__ int64_t tile_segkey(const BatchDev& b, const EventDev& E, int64_t j, int64_t jend) {
   if (j >= jend) return -1;
-  const int e = b.ev[j];
-  if (e < 0) return -1;
-  const EventDev& E = b.evt[e];
   const int32_t key = b.keys[j];
   return (int64_t)E.c_base + key - key % E.nc[0];
 }
@@ -104,14 +103,15 @@ struct TeamSort {
   static constexpr bool ON = (D == 3 ? CCAKE_TEAM_SORT3 : CCAKE_TEAM_SORT2) != 0;
 };
 
-// Set-up of a tile: segments, halos, halo bases and the targets' ranges in
-// halo index space.  Every thread of the workgroup must call it.  Team t owns
+// Set-up of a tile of event ev0: segments, halos, halo bases and the targets'
+// ranges in halo index space.  Every thread of the workgroup must call it.  Team t owns
 // threads [t L, (t + 1) L); it sets up target j0 + t (if below jend) and then
 // walks target j0 + perm[t] (with TeamSort<D>::ON; else target j0 + t), so
 // that the teams of a wave, which run in lock step, walk candidate lists of
 // similar length.  Returns the halo size.
 template <int D, int L, int P>
-__device__ __forceinline__ int32_t tile_setup(const BatchDev& b, int64_t j0, int64_t jend, TileShared<D, P>& S) {
+__device__ __forceinline__ int32_t tile_setup(const BatchDev& b, int ev0, int64_t j0, int64_t jend,
+                                              TileShared<D, P>& S) {
   constexpr int ROWS = RowBlock<D>::ROWS;
   constexpr int NENT = P * ROWS;
   const int tid = threadIdx.x, t = tid / L, lane = tid % L;
@@ -129,7 +129,7 @@ __device__ __forceinline__ int32_t tile_setup(const BatchDev& b, int64_t j0, int
     rhi[k] = ld ? b.rows[(int64_t)(2 * r + 1) * b.cap + j] : 0;
   }
   // 1. segment keys, then segment numbers by a prefix count of the boundaries
-  if (lane == 0) S.key[t] = tile_segkey(b, j, jend);
+  if (lane == 0) S.key[t] = tile_segkey(b, b.evt[ev0], j, jend);
   for (int q = tid; q < NENT; q += 256) {
     S.glo[q] = INT32_MAX;
     S.ghi[q] = INT32_MIN;
