@@ -166,6 +166,14 @@ def lumpy3d_small():
     return I.lumpy_3d_workload(nxy=20, dxy=0.1, neta=12, deta=0.125, h=0.3, seed=3, n_hot=6, radius=0.6)
 
 
+def dense3d():
+    """13,824 particles at 0.1 fm spacing with h = 0.55 fm: about 5,500
+    neighbours in the middle of the box, under a thousand in its corners, so
+    that targets with more accepted pairs than a pair list holds (4096) share
+    workgroups with targets whose lists fit."""
+    return I.lumpy_3d_workload(nxy=24, dxy=0.1, neta=24, deta=0.1, h=0.55, seed=5, n_hot=4, radius=0.5)
+
+
 RATE_CASES = {
     "gubser2d_ideal": dict(wl=lambda: I.gubser_workload(), kw=dict(dim=2, eos="conformal", h=0.3), visc=False),
     "gubser2d_cartesian": dict(wl=lambda: I.gubser_workload(hyperbolic=False),
@@ -191,6 +199,8 @@ RATE_CASES = {
                                                         coeffs=dict(c_pisig=-0.6)), visc=True),
     "lumpy3d_ideal_cartesian": dict(wl=lumpy3d_small, kw=dict(dim=3, hyperbolic=False, ncharge=3, eos="gas", h=0.3),
                                     visc=False),
+    "dense3d_list_overflow": dict(wl=dense3d, kw=dict(dim=3, viscous=True, ncharge=3, eos="table", h=0.55),
+                                  visc=True),
 }
 
 
@@ -396,6 +406,29 @@ def test_mixed_precision_lumpy(B, O):
     f, aux_g = sim.rhs()
     assert rel_l2(aux_g[O.A_E], aux_o[O.A_E]) <= 1e-4
     assert rel_l2(aux_g[O.A_NB], aux_o[O.A_NB]) <= 1e-4
+
+
+def test_pair_list_overflow(B, O):
+    """The 3+1D gradient pass walks the pairs the density pass listed, up to
+    4096 per target, and a target with more walks its candidates instead.  In
+    the dense case both kinds occur (checked on the oracle's neighbour
+    counts, self included, as the lists count it); test_rate_parity_fp64
+    checks their FP64 rates element by element, and here the mixed-precision
+    rates of both kinds stay within 1e-6 of the oracle (measured 1e-8 to 4e-8)."""
+    prm, oe, cfg, ge, y, t0 = prepared(B, O, "dense3d_list_overflow")
+    f_o, aux_o, bad = O.rhs(prm, oe, t0, y)
+    assert bad == 0
+    listed = aux_o[O.A_NNB] + 1 <= 4096
+    assert listed.sum() > 1000 and (~listed).sum() > 1000
+    _, _, cfg_m, ge_m = make(O, B, precision=B.MIXED, **RATE_CASES["dense3d_list_overflow"]["kw"])
+    sim = sim_from_state(B, cfg_m, ge_m, y, t0)
+    f_g, aux_g = sim.rhs()
+    for part in (listed, ~listed):
+        for r in (O.V_U1, O.V_U2, O.V_U3, O.V_S):
+            scale = np.abs(f_o[r]).max()
+            err = np.abs(f_g[r][part] - f_o[r][part]).max() / scale
+            print(f"\nrate row {r}, {'listed' if part is listed else 'overflowing'} targets: {err:.1e}")
+            assert err <= 1e-6, r
 
 
 def test_mixed_precision_conservation(B, O):
