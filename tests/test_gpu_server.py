@@ -256,3 +256,27 @@ def test_failing_event_isolated(B):
         assert r["steps"] == steps[r["tag"]]
         assert np.array_equal(r["state"], y, equal_nan=True)
     assert ref[1][0] == 0 and ref[2][0] == 0
+
+
+def test_alone_equals_in_mix_3d(B):
+    """3+1D events served together end bit for bit as alone: their neighbour
+    tiles, the accepted-pair lists of the gradient pass (one per target, in
+    the shared arena) and the teams' walk order stay per event."""
+    cols, lo, hi = I.massless_gas_table(nT=24, nmu=12)
+    eos = B.Eos.table(cols, lo, hi)
+    cfg = B.config(dim=3, hyperbolic=True, viscous=True, ncharge=3, h=0.3, precision=B.MIXED, **TR)
+    evs = [I.lumpy_3d_workload(nxy=8 + 2 * i, dxy=0.1, neta=6 + i, deta=0.125, h=0.3, seed=20 + i, n_hot=2,
+                               radius=0.3) for i in range(4)]
+    steps = [4, 6, 3, 5]
+    ref = [alone(B, cfg, eos, w, s) for w, s in zip(evs, steps)]
+    srv = B.Server(cfg, eos, budget_bytes=2 << 30, max_particles=20000, max_events=8, dt=evs[0].dt)
+    for i, (w, s) in enumerate(zip(evs, steps)):
+        srv.submit(w.t0, w.t0 + s * w.dt, w.xi, w.u, w.dens_kind, w.dens, tag=i)
+    srv.drain()
+    res = srv.poll(16)
+    srv.close()
+    assert len(res) == len(evs)
+    for r in res:
+        i = r["tag"]
+        assert r["status"] == 0 and r["steps"] == steps[i]
+        assert np.array_equal(r["state"], ref[i]), i
