@@ -123,11 +123,11 @@ struct SourceSet {
 #ifndef CCAKE_SUBCELLS3
 #define CCAKE_SUBCELLS3 2
 #endif
-// Entries per target of the accepted-pair lists (2D, 3D; 0: no lists):
-// about six times the mean neighbour count of the 3D benchmark events; a
-// target with more pairs falls back to the candidate walk in the gradient
-// pass.  In 2D the candidate walk accepts most of what it reads and writing
-// the lists costs the density pass more than the gradient pass saves.
+// Entries per target of the skin lists (2D, 3D; 0: no lists): about six
+// times the mean neighbour count of the 3D benchmark events; a target with
+// more falls back to the candidate walk.  In 2D the candidate walk accepts
+// most of what it reads and writing the lists costs the density pass more
+// than the other passes save.
 #ifndef CCAKE_LIST_CAP2
 #define CCAKE_LIST_CAP2 0
 #endif
@@ -235,8 +235,8 @@ struct BatchDev {
   int32_t* fo_slot;  // [cap] sorted slot of each record's particle (step of its crossing)
   int32_t* fo_mark;  // [cap] per sorted slot: record found in this step's first stage, or -1
   uint32_t* fo_ctr;  // [2] records so far, records before this step
-  uint16_t* plist;   // [cap][list_cap(dim)] accepted candidates of each target (halo indices, walk order)
-  int32_t* pcnt;     // [cap] their number, or -1 when they do not fit (the gradient pass walks)
+  uint16_t* slist;   // [cap][list_cap(dim)] skin list of each target: halo indices of its candidates within 2h + 2d at a step's first stage, in walk order
+  int32_t* scnt;     // [cap] their number, or -1 when they do not fit (the passes walk the candidates)
   int32_t* cell_start;  // [ccap + 1] absolute slot of each cell
   int32_t* cell_fill;   // [ccap] counts / cursors
   EventDev* evt;     // [max_events]

@@ -146,8 +146,8 @@ Layout make_layout(int64_t cap, int64_t ccap, int nev, int dim) {
   L.fo_slot = take(&o, I4 * cap);
   L.fo_mark = take(&o, I4 * cap);
   L.fo_ctr = take(&o, I4 * 2);
-  L.plist = take(&o, sizeof(uint16_t) * (size_t)list_cap(dim) * cap);
-  L.pcnt = take(&o, I4 * cap);
+  L.slist = take(&o, sizeof(uint16_t) * (size_t)list_cap(dim) * cap);
+  L.scnt = take(&o, I4 * cap);
   L.cs = take(&o, I4 * (ccap + 1));
   L.cf = take(&o, I4 * (ccap + 1));
   L.evt = take(&o, sizeof(EventDev) * nev);
@@ -182,8 +182,8 @@ BatchDev bind_batch(char* base, const Layout& L, int64_t cap, int64_t ccap, int 
   b.fo_slot = (int32_t*)(base + L.fo_slot);
   b.fo_mark = (int32_t*)(base + L.fo_mark);
   b.fo_ctr = (uint32_t*)(base + L.fo_ctr);
-  b.plist = (uint16_t*)(base + L.plist);
-  b.pcnt = (int32_t*)(base + L.pcnt);
+  b.slist = (uint16_t*)(base + L.slist);
+  b.scnt = (int32_t*)(base + L.scnt);
   b.cell_start = (int32_t*)(base + L.cs);
   b.cell_fill = (int32_t*)(base + L.cf);
   b.evt = (EventDev*)(base + L.evt);

@@ -19,7 +19,7 @@ struct Handle {
 
 // byte offsets of the arrays of one batch inside its workspace
 struct Layout {
-  size_t Y0, Ys, Y1, th, rec, recf, drec, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, xbin, rows, fo_rec, fo_slot, fo_mark, fo_ctr, plist, pcnt, cs, cf, evt,
+  size_t Y0, Ys, Y1, th, rec, recf, drec, warm, warms, dsum, gsum, aux, id, ids, ev, key, keys, perm, xbin, rows, fo_rec, fo_slot, fo_mark, fo_ctr, slist, scnt, cs, cf, evt,
       scratch, src, total;
 };
 

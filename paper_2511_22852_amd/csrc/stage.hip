@@ -185,9 +185,12 @@ __device__ __forceinline__ void take(Cursor& cur, int32_t k[U], bool v[U]) {
 
 // ---------------------------------------------------------------------------
 // NS: smoothed scalars per neighbour (0 specific densities, 1 s*, 4 s* and n*);
-// DBG: export the accepted pairs
+// DBG: export the accepted pairs.  stage: the Heun stage (in 3+1D, stage 0
+// also lists every candidate within the support plus twice a step's
+// displacement bound, and the later pair passes of the step walk that skin
+// list instead of the candidates)
 template <int D, bool MIXED, int NS, bool DBG>
-__global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const double* __restrict__ Y,
+__global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const double* __restrict__ Y, int stage,
                                                  PairExport px) {
   constexpr int L = Team<D>::L, P = Team<D>::P;
   constexpr int ROWS = RowBlock<D>::ROWS;
@@ -220,11 +223,9 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   TileCursor<L, ROWS> cur;
   cur.start(S.lo[q], S.hi[q], lane);
   constexpr int U = PairU<D>::U;
-  // this team's lanes within the wave; accepted pairs listed so far (the
-  // same on the team's lanes while they walk)
-  // the accepted-pair list of the target (gradient pass), appended one
-  // ballot group at a time: the team's lanes are bits [tsh, tsh + L) of a
-  // wave ballot; nlist counts the team's appends so far (the same on its
+  // The target's skin list (3+1D), appended one ballot group at a time: the
+  // team's lanes are bits [tsh, tsh + L) of a wave ballot, and a group goes
+  // out in lane order; nskin counts the entries (the same on the team's
   // lanes while they walk).  Past the capacity the entries pile up on the
   // last one: such a list is marked unusable below.
   constexpr bool LIST = list_cap(D) > 0;
@@ -232,8 +233,71 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
   constexpr uint32_t TEAM_BITS = L == 32 ? ~0u : (1u << L) - 1u;
   const uint32_t tsh = (uint32_t)threadIdx.x & 63u & ~(uint32_t)(L - 1);
   const uint32_t below = (1u << lane) - 1u;
-  uint16_t* const mylist = b.plist + (LIST ? (have ? j : j0) * list_cap(D) : 0);
-  int32_t nlist = 0;
+  uint16_t* const myskin = b.slist + (LIST ? (have ? j : j0) * list_cap(D) : 0);
+  int32_t nskin = 0;
+  // Skin list of stage 0: every candidate within 2h + 2d of the target,
+  // d = dt max(1, 1/x0) the bound on a particle's displacement over a step
+  // (its coordinate speeds are below 1, and below 1/x0 along eta in Milne
+  // coordinates).  A pair within 2h at the stage-1 positions is within
+  // 2h + 2d at the stage-0 ones, and the rows of the last binning hold every
+  // such candidate (a binning is redone before twice the displacement bound
+  // accumulated by the end of a step exceeds the skin).  The gradient pass of
+  // stage 0 and both passes of stage 1 then test only these, with the same
+  // pair test.
+  const bool make_skin = LIST && !DBG && stage == 0;
+  double r2skin = 0.0;
+  if (make_skin) {
+    const EventDev& E = b.evt[ev0];
+    const double vmax = (prm.hyperbolic && D == 3) ? fmax(1.0, 1.0 / E.t) : 1.0;
+    const double rs = 2.0 * h + 2.0 * E.dt * vmax;
+    r2skin = rs * rs * (1.0 + 1e-9);
+  }
+  // stage 1: the target's skin list (-1: it did not fit; walk the candidates)
+  const int32_t scnt = !(LIST && !DBG && stage == 1) ? -1 : have ? min(b.scnt[j], list_cap(D)) : 0;
+  const bool from_skin = scnt >= 0;
+  int32_t sp = 0;  // next skin-list entry
+  // the sums over U candidates per lane (chunk-local halo indices k[u]; v[u]
+  // marks the ones to test), with the skin-list appends
+  auto add_pairs = [&](int32_t c0, const int32_t (&k)[U], const bool (&v)[U]) {
+    double d2[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double2 p = H.xy()[k[u]];
+      const double xb[3] = {p.x, p.y, D == 3 ? H.z()[k[u]] : 0.0};
+      d2[u] = dist2<D>(xa, xb);
+      ok[u] = v[u] && d2[u] < r2max;
+    }
+    RT sc[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sc[u][0] = sc[u][1] = sc[u][2] = sc[u][3] = RT(0);
+      if (G) H.q(0)[k[u]].get(sc[u]);
+    }
+    A.template add_block<U>(ok, d2, ih, sc);
+    if (make_skin) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool sk = v[u] && d2[u] < r2skin;
+        const uint32_t tb = (uint32_t)(__builtin_amdgcn_ballot_w64(sk) >> tsh);
+        if (sk) {
+          const int32_t at = nskin + __popc(tb & below);
+          myskin[at < list_cap(D) ? at : list_cap(D) - 1] = (uint16_t)(c0 + k[u]);
+        }
+        nskin += __popc(tb & TEAM_BITS);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (DBG && ok[u]) {
+        const int64_t at = (int64_t)atomicAdd((unsigned long long*)px.counter, 1ull);
+        if (at < px.cap) {
+          px.a[at] = b.ids[j];
+          px.b[at] = b.ids[H.slot()[k[u]]];
+        }
+      }
+    }
+  };
   for (int32_t c0 = 0; c0 < total; c0 += C) {
     const int32_t c1 = total - c0 < C ? total : c0 + C;
     halo_load(H, S, Y, cap, c0, c1, [&](int32_t sl, Quad<MIXED>* q, size_t) {
@@ -243,63 +307,74 @@ __global__ void __launch_bounds__(256) k_density(BatchDev b, Params prm, const d
         q->put(row(Y, cap, R_S, sl), 0.0, 0.0, 0.0);
     });
     __syncthreads();
-    cur.chunk(c0, c1);
-    for (;;) {
-      int32_t k[U];
-      bool v[U];
-      take<U>(cur, k, v);
-      if (!v[0]) break;
-      double d2[U];
-      bool ok[U];
+    if (from_skin) {
+      // stage 1: the skin-list entries with halo index in [c0, c1), lane k
+      // taking entries sp + k, sp + k + L, ...  Lanes enter a chunk of the
+      // stage-0 walk at different phases, so the list is ordered group by
+      // group only (entries L or more apart are in halo order): a lane's
+      // first entry at or beyond c1 is followed only by larger ones, and
+      // entries met again below c0 were taken in an earlier chunk.
+      int32_t out = INT32_MAX;  // this lane's first entry at or beyond c1
+      auto fetch = [&](int32_t (&xs)[U], int32_t i0) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double2 p = H.xy()[k[u]];
-        const double xb[3] = {p.x, p.y, D == 3 ? H.z()[k[u]] : 0.0};
-        d2[u] = dist2<D>(xa, xb);
-        ok[u] = v[u] && d2[u] < r2max;
-      }
-      RT sc[U][4];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        sc[u][0] = sc[u][1] = sc[u][2] = sc[u][3] = RT(0);
-        if (G) H.q(0)[k[u]].get(sc[u]);
-      }
-      A.template add_block<U>(ok, d2, ih, sc);
-      // the accepted candidates, appended in walk order (lane order within
-      // a pass) to the target's list for the gradient pass
-#pragma unroll
-      for (int u = 0; u < (LIST ? U : 0); ++u) {
-        const uint32_t tb = (uint32_t)(__builtin_amdgcn_ballot_w64(ok[u]) >> tsh);
-        if (ok[u]) {
-          const int32_t at = nlist + __popc(tb & below);
-          mylist[at < list_cap(D) ? at : list_cap(D) - 1] = (uint16_t)(c0 + k[u]);
+        for (int u = 0; u < U; ++u) {
+          // unconditional loads (entry 0 stands in past the end), so that
+          // the wait for them can leave the next pass's loads in flight
+          const int32_t i = i0 + u * L;
+          const int32_t v = myskin[i < scnt ? i : 0];
+          xs[u] = i < scnt ? v : INT32_MAX;
         }
-        nlist += __popc(tb & TEAM_BITS);
+      };
+      int32_t x[U];
+      fetch(x, sp + lane);
+      for (int32_t i0 = sp + lane;; i0 += L * U) {
+        int32_t xn[U];
+        fetch(xn, i0 + L * U);
+        int32_t k[U];
+        bool v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t i = i0 + u * L;
+          v[u] = x[u] >= c0 && x[u] < c1;
+          if (x[u] >= c1 && i < out) out = i;
+          k[u] = v[u] ? x[u] - c0 : 0;
+        }
+        const bool end = out != INT32_MAX;
+        if (end && !v[0]) break;
+        add_pairs(c0, k, v);
+        if (end) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = xn[u];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (DBG && ok[u]) {
-          const int64_t at = (int64_t)atomicAdd((unsigned long long*)px.counter, 1ull);
-          if (at < px.cap) {
-            px.a[at] = b.ids[j];
-            px.b[at] = b.ids[H.slot()[k[u]]];
-          }
-        }
+      for (int off = L / 2; off >= 1; off >>= 1) {
+        const int32_t o = __shfl_xor(out, off, 64);
+        out = o < out ? o : out;
       }
-      if (!v[U - 1]) break;
+      sp = out;
+    } else {
+      cur.chunk(c0, c1);
+      for (;;) {
+        int32_t k[U];
+        bool v[U];
+        take<U>(cur, k, v);
+        if (!v[0]) break;
+        add_pairs(c0, k, v);
+        if (!v[U - 1]) break;
+      }
     }
-    // the list's length so far: the lane that walked longest has seen every
-    // append of the chunk
+    // the lists' lengths so far: the lane that walked longest has seen
+    // every append of the chunk
 #pragma unroll
     for (int off = LIST ? L / 2 : 0; off >= 1; off >>= 1) {
-      const int32_t o = __shfl_xor(nlist, off, 64);
-      nlist = o > nlist ? o : nlist;
+      const int32_t os = __shfl_xor(nskin, off, 64);
+      nskin = os > nskin ? os : nskin;
     }
     A.flush();
     __syncthreads();
   }
   // -1 when the list overflows or its halo indices do not fit 16 bits
-  if (LIST && have && lane == 0) b.pcnt[j] = (nlist <= list_cap(D) && total <= 65536) ? nlist : -1;
+  if (make_skin && have && lane == 0) b.scnt[j] = (nskin <= list_cap(D) && total <= 65536) ? nskin : -1;
   // lanes v < 6 form row v of the density sums (sigma*, S, N_B, N_S, N_Q, count)
   double part[6], tot[(6 + L - 1) / L];
   A.partials(part);
@@ -396,13 +471,13 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
   TileCursor<L, ROWS> cur;
   cur.start(S.lo[q], S.hi[q], lane);
   constexpr int U = PairU<D>::U;
-  // the target's accepted-pair list from this stage's density pass (-1:
-  // it did not fit; walk the candidates instead), next entry lp
+  // the target's skin list from the step's first density pass (-1: it did
+  // not fit; walk the candidates instead), next entry lp
   constexpr bool LIST = list_cap(D) > 0;
-  const int32_t cnt = !LIST ? -1 : have ? min(b.pcnt[j], list_cap(D)) : 0;
+  const int32_t cnt = !LIST ? -1 : have ? min(b.scnt[j], list_cap(D)) : 0;
   const bool listed = LIST && cnt >= 0;
   // (a lane without a target reads the list of the workgroup's first one)
-  const uint16_t* const mylist = b.plist + (LIST ? (have ? j : j0) * list_cap(D) : 0);
+  const uint16_t* const mylist = b.slist + (LIST ? (have ? j : j0) * list_cap(D) : 0);
   int32_t lp = 0;
   for (int32_t c0 = 0; c0 < total; c0 += C) {
     const int32_t c1 = total - c0 < C ? total : c0 + C;
@@ -425,7 +500,8 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
         xb[u][1] = p.y;
         xb[u][2] = D == 3 ? H.z()[k[u]] : 0.0;
         d2[u] = dist2<D>(A.xa, xb[u]);
-        ok[u] = okin[u] && d2[u] > 0.0;  // the target itself has no gradient term
+        // the pair test (the target itself has no gradient term)
+        ok[u] = okin[u] && d2[u] < r2max && d2[u] > 0.0;
       }
       RT rec[U][4 * GR::G];
 #pragma unroll
@@ -443,15 +519,14 @@ __global__ void __launch_bounds__(256) k_grad(BatchDev b, Params prm, const doub
       }
     };
     if (listed) {
-      // the target's pairs from the density pass of this stage (the same
-      // positions, so the same pair test) with halo index in [c0, c1):
-      // entries lp + lane, lp + lane + L, ... of its list.  The density pass
-      // appends one ballot group (at most L entries, lanes in lane order) at
-      // a time and its lanes enter a chunk at different phases, so the list
-      // is ordered group by group: entries L or more apart are in halo order.
-      // A lane's first entry at or beyond c1 is therefore followed only by
-      // larger ones, and entries of the previous chunks met again below c0
-      // are skipped.
+      // the target's skin-list entries with halo index in [c0, c1), each
+      // with the pair test at this stage's positions: entries lp + lane,
+      // lp + lane + L, ... of its list.  The density pass appends one ballot
+      // group (at most L entries, lanes in lane order) at a time and its
+      // lanes enter a chunk at different phases, so the list is ordered group
+      // by group: entries L or more apart are in halo order.  A lane's first
+      // entry at or beyond c1 is therefore followed only by larger ones, and
+      // entries of the previous chunks met again below c0 are skipped.
       int32_t out = INT32_MAX;  // this lane's first entry at or beyond c1
       // the entries of a pass are loaded one pass ahead, so that their
       // latency hides behind the sums of the previous one
@@ -1192,11 +1267,11 @@ static void stage_t(const BatchDev& b, const Params& prm, const EosDev& eos, int
   const hipEvent_t* eg = mk ? mk + 4 : nullptr;
   const hipEvent_t* em = mk ? mk + 6 : nullptr;
   if (prm.density_mode != 0)
-    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 0, false>), dim3(gt), dim3(256), b, prm, Y, none);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 0, false>), dim3(gt), dim3(256), b, prm, Y, stage, none);
   else if (prm.ncharge)
-    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 4, false>), dim3(gt), dim3(256), b, prm, Y, none);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 4, false>), dim3(gt), dim3(256), b, prm, Y, stage, none);
   else
-    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 1, false>), dim3(gt), dim3(256), b, prm, Y, none);
+    CCAKE_STAGE_LAUNCH(ed, (k_density<D, MIXED, 1, false>), dim3(gt), dim3(256), b, prm, Y, stage, none);
   // the freeze-out surface is looked for at the step start of a step
   const int fo = (mode == 0 && prm.e_fo > 0.0) ? 1 : 0;
   if (fo) hipLaunchKernelGGL(k_fo_begin, dim3(1), dim3(64), 0, s, b);
@@ -1239,11 +1314,11 @@ static void pairs_cached_t(const BatchDev& b, const Params& prm, int64_t nslots,
   if (b.max_events > 1) hipLaunchKernelGGL(k_tiles, dim3(1), dim3(256), 0, s, b, Team<D>::P);
   const dim3 grid(pair_blocks(b, nslots, Team<D>::P));
   if (prm.density_mode != 0)
-    hipLaunchKernelGGL((k_density<D, MIXED, 0, true>), grid, dim3(256), 0, s, b, prm, b.Ys, px);
+    hipLaunchKernelGGL((k_density<D, MIXED, 0, true>), grid, dim3(256), 0, s, b, prm, b.Ys, 0, px);
   else if (prm.ncharge)
-    hipLaunchKernelGGL((k_density<D, MIXED, 4, true>), grid, dim3(256), 0, s, b, prm, b.Ys, px);
+    hipLaunchKernelGGL((k_density<D, MIXED, 4, true>), grid, dim3(256), 0, s, b, prm, b.Ys, 0, px);
   else
-    hipLaunchKernelGGL((k_density<D, MIXED, 1, true>), grid, dim3(256), 0, s, b, prm, b.Ys, px);
+    hipLaunchKernelGGL((k_density<D, MIXED, 1, true>), grid, dim3(256), 0, s, b, prm, b.Ys, 0, px);
 }
 
 hipError_t launch_pairs_cached(const BatchDev& b, const Params& prm, int64_t nslots, int64_t* counter,

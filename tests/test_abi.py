@@ -48,8 +48,8 @@ def test_workspace_bytes_grows_with_n():
     # about 2 kB per particle: state and stage copies, neighbour records, sums,
     # row caches and the diffusion records and sums
     assert sizes[2] < 2500 * 40000
-    # 3+1D adds the accepted-pair list of the gradient pass: 4096 two-byte
-    # entries per particle
+    # 3+1D adds the skin list that the pair passes after a step's first
+    # density pass walk: 4096 two-byte entries per particle
     cfg3 = B.config(dim=3, viscous=True, eta_over_s=0.08, ncharge=3)
     nb3 = ctypes.c_size_t()
     assert B.lib().ccake_workspace_bytes(ctypes.byref(cfg3), 40000, ctypes.byref(nb3)) == B.OK

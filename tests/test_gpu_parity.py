@@ -169,8 +169,8 @@ def lumpy3d_small():
 def dense3d():
     """13,824 particles at 0.1 fm spacing with h = 0.55 fm: about 5,500
     neighbours in the middle of the box, under a thousand in its corners, so
-    that targets with more accepted pairs than a pair list holds (4096) share
-    workgroups with targets whose lists fit."""
+    that targets with more candidates within reach than a skin list holds
+    (4096) share workgroups with targets whose lists fit."""
     return I.lumpy_3d_workload(nxy=24, dxy=0.1, neta=24, deta=0.1, h=0.55, seed=5, n_hot=4, radius=0.5)
 
 
@@ -409,12 +409,14 @@ def test_mixed_precision_lumpy(B, O):
 
 
 def test_pair_list_overflow(B, O):
-    """The 3+1D gradient pass walks the pairs the density pass listed, up to
-    4096 per target, and a target with more walks its candidates instead.  In
-    the dense case both kinds occur (checked on the oracle's neighbour
-    counts, self included, as the lists count it); test_rate_parity_fp64
-    checks their FP64 rates element by element, and here the mixed-precision
-    rates of both kinds stay within 1e-6 of the oracle (measured 1e-8 to 4e-8)."""
+    """In 3+1D the pair passes after a step's first density pass walk that
+    pass's skin list (every candidate within 2h plus twice a step's
+    displacement bound), up to 4096 entries per target, and a target with
+    more walks its candidates instead.  In the dense case both kinds occur
+    (told apart here by the oracle's neighbour counts, self included, which
+    the skin lists exceed by a few per cent); test_rate_parity_fp64 checks
+    their FP64 rates element by element, and here the mixed-precision rates
+    of both kinds stay within 1e-6 of the oracle (measured 1e-8 to 4e-8)."""
     prm, oe, cfg, ge, y, t0 = prepared(B, O, "dense3d_list_overflow")
     f_o, aux_o, bad = O.rhs(prm, oe, t0, y)
     assert bad == 0
